@@ -1,0 +1,482 @@
+"""Pins of the CPU oracle against facts fixed outside the oracle itself.
+
+Each test checks one step of the oracle against something it does not share
+code with: a library implementation of the same published generator, float64
+evaluation, closed-form integrals, geometric invariants, brute force.
+"""
+import numpy as np
+import pytest
+
+from paper_2310_07182_amd import scenes
+
+
+# ---------------------------------------------------------------- RNG
+@pytest.mark.parametrize("ctr,key", [
+    ((0, 0, 0, 0), (0, 0)),
+    ((5, 1, 2, 0), (123456789, 0)),
+    ((2 ** 64 - 2, 3, 7, 1), (2310071820, 0)),
+    ((12345, 0, 4, 1), (2 ** 63 + 11, 0)),
+])
+def test_philox_matches_numpy(orc, ctr, key):
+    # numpy's Philox returns the block of counter+1 (256-bit little-endian increment)
+    c = np.array(ctr, dtype=np.uint64)
+    prev = c.copy()
+    if prev[0] == 0:
+        pytest.skip("no predecessor needed for this pin")
+    prev[0] -= np.uint64(1)
+    g = np.random.Philox(counter=prev, key=np.array(key, dtype=np.uint64))
+    ref = g.random_raw(4)
+    got = orc.philox(ctr, key)
+    assert np.array_equal(ref, got)
+
+
+def test_philox_zero_counter(orc):
+    # counter 0 = successor of all-ones (carry propagates through all 4 words)
+    ones = np.array([2 ** 64 - 1] * 4, dtype=np.uint64)
+    g = np.random.Philox(counter=ones, key=np.array([0, 0], dtype=np.uint64))
+    assert np.array_equal(g.random_raw(4), orc.philox((0, 0, 0, 0), (0, 0)))
+
+
+# ---------------------------------------------------------------- sincos2pi
+def test_sincos2pi_exhaustive(orc):
+    u = (np.arange(1 << 24, dtype=np.float64) * 2.0 ** -24).astype(np.float32)
+    s, c = orc.sincos2pi(u)
+    ang = 2.0 * np.pi * u.astype(np.float64)
+    es = np.abs(s.astype(np.float64) - np.sin(ang))
+    ec = np.abs(c.astype(np.float64) - np.cos(ang))
+    assert es.max() <= 2.0 ** -23 and ec.max() <= 2.0 ** -23
+    # relative error where the value is not tiny: a few ulp
+    big = np.abs(np.sin(ang)) > 1e-3
+    assert (es[big] / np.abs(np.sin(ang[big]))).max() < 4e-7
+    # exact values at the octant points
+    for uu, ss, cc in [(0.0, 0.0, 1.0), (0.25, 1.0, 0.0), (0.5, 0.0, -1.0), (0.75, -1.0, 0.0)]:
+        a, b = orc.sincos2pi(np.array([uu], np.float32))
+        assert a[0] == ss and b[0] == cc
+
+
+# ---------------------------------------------------------------- camera
+def test_camera_center_and_symmetry(orc):
+    cam = dict(pos=(1.0, 2.0, 3.0), look_at=(1.0, 2.0, -7.0), up=(0.0, 1.0, 0.0), vfov=60.0)
+    w, h = 65, 33
+    o, d = orc.camera_ray(cam, w, h, 32, 16, 0.5, 0.5)
+    assert np.allclose(o, cam["pos"])
+    assert np.allclose(d, [0.0, 0.0, -1.0], atol=1e-6)
+    # corner ray: tan(vfov/2) vertically, aspect-scaled horizontally
+    o, d = orc.camera_ray(cam, w, h, 0, 0, 0.0, 0.0)
+    th = np.tan(np.deg2rad(30.0))
+    ref = np.array([-th * w / h, th, -1.0])
+    ref /= np.linalg.norm(ref)
+    assert np.allclose(d, ref, atol=1e-6)
+    assert abs(np.linalg.norm(d.astype(np.float64)) - 1.0) < 1e-6
+
+
+# ---------------------------------------------------------------- frame
+@pytest.mark.parametrize("n", [(0, 0, 1), (0, 0, -1), (1, 0, 0), (0, 1, 0), (0.3, -0.5, 0.81),
+                               (0.0, 1e-4, -1.0), (-0.6, 0.0, -0.8)])
+def test_onb_orthonormal(orc, n):
+    n = np.asarray(n, np.float64)
+    n = (n / np.linalg.norm(n)).astype(np.float32)
+    t, b = orc.onb(n)
+    M = np.stack([t, b, n]).astype(np.float64)
+    assert np.allclose(M @ M.T, np.eye(3), atol=2e-6)
+    assert np.allclose(np.cross(t.astype(np.float64), b.astype(np.float64)), n, atol=2e-6)  # right-handed
+
+
+def test_onb_random(orc):
+    rng = np.random.default_rng(5)
+    for _ in range(2000):
+        n = rng.normal(size=3)
+        n = (n / np.linalg.norm(n)).astype(np.float32)
+        t, b = orc.onb(n)
+        M = np.stack([t, b, n]).astype(np.float64)
+        assert np.allclose(M @ M.T, np.eye(3), atol=4e-6)
+
+
+def test_offset_origin_side(orc):
+    rng = np.random.default_rng(9)
+    for scale in (1e-3, 1.0, 50.0, 4000.0):
+        for _ in range(300):
+            p = (rng.normal(size=3) * scale).astype(np.float32)
+            n = rng.normal(size=3)
+            n = (n / np.linalg.norm(n)).astype(np.float32)
+            q = orc.offset_origin(p, n)
+            dp = q.astype(np.float64) - p.astype(np.float64)
+            assert np.dot(dp, n.astype(np.float64)) > 0.0
+            assert np.linalg.norm(dp) <= 1e-3 * max(scale, 1.0)
+
+
+# ---------------------------------------------------------------- watertight test
+def _scene_from_tris(tris):
+    tris = np.asarray(tris, np.float32).reshape(-1, 3, 3)
+    mats = np.array([(0, (0.5, 0.5, 0.5), 0.0, (0, 0, 0))], dtype=scenes.MATERIAL_DTYPE)
+    return dict(tris=tris, tri_mat=np.zeros(len(tris), np.uint32), mats=mats,
+                env=np.zeros(3, np.float32), camera=dict(pos=(0, 0, 5), look_at=(0, 0, 0), up=(0, 1, 0), vfov=60.0))
+
+
+def test_interior_rays_never_miss(orc):
+    v, f = scenes.icosphere(3)
+    tris = (v * 1.7 + np.array([0.3, -0.2, 0.1]))[f]
+    sc = orc.OracleScene(_scene_from_tris(tris))
+    rng = np.random.default_rng(1)
+    n = 20000
+    o = (rng.uniform(-0.5, 0.5, (n, 3)) + np.array([0.3, -0.2, 0.1])).astype(np.float32)
+    d = rng.normal(size=(n, 3))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    # directions aimed exactly at mesh vertices and edge midpoints
+    tgt = np.concatenate([tris[:, 0], 0.5 * (tris[:, 0] + tris[:, 1])])[: n // 2]
+    d[: len(tgt)] = (tgt - o[: len(tgt)]).astype(np.float32)
+    prim, t, _ = sc.trace(orc.pack_rays(o, d))
+    assert (prim >= 0).all()
+
+
+def test_axis_aligned_quad_exact_t(orc):
+    q = scenes.quad((-2, -2, 5), (2, -2, 5), (2, 2, 5), (-2, 2, 5))
+    sc = orc.OracleScene(_scene_from_tris(q))
+    o = np.array([[0.3, 0.2, 0.0], [0.0, 0.0, 0.0], [-1.0, 1.5, 1.0]], np.float32)
+    d = np.array([[0, 0, 1], [0, 0, 1], [0, 0, 1]], np.float32)
+    prim, t, _ = sc.trace(orc.pack_rays(o, d))
+    assert (prim >= 0).all()
+    assert t[0] == 5.0 and t[1] == 5.0 and t[2] == 4.0
+    # the diagonal (shared edge) ray hits with the smaller prim id on a tie
+    assert prim[1] == 0
+
+
+def test_shared_edge_and_vertex_hit_once(orc):
+    # a fan of triangles around a shared vertex; rays through the vertex and edges
+    c = np.array([0.0, 0.0, 0.0])
+    ring = [np.array([np.cos(a), np.sin(a), 0.0]) for a in np.linspace(0, 2 * np.pi, 9)[:-1]]
+    tris = [(c, ring[i], ring[(i + 1) % 8]) for i in range(8)]
+    sc = orc.OracleScene(_scene_from_tris(tris))
+    o = np.array([[0.0, 0.0, -3.0]] + [[0.5 * r[0], 0.5 * r[1], -2.0] for r in ring], np.float32)
+    d = np.tile(np.array([[0.0, 0.0, 1.0]], np.float32), (len(o), 1))
+    prim, t, _ = sc.trace(orc.pack_rays(o, d))
+    assert (prim >= 0).all()
+    assert t[0] == 3.0
+
+
+# ---------------------------------------------------------------- closest hit
+def _random_rays(sc_dict, n, rng):
+    tris = sc_dict["tris"].astype(np.float64)
+    lo, hi = tris.reshape(-1, 3).min(0), tris.reshape(-1, 3).max(0)
+    o = rng.uniform(lo + 0.1, hi - 0.1, (n, 3)).astype(np.float32)
+    d = rng.normal(size=(n, 3))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    return o, d
+
+
+def test_bvh_equals_brute_force_tiny(orc):
+    s = scenes.tiny()
+    sc = orc.OracleScene(s)
+    rng = np.random.default_rng(3)
+    o, d = _random_rays(s, 6000, rng)
+    cam_o, cam_d = [], []
+    for i in range(2000):
+        x, y = rng.integers(0, 64, 2)
+        oo, dd = orc.camera_ray(s["camera"], 64, 64, int(x), int(y), rng.uniform(), rng.uniform())
+        cam_o.append(oo)
+        cam_d.append(dd)
+    o = np.concatenate([o, np.array(cam_o)])
+    d = np.concatenate([d, np.array(cam_d)])
+    rays = orc.pack_rays(o, d)
+    p1, t1, _ = sc.trace(rays)
+    p2, t2 = sc.trace_brute(rays)
+    assert np.array_equal(p1, p2)
+    assert np.array_equal(t1.view(np.uint32), t2.view(np.uint32))
+
+
+def test_closest_hit_vs_float64(orc):
+    from oracle import brute
+    s = scenes.tiny()
+    sc = orc.OracleScene(s)
+    rng = np.random.default_rng(4)
+    o, d = _random_rays(s, 3000, rng)
+    rays = orc.pack_rays(o, d)
+    p32, t32, _ = sc.trace(rays)
+    p64, t64, t64b = brute.closest_hits(s["tris"], rays)
+    near_tie = (t64b - t64) <= 1e-5 * t64
+    ok = (p32 == p64) | near_tie
+    assert ok.mean() >= 0.999, ok.mean()
+    hit = (p32 >= 0) & (p32 == p64)
+    assert np.all(np.abs(t32[hit] - t64[hit]) <= 1e-5 * t64[hit])
+
+
+def test_bvh_equals_brute_force_indoor_sample(orc):
+    s = scenes.mixed_small()
+    sc = orc.OracleScene(s)
+    rng = np.random.default_rng(8)
+    o, d = _random_rays(s, 1500, rng)
+    rays = orc.pack_rays(o, d)
+    p1, t1, _ = sc.trace(rays)
+    p2, t2 = sc.trace_brute(rays)
+    assert np.array_equal(p1, p2)
+    assert np.array_equal(t1.view(np.uint32), t2.view(np.uint32))
+
+
+# ---------------------------------------------------------------- sampling
+def _grid(n):
+    g = ((np.arange(n) + 0.5) / n).astype(np.float32)
+    return np.meshgrid(g, g, indexing="ij")
+
+
+def test_lambert_moments(orc):
+    U2, U3 = _grid(256)
+    q = np.array([orc.sample_lambert(a, b) for a, b in zip(U2.ravel()[::7], U3.ravel()[::7])])
+    z = q[:, 2].astype(np.float64)
+    assert abs(z.mean() - 2.0 / 3.0) < 2e-3
+    assert abs((z * z).mean() - 0.5) < 2e-3
+    assert np.allclose(np.linalg.norm(q.astype(np.float64), axis=1), 1.0, atol=1e-6)
+    # azimuth is uniform
+    phi = np.arctan2(q[:, 1], q[:, 0])
+    hist, _ = np.histogram(phi, bins=16, range=(-np.pi, np.pi))
+    assert hist.min() > 0.9 * hist.mean()
+
+
+def _ggx_albedo_quadrature(wi, alpha, f0, n=800):
+    """Directional albedo of GGX with separable Smith G and Schlick F, float64 quadrature."""
+    th = (np.arange(n) + 0.5) / n * (np.pi / 2)
+    ph = (np.arange(2 * n) + 0.5) / (2 * n) * (2 * np.pi)
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    wo = np.stack([np.sin(T) * np.cos(P), np.sin(T) * np.sin(P), np.cos(T)], -1)
+    hv = wo + wi
+    hv /= np.linalg.norm(hv, axis=-1, keepdims=True)
+    a2 = alpha * alpha
+    cm = hv[..., 2]
+    D = a2 / (np.pi * (cm * cm * (a2 - 1) + 1) ** 2)
+
+    def g1(z):
+        t2 = (1 - z * z) / (z * z)
+        return 2 / (1 + np.sqrt(1 + a2 * t2))
+
+    G = g1(wi[2]) * g1(wo[..., 2])
+    c = 1 - np.sum(wi * hv, -1)
+    F = f0 + (1 - f0) * c ** 5
+    f = D * F * G / (4 * wi[2] * wo[..., 2])
+    dw = (np.pi / 2 / n) * (2 * np.pi / (2 * n)) * np.sin(T)
+    return np.sum(f * wo[..., 2] * dw)
+
+
+@pytest.mark.parametrize("alpha,theta_i,f0", [(0.3, 0.4, 0.9), (0.5, 1.0, 0.6), (0.1, 0.2, 0.95)])
+def test_ggx_weight_mean_equals_albedo(orc, alpha, theta_i, f0):
+    wi = np.array([np.sin(theta_i), 0.0, np.cos(theta_i)])
+    ref = _ggx_albedo_quadrature(wi, alpha, f0)
+    U2, U3 = _grid(300)
+    ws = []
+    for a, b in zip(U2.ravel(), U3.ravel()):
+        ok, wo, w = orc.sample_ggx(wi.astype(np.float32), alpha, np.full(3, f0, np.float32), a, b)
+        ws.append(w[0] if ok else 0.0)
+    est = float(np.mean(ws))
+    assert abs(est - ref) < 0.01 * ref + 2e-3, (est, ref)
+
+
+# ---------------------------------------------------------------- grouping
+@pytest.mark.parametrize("wh,k", [(1, 1), (2, 1), (16, 2), (16, 16), (64, 8), (256, 32), (1024, 8)])
+def test_shuffle_bijection_and_group_sizes(orc, wh, k):
+    rng = np.random.default_rng(wh)
+    for _ in range(20):
+        x0, x1 = int(rng.integers(0, 2 ** 63)), int(rng.integers(0, 2 ** 63))
+        s = orc.shuffle(wh, x0, x1)
+        assert np.array_equal(np.sort(s), np.arange(wh))
+        counts = np.bincount(s // k, minlength=wh // k)
+        assert (counts == k).all()
+
+
+# ---------------------------------------------------------------- key
+def test_ray_key_matches_bitwise_rebuild(orc):
+    lo = np.array([0.0, -1.0, 0.0], np.float32)
+    hi = np.array([20.0, 8.0, 20.0], np.float32)
+    rng = np.random.default_rng(2)
+    for _ in range(300):
+        o = rng.uniform(lo, hi).astype(np.float32)
+        d = rng.normal(size=3)
+        d = (d / np.linalg.norm(d)).astype(np.float32)
+        key = orc.ray_key(lo, hi, o, d)
+        ext = hi - lo
+        L = np.float32(0.25) * ext.max()
+        e = (o + L * d).astype(np.float32)
+        q = []
+        for x in list(o) + list(e):
+            pass
+        coords = [o[0], o[1], o[2], e[0], e[1], e[2]]
+        axes = [0, 1, 2, 0, 1, 2]
+        bits = ""
+        qs = []
+        for x, a in zip(coords, axes):
+            f = (np.float32(x) - lo[a]) / ext[a] * np.float32(32.0)
+            qs.append(int(min(31, max(0, np.floor(f)))))
+        for b in range(4, -1, -1):
+            for qq in qs:
+                bits += str((qq >> b) & 1)
+        assert key == int(bits, 2)
+        assert key < 2 ** 30
+
+
+# ---------------------------------------------------------------- whole-path properties
+@pytest.mark.parametrize("mode,k", [("incoherent", 1), ("sorted", 1), ("reuse", 1), ("reuse", 4), ("reuse", 16)])
+def test_furnace_closed_form(orc, mode, k):
+    rho, E, B = 0.5, 1.0, 3
+    s = scenes.furnace(rho, E)
+    sc = orc.OracleScene(s)
+    r = sc.render(16, 16, 2, B, mode=mode, tile=(4, 4), k=k, seed=11)
+    expect = E * sum(rho ** i for i in range(B + 1))
+    assert np.allclose(r["radiance"], expect, rtol=1e-5)
+    assert (r["hit_prim"] >= 0).all()   # closed box: nothing escapes
+
+
+def _bits(a):
+    return a.view(np.uint32) if a.dtype == np.float32 else a
+
+
+@pytest.mark.parametrize("scene_fn", [scenes.tiny, scenes.mixed_small])
+def test_reuse_k1_equals_incoherent(orc, scene_fn):
+    s = scene_fn()
+    sc = orc.OracleScene(s)
+    a = sc.render(48, 40, 2, 3, mode="incoherent", tile=(4, 4), k=1, seed=21)
+    b = sc.render(48, 40, 2, 3, mode="reuse", tile=(4, 4), k=1, seed=21)
+    for key in ("radiance", "hit_prim", "hit_t", "rays_per_bounce"):
+        assert np.array_equal(_bits(a[key]), _bits(b[key])), key
+
+
+def test_sorted_equals_incoherent(orc):
+    s = scenes.mixed_small()
+    sc = orc.OracleScene(s)
+    a = sc.render(40, 32, 1, 3, mode="incoherent", seed=5)
+    b = sc.render(40, 32, 1, 3, mode="sorted", seed=5)
+    for key in ("radiance", "hit_prim", "hit_t"):
+        assert np.array_equal(_bits(a[key]), _bits(b[key])), key
+
+
+def test_glossy_only_reuse_equals_incoherent(orc):
+    s = scenes.glossy_only()
+    kinds = s["mats"]["kind"][np.unique(s["tri_mat"])]
+    assert (kinds != 0).all()
+    sc = orc.OracleScene(s)
+    a = sc.render(48, 48, 1, 3, mode="incoherent", seed=8)
+    for tile, k in [((4, 4), 4), ((8, 8), 8), ((8, 8), 64)]:
+        b = sc.render(48, 48, 1, 3, mode="reuse", tile=tile, k=k, seed=8)
+        for key in ("radiance", "hit_prim", "hit_t"):
+            assert np.array_equal(_bits(a[key]), _bits(b[key])), (key, tile, k)
+
+
+def _pairwise_sum(vecs):
+    v = [np.asarray(x, np.float32) for x in vecs]
+    while len(v) > 1:
+        v = [v[2 * j] + v[2 * j + 1] for j in range(len(v) // 2)]
+    return v[0]
+
+
+@pytest.mark.parametrize("tile,k", [((4, 4), 4), ((8, 8), 8)])
+def test_reuse_rules_per_category(orc, tile, k):
+    """Sections 3.2/3.3: diffuse groups share the representative's tangent
+    direction, glossy members keep their own, hybrid diffuse members take the
+    normalized sum of the glossy members' exits."""
+    s = scenes.mixed_small()
+    sc = orc.OracleScene(s)
+    W, H = tile
+    w, h = 64, 48
+    inc = sc.render(w, h, 1, 2, mode="incoherent", tile=tile, k=k, seed=31, debug=True)
+    reu = sc.render(w, h, 1, 2, mode="reuse", tile=tile, k=k, seed=31, debug=True)
+    # only the first generated ray (bounce 0 -> 1) has identical shading points in both runs
+    fi, qi = inc["dbg_flags"][0, 0], inc["dbg_q"][0, 0]
+    fr, qr = reu["dbg_flags"][0, 0], reu["dbg_q"][0, 0]
+    assert np.array_equal(fi & orc.F_ACTIVE, fr & orc.F_ACTIVE)
+    seen = {1: 0, 2: 0, 3: 0}
+    for ty in range(h // H):
+        for tx in range(w // W):
+            fl = fr[ty * H:(ty + 1) * H, tx * W:(tx + 1) * W].ravel()
+            qo = qi[ty * H:(ty + 1) * H, tx * W:(tx + 1) * W].reshape(-1, 3)
+            qu = qr[ty * H:(ty + 1) * H, tx * W:(tx + 1) * W].reshape(-1, 3)
+            own_ok = (fi[ty * H:(ty + 1) * H, tx * W:(tx + 1) * W].ravel() & orc.F_VALID) != 0
+            slot = (fl >> orc.F_SLOT_SH) & 0xFFFF
+            assert np.array_equal(np.sort(slot), np.arange(W * H))
+            # screen-order numbering i = row*W + col, shuffled by the tile draw
+            # of counter (tile id, sample, bounce, stream 1) (Section 3.3)
+            x = orc.philox((ty * (w // W) + tx, 0, 0, 1), (31, 0))
+            assert np.array_equal(slot, orc.shuffle(W * H, int(x[0]), int(x[1])))
+            for g in range(W * H // k):
+                mem = np.where((slot // k) == g)[0]
+                mem = mem[np.argsort(slot[mem])]
+                act = mem[(fl[mem] & orc.F_ACTIVE) != 0]
+                if len(act) == 0:
+                    continue
+                cls = (fl[act] >> orc.F_CLASS_SH) & 3
+                cat = (fl[act] >> orc.F_CAT_SH) & 3
+                assert (cat == cat[0]).all()
+                expect = 1 if (cls == 0).all() else (2 if (cls != 0).all() else 3)
+                assert cat[0] == expect
+                seen[expect] += 1
+                glossy = act[cls != 0]
+                assert np.array_equal(qu[glossy].view(np.uint32), qo[glossy].view(np.uint32))
+                diff = act[cls == 0]
+                if expect == 1:
+                    rep = act[0]                      # smallest shuffled slot
+                    assert fl[rep] & orc.F_REP
+                    for m in diff:
+                        assert np.array_equal(qu[m].view(np.uint32), qo[rep].view(np.uint32))
+                elif expect == 3:
+                    vec = []
+                    for m in mem:
+                        f_m = fl[m]
+                        use = (f_m & orc.F_ACTIVE) and ((f_m >> orc.F_CLASS_SH) & 3) != 0 and own_ok[m]
+                        vec.append(qo[m] if use else np.zeros(3, np.float32))
+                    if any(((fl[m] & orc.F_ACTIVE) and ((fl[m] >> orc.F_CLASS_SH) & 3) != 0 and own_ok[m]) for m in mem):
+                        S = _pairwise_sum(vec)
+                        ln = np.float32(1.0) / np.sqrt(np.float32((S[0] * S[0] + S[1] * S[1]) + S[2] * S[2]))
+                        ref = (S * ln).astype(np.float32)
+                        for m in diff:
+                            assert np.array_equal(qu[m].view(np.uint32), ref.view(np.uint32))
+                    else:
+                        for m in diff:
+                            assert np.array_equal(qu[m].view(np.uint32), qo[m].view(np.uint32))
+    assert seen[1] > 0 and seen[3] > 0
+
+
+def test_group_composition_changes_across_samples(orc):
+    wh, k = 64, 8
+    comps = []
+    for smp in range(6):
+        x = orc.philox((7, smp, 1, 1), (2310071820, 0))
+        s = orc.shuffle(wh, int(x[0]), int(x[1]))
+        comps.append(tuple(s // k))
+    assert len(set(comps)) == len(comps)
+
+
+def test_unbiased_diffuse_groups(orc):
+    """All-Lambert tiny room: diffuse groups reuse a cosine-distributed
+    direction with the receiving point's own pdf, so the expected image equals
+    plain path tracing (Section 3.2).  Tile-level z test over independent seeds."""
+    s = scenes.tiny()
+    sc = orc.OracleScene(s)
+    w = h = 32
+    spp = 192
+    a = sc.render(w, h, spp, 2, mode="incoherent", tile=(4, 4), k=2, seed=101)["radiance"].astype(np.float64)
+    b = sc.render(w, h, spp, 2, mode="reuse", tile=(4, 4), k=8, seed=202)["radiance"].astype(np.float64)
+    D = (b - a).reshape(h // 4, 4, w // 4, 4, 3).mean(axis=(1, 3)).reshape(-1)
+    z = abs(D.mean()) / (D.std(ddof=1) / np.sqrt(D.size))
+    assert z < 4.0, z
+
+
+def test_rays_per_bounce_counts(orc):
+    s = scenes.tiny()
+    sc = orc.OracleScene(s)
+    r = sc.render(64, 64, 1, 2, mode="reuse", tile=(4, 4), k=2, seed=3)
+    hp = r["hit_prim"]
+    for b in range(3):
+        assert r["rays_per_bounce"][b] == np.count_nonzero(hp[b] != -2)
+    assert r["rays_per_bounce"][0] == 64 * 64
+
+
+def test_tile_mask_matches_full_render(orc):
+    s = scenes.mixed_small()
+    sc = orc.OracleScene(s)
+    w, h, W, H = 40, 24, 8, 8
+    full = sc.render(w, h, 1, 3, mode="reuse", tile=(W, H), k=8, seed=13)
+    ntx, nty = (w + W - 1) // W, (h + H - 1) // H
+    mask = np.zeros(ntx * nty, np.uint8)
+    mask[[0, 3, 7, ntx * nty - 1]] = 1
+    part = sc.render(w, h, 1, 3, mode="reuse", tile=(W, H), k=8, seed=13, tile_mask=mask)
+    pix = np.zeros((h, w), bool)
+    for t in np.where(mask)[0]:
+        ty, tx = divmod(int(t), ntx)
+        pix[ty * H:(ty + 1) * H, tx * W:(tx + 1) * W] = True
+    assert np.array_equal(full["hit_prim"][:, :, pix], part["hit_prim"][:, :, pix])
+    assert np.array_equal(full["radiance"][pix].view(np.uint32), part["radiance"][pix].view(np.uint32))
