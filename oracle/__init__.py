@@ -36,7 +36,7 @@ class _Camera(C.Structure):
 class _Outputs(C.Structure):
     _fields_ = [("radiance", C.c_void_p), ("hit_prim", C.c_void_p), ("hit_t", C.c_void_p),
                 ("hit_t2", C.c_void_p), ("dbg_q", C.c_void_p), ("dbg_flags", C.c_void_p),
-                ("dbg_keys", C.c_void_p), ("rays_per_bounce", C.c_void_p)]
+                ("dbg_keys", C.c_void_p), ("rays", C.c_void_p), ("rays_per_bounce", C.c_void_p)]
 
 
 _lib = None
@@ -150,8 +150,9 @@ class OracleScene:
             q = np.zeros((max(B, 1), spp, h, w, 3), np.float32)
             fl = np.zeros((max(B, 1), spp, h, w), np.int32)
             keys = np.full((max(B, 1), spp, h, w), 0xFFFFFFFF, np.uint32)
-            out.dbg_q, out.dbg_flags, out.dbg_keys = _p(q), _p(fl), _p(keys)
-            res.update(dbg_q=q[:B], dbg_flags=fl[:B], dbg_keys=keys[:B])
+            rays = np.zeros((B + 1, spp, h, w, 8), np.float32)
+            out.dbg_q, out.dbg_flags, out.dbg_keys, out.rays = _p(q), _p(fl), _p(keys), _p(rays)
+            res.update(dbg_q=q[:B], dbg_flags=fl[:B], dbg_keys=keys[:B], rays=rays)
         mask = None
         if tile_mask is not None:
             mask = np.ascontiguousarray(tile_mask, dtype=np.uint8)

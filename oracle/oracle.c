@@ -793,6 +793,7 @@ int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp,
                 if (out->hit_prim) out->hit_prim[at] = -2;
                 if (out->hit_t) out->hit_t[at] = INFINITY;
                 if (out->hit_t2) out->hit_t2[at] = INFINITY;
+                if (out->rays) memset(out->rays + at * 8, 0, 8 * sizeof(float));
                 if (b < B) {
                     if (out->dbg_flags) out->dbg_flags[at] = 0;
                     if (out->dbg_keys) out->dbg_keys[at] = 0xFFFFFFFFu;
@@ -840,6 +841,12 @@ int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp,
             }
             for (size_t j = 0; j < nl; ++j) {
                 opath* p = &P[list[j]];
+                if (out->rays) {
+                    float* rr = out->rays + (((size_t)b * spp + smp) * plane + list[j]) * 8;
+                    uint32_t pxi = list[j];
+                    rr[0] = p->o.x; rr[1] = p->o.y; rr[2] = p->o.z; memcpy(&rr[3], &p->excl, 4);
+                    rr[4] = p->d.x; rr[5] = p->d.y; rr[6] = p->d.z; memcpy(&rr[7], &pxi, 4);
+                }
                 hit2 hh = trace_one(s, p->o, p->d, p->excl, NULL, NULL);
                 p->prim = hh.p1 == INT32_MAX ? -1 : hh.p1;
                 p->t = hh.p1 == INT32_MAX ? INFINITY : hh.t1;

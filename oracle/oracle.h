@@ -47,6 +47,7 @@ typedef struct {
     float* dbg_q;             /* [B][spp][h][w][3] tangent-space direction used for ray b+1 */
     int32_t* dbg_flags;       /* [B][spp][h][w] see ORC_F_* */
     uint32_t* dbg_keys;       /* [B][spp][h][w] two-point key of ray b+1 (sorted mode) */
+    float* rays;              /* [B+1][spp][h][w][8] ray traced at bounce b {o, excluded, d, pixel} */
     uint64_t* rays_per_bounce;/* [B+1] */
 } orc_outputs;
 

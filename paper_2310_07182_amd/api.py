@@ -1,0 +1,242 @@
+"""Python API over libpt: torch tensors hold device memory, the torch current
+stream is the HIP stream.  Every computation runs in libpt's HIP kernels."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import capi
+from .capi import check, lib
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _require_cuda(device):
+    if not torch.cuda.is_available():
+        raise RuntimeError("a ROCm GPU is required (libpt has no CPU path)")
+    return torch.device(device)
+
+
+def camera_struct(cam: dict) -> capi.Camera:
+    c = capi.Camera()
+    c.pos[:] = [float(v) for v in cam["pos"]]
+    c.look_at[:] = [float(v) for v in cam["look_at"]]
+    c.up[:] = [float(v) for v in cam["up"]]
+    c.vfov_deg = float(cam["vfov"])
+    return c
+
+
+def group_struct(tile=(8, 8), k=8, reuse_max_bounce=0xFFFF) -> capi.Group:
+    g = capi.Group()
+    g.tile_w, g.tile_h = int(tile[0]), int(tile[1])
+    g.k = int(k)
+    g.reuse_max_bounce = int(min(reuse_max_bounce, 0xFFFF))
+    return g
+
+
+class Scene:
+    """A scene built (BVH on the host) and uploaded into a torch-owned device arena."""
+
+    def __init__(self, scene: dict, device="cuda:0", upload: bool = True):
+        self.desc_src = scene
+        self._tris = np.ascontiguousarray(scene["tris"], dtype=np.float32)
+        self._mat = np.ascontiguousarray(scene["tri_mat"], dtype=np.uint32)
+        self._mats = np.ascontiguousarray(scene["mats"])
+        assert self._mats.dtype.itemsize == C.sizeof(capi.Material)
+        d = capi.SceneDesc()
+        d.tris = self._tris.ctypes.data
+        d.ntri = int(self._tris.shape[0])
+        d.tri_mat = self._mat.ctypes.data
+        d.mats = self._mats.ctypes.data
+        d.nmat = len(self._mats)
+        d.env_radiance[:] = [float(v) for v in scene["env"]]
+        h = C.c_void_p()
+        check(lib().pt_scene_create(C.byref(d), C.byref(h)))
+        self.handle = h
+        self.camera = scene.get("camera")
+        self.arena = None
+        self.device = None
+        if upload:
+            self.upload(device)
+
+    def upload(self, device="cuda:0"):
+        dev = _require_cuda(device)
+        nbytes = lib().pt_scene_device_bytes(self.handle)
+        with torch.cuda.device(dev):
+            self.arena = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+            assert self.arena.data_ptr() % 256 == 0
+            check(lib().pt_scene_upload(self.handle, self.arena.data_ptr(), self.arena.numel(),
+                                        _stream_handle(dev)))
+        self.device = dev
+        return self
+
+    def info(self) -> dict:
+        i = capi.SceneInfo()
+        check(lib().pt_scene_get_info(self.handle, C.byref(i)))
+        return dict(ntri=i.ntri, nnodes=i.nnodes, max_depth=i.max_depth, max_leaf=i.max_leaf,
+                    lo=list(i.lo), hi=list(i.hi), sah_cost=i.sah_cost, device_bytes=i.device_bytes)
+
+    def export_bvh(self):
+        inf = self.info()
+        nodes = np.zeros((inf["nnodes"], 16), dtype=np.float32)
+        order = np.zeros(inf["ntri"], dtype=np.uint32)
+        check(lib().pt_scene_export_bvh(self.handle, nodes.ctypes.data, order.ctypes.data))
+        return nodes, order
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                lib().pt_scene_free(h)
+            except Exception:
+                pass
+            self.handle = None
+
+
+class Timer:
+    def __init__(self, capacity: int = 4096):
+        h = C.c_void_p()
+        check(lib().pt_timer_create(int(capacity), C.byref(h)))
+        self.handle = h
+        self.capacity = capacity
+
+    def reset(self):
+        check(lib().pt_timer_reset(self.handle))
+
+    def read(self):
+        n = C.c_int32()
+        ms = np.zeros(self.capacity, np.float32)
+        kind = np.zeros(self.capacity, np.int32)
+        bounce = np.zeros(self.capacity, np.int32)
+        check(lib().pt_timer_read(self.handle, ms.ctypes.data, kind.ctypes.data, bounce.ctypes.data,
+                                  self.capacity, C.byref(n)))
+        m = n.value
+        return ms[:m], kind[:m], bounce[:m]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                lib().pt_timer_free(h)
+            except Exception:
+                pass
+            self.handle = None
+
+
+@dataclass
+class RenderConfig:
+    w: int
+    h: int
+    spp: int = 1
+    bounces: int = 2
+    mode: str = "incoherent"
+    tile: tuple = (8, 8)
+    k: int = 8
+    reuse_max_bounce: int | None = None
+
+
+class Renderer:
+    """Holds the workspace and output tensors for repeated frames of one configuration."""
+
+    def __init__(self, scene: Scene, cfg: RenderConfig, stats: bool = False, timer: Timer | None = None,
+                 rays: bool = False):
+        self.scene = scene
+        self.cfg = cfg
+        dev = scene.device
+        B = cfg.bounces
+        rmax = B if cfg.reuse_max_bounce is None else cfg.reuse_max_bounce
+        self.group = group_struct(cfg.tile, cfg.k, rmax)
+        self.mode = capi.MODES[cfg.mode]
+        ws = lib().pt_render_workspace_bytes(cfg.w, cfg.h, cfg.spp, B, self.mode, self.group)
+        if ws == 0:
+            raise capi.PtError(capi.PT_EINVAL, "invalid render configuration")
+        with torch.cuda.device(dev):
+            self.workspace = torch.empty(ws, dtype=torch.uint8, device=dev)
+            self.radiance = torch.empty((cfg.h, cfg.w, 3), dtype=torch.float32, device=dev)
+            self.hit_prim = torch.empty((B + 1, cfg.spp, cfg.h, cfg.w), dtype=torch.int32, device=dev)
+            self.hit_t = torch.empty((B + 1, cfg.spp, cfg.h, cfg.w), dtype=torch.float32, device=dev)
+            self.ray_count = torch.empty((B + 1, cfg.spp), dtype=torch.int32, device=dev)
+            self.stats = torch.empty((B + 1, 2), dtype=torch.int64, device=dev) if stats else None
+            self.rays = torch.zeros((B + 1, cfg.spp, cfg.h, cfg.w, 8), dtype=torch.float32, device=dev) if rays else None
+        self.timer = timer
+        self.out = capi.Outputs()
+        self.out.radiance = self.radiance.data_ptr()
+        self.out.hit_prim = self.hit_prim.data_ptr()
+        self.out.hit_t = self.hit_t.data_ptr()
+        self.out.ray_count = self.ray_count.data_ptr()
+        self.out.stats = self.stats.data_ptr() if stats else None
+        self.out.rays = self.rays.data_ptr() if rays else None
+        self.out.timer = timer.handle if timer is not None else None
+
+    def render(self, seed: int = 1, camera: dict | None = None):
+        cfg = self.cfg
+        cam = camera_struct(camera or self.scene.camera)
+        dev = self.scene.device
+        with torch.cuda.device(dev):
+            check(lib().pt_render(self.scene.handle, C.byref(cam), cfg.w, cfg.h, cfg.spp, cfg.bounces,
+                                  self.mode, self.group, C.c_uint64(int(seed)), self.workspace.data_ptr(),
+                                  self.workspace.numel(), C.byref(self.out), _stream_handle(dev)))
+        return self
+
+    def results(self) -> dict:
+        r = dict(radiance=self.radiance, hit_prim=self.hit_prim, hit_t=self.hit_t,
+                 rays_per_bounce=self.ray_count.sum(dim=1))
+        if self.stats is not None:
+            r["stats"] = self.stats
+        if self.rays is not None:
+            r["rays"] = self.rays
+        return r
+
+
+def render(scene: Scene, w, h, spp=1, bounces=2, mode="incoherent", tile=(8, 8), k=8,
+           reuse_max_bounce=None, seed=1, camera=None, stats=False, rays=False) -> dict:
+    r = Renderer(scene, RenderConfig(w, h, spp, bounces, mode, tuple(tile), k, reuse_max_bounce), stats=stats,
+                 rays=rays)
+    r.render(seed, camera)
+    return r.results()
+
+
+def trace(scene: Scene, rays: torch.Tensor):
+    """rays: device float32 [n, 8]; returns (prim int32 [n], t float32 [n])."""
+    assert rays.dtype == torch.float32 and rays.is_contiguous() and rays.shape[-1] == 8
+    dev = scene.device
+    n = rays.shape[0]
+    prim = torch.empty(n, dtype=torch.int32, device=dev)
+    t = torch.empty(n, dtype=torch.float32, device=dev)
+    ws = torch.empty(lib().pt_trace_workspace_bytes(), dtype=torch.uint8, device=dev)
+    with torch.cuda.device(dev):
+        check(lib().pt_trace(scene.handle, rays.data_ptr(), n, prim.data_ptr(), t.data_ptr(), ws.data_ptr(),
+                             ws.numel(), _stream_handle(dev)))
+    return prim, t
+
+
+def ray_keys(scene: Scene, rays: torch.Tensor) -> torch.Tensor:
+    assert rays.dtype == torch.float32 and rays.is_contiguous() and rays.shape[-1] == 8
+    dev = scene.device
+    keys = torch.empty(rays.shape[0], dtype=torch.int32, device=dev)
+    with torch.cuda.device(dev):
+        check(lib().pt_ray_keys(scene.handle, rays.data_ptr(), rays.shape[0], keys.data_ptr(), _stream_handle(dev)))
+    return keys
+
+
+def sort_pairs(keys: torch.Tensor, vals: torch.Tensor):
+    """In-place stable sort of (keys, vals) by the 32-bit key (int32 tensors viewed as uint32)."""
+    assert keys.dtype == torch.int32 and vals.dtype == torch.int32 and keys.numel() == vals.numel()
+    dev = keys.device
+    n = keys.numel()
+    ws = torch.empty(max(lib().pt_sort_workspace_bytes(n), 256), dtype=torch.uint8, device=dev)
+    with torch.cuda.device(dev):
+        check(lib().pt_sort_pairs(keys.data_ptr(), vals.data_ptr(), n, ws.data_ptr(), ws.numel(),
+                                  _stream_handle(dev)))
+    return keys, vals
+
+
+def device_info():
+    cu, ma, mi = C.c_int32(), C.c_int32(), C.c_int32()
+    check(lib().pt_device_info(C.byref(cu), C.byref(ma), C.byref(mi)))
+    return dict(compute_units=cu.value, major=ma.value, minor=mi.value)

@@ -1,0 +1,290 @@
+// Host BVH2 builder: binned surface-area heuristic (32 centroid bins per axis,
+// traversal and intersection cost 1), leaves of at most kMaxLeaf triangles,
+// object-median splits once the remaining depth budget only just fits a
+// balanced subtree, so that the leaf depth never exceeds kMaxDepth.  Large subtrees are built on separate threads; the output
+// (node order, triangle order) does not depend on thread timing because every
+// subtree is built from its own triangle range and the nodes are numbered by a
+// final depth-first pass.
+//
+// The BVH only prunes: the closest hit is the (t, prim id) minimum over all
+// triangles, whatever BVH is used.
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <array>
+#include <cstring>
+#include <future>
+#include <limits>
+#include <thread>
+
+#include "pt_internal.h"
+
+namespace pt {
+namespace {
+
+constexpr int kBins = 32;
+constexpr uint32_t kParallelMin = 1u << 16;
+constexpr uint32_t kParallelBinMin = 1u << 20;
+
+struct Box {
+    float lo[3] = {INFINITY, INFINITY, INFINITY};
+    float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    void grow(const float* l, const float* h) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], l[a]);
+            hi[a] = std::max(hi[a], h[a]);
+        }
+    }
+    void grow(const Box& b) { grow(b.lo, b.hi); }
+    double half_area() const {
+        double dx = (double)hi[0] - lo[0], dy = (double)hi[1] - lo[1], dz = (double)hi[2] - lo[2];
+        if (dx < 0 || dy < 0 || dz < 0) return 0.0;
+        return dx * dy + dy * dz + dz * dx;
+    }
+};
+
+struct BNode {
+    Box box;
+    int32_t left = -1, right = -1;   // children (build-node ids); -1 = leaf
+    uint32_t first = 0, count = 0;
+    uint32_t depth = 0;
+};
+
+struct Builder {
+    const float* tris;
+    std::vector<float> tlo, thi, cen;   // per-triangle bounds and centroid
+    std::vector<uint32_t> idx;
+    std::vector<BNode> nodes;
+    std::atomic<uint32_t> nnodes{0};
+    std::atomic<int> threads_left{0};
+
+    uint32_t alloc() { return nnodes.fetch_add(1, std::memory_order_relaxed); }
+
+    void bin_range(uint32_t first, uint32_t n, int axis, float clo, double scale, Box* bb, uint32_t* cnt) {
+        for (uint32_t i = 0; i < n; ++i) {
+            uint32_t p = idx[first + i];
+            int b = (int)(((double)cen[3 * (size_t)p + axis] - clo) * scale);
+            b = std::min(std::max(b, 0), kBins - 1);
+            ++cnt[b];
+            bb[b].grow(&tlo[3 * (size_t)p], &thi[3 * (size_t)p]);
+        }
+    }
+
+    void build(uint32_t node, uint32_t first, uint32_t n, uint32_t depth) {
+        BNode& nd = nodes[node];
+        nd.depth = depth;
+        Box cb;
+        Box bb;
+        for (uint32_t i = 0; i < n; ++i) {
+            uint32_t p = idx[first + i];
+            bb.grow(&tlo[3 * (size_t)p], &thi[3 * (size_t)p]);
+            cb.grow(&cen[3 * (size_t)p], &cen[3 * (size_t)p]);
+        }
+        nd.box = bb;
+        if (n <= (uint32_t)kMaxLeaf) {
+            nd.first = first;
+            nd.count = n;
+            return;
+        }
+        uint32_t mid = 0;
+        // switch to object-median splits while a balanced subtree still fits the depth budget
+        uint32_t need = 0;
+        for (uint64_t m = n; m > (uint64_t)kMaxLeaf; m = (m + 1) / 2) ++need;
+        bool median = depth + need + 2 >= (uint32_t)kMaxDepth;
+        int best_axis = -1, best_split = 0;
+        if (!median) {
+            double best = std::numeric_limits<double>::infinity();
+            for (int a = 0; a < 3; ++a) {
+                double ext = (double)cb.hi[a] - cb.lo[a];
+                if (!(ext > 0.0)) continue;
+                double scale = kBins / ext;
+                Box bins[kBins];
+                uint32_t cnt[kBins] = {0};
+                if (n >= kParallelBinMin) {
+                    unsigned T = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+                    std::vector<std::array<Box, kBins>> pb(T);
+                    std::vector<std::array<uint32_t, kBins>> pc(T);
+                    std::vector<std::thread> th;
+                    uint32_t chunk = (n + T - 1) / T;
+                    for (unsigned t = 0; t < T; ++t) {
+                        pc[t].fill(0);
+                        uint32_t f = first + t * chunk;
+                        uint32_t m = std::min(chunk, first + n - std::min(f, first + n));
+                        th.emplace_back([&, t, f, m] { bin_range(f, m, a, cb.lo[a], scale, pb[t].data(), pc[t].data()); });
+                    }
+                    for (auto& x : th) x.join();
+                    for (unsigned t = 0; t < T; ++t)
+                        for (int b = 0; b < kBins; ++b) {
+                            bins[b].grow(pb[t][b]);
+                            cnt[b] += pc[t][b];
+                        }
+                } else {
+                    bin_range(first, n, a, cb.lo[a], scale, bins, cnt);
+                }
+                double rarea[kBins];
+                uint32_t rcnt[kBins];
+                Box r;
+                uint32_t rc = 0;
+                for (int b = kBins - 1; b > 0; --b) {
+                    r.grow(bins[b]);
+                    rc += cnt[b];
+                    rarea[b] = r.half_area();
+                    rcnt[b] = rc;
+                }
+                Box l;
+                uint32_t lc = 0;
+                for (int b = 0; b < kBins - 1; ++b) {
+                    l.grow(bins[b]);
+                    lc += cnt[b];
+                    if (lc == 0 || rcnt[b + 1] == 0) continue;
+                    double c = l.half_area() * lc + rarea[b + 1] * rcnt[b + 1];
+                    if (c < best) {
+                        best = c;
+                        best_axis = a;
+                        best_split = b + 1;
+                    }
+                }
+            }
+        }
+        if (best_axis >= 0) {
+            double scale = kBins / ((double)cb.hi[best_axis] - cb.lo[best_axis]);
+            float clo = cb.lo[best_axis];
+            auto it = std::partition(idx.begin() + first, idx.begin() + first + n, [&](uint32_t p) {
+                int b = (int)(((double)cen[3 * (size_t)p + best_axis] - clo) * scale);
+                b = std::min(std::max(b, 0), kBins - 1);
+                return b < best_split;
+            });
+            mid = (uint32_t)(it - (idx.begin() + first));
+        }
+        if (best_axis < 0 || mid == 0 || mid == n) {
+            // object median on the widest centroid axis (ties by triangle id)
+            int axis = 0;
+            for (int a = 1; a < 3; ++a)
+                if ((double)cb.hi[a] - cb.lo[a] > (double)cb.hi[axis] - cb.lo[axis]) axis = a;
+            mid = n / 2;
+            std::nth_element(idx.begin() + first, idx.begin() + first + mid, idx.begin() + first + n,
+                             [&](uint32_t x, uint32_t y) {
+                                 float cx = cen[3 * (size_t)x + axis], cy = cen[3 * (size_t)y + axis];
+                                 return cx < cy || (cx == cy && x < y);
+                             });
+        }
+        uint32_t L = alloc(), R = alloc();
+        nd.left = (int32_t)L;
+        nd.right = (int32_t)R;
+        bool par = n >= kParallelMin && threads_left.fetch_sub(1) > 0;
+        if (par) {
+            auto fut = std::async(std::launch::async, [this, L, first, mid, depth] { build(L, first, mid, depth + 1); });
+            build(R, first + mid, n - mid, depth + 1);
+            fut.get();
+            threads_left.fetch_add(1);
+        } else {
+            if (n >= kParallelMin) threads_left.fetch_add(1);
+            build(L, first, mid, depth + 1);
+            build(R, first + mid, n - mid, depth + 1);
+        }
+    }
+};
+
+int32_t leaf_code(const BNode& b) {
+    return (int32_t)~((b.first << 3) | (b.count - 1));
+}
+
+}  // namespace
+
+bool build_bvh(const float* tris, uint32_t ntri, HostBvh& out, std::string& err) {
+    out = HostBvh();
+    if (ntri > kMaxTris) {
+        err = "too many triangles";
+        return false;
+    }
+    BvhNode empty_root;
+    for (int i = 0; i < 12; ++i) empty_root.f[i] = (i % 2 == 0) ? INFINITY : -INFINITY;
+    empty_root.c[0] = empty_root.c[1] = kEmpty;
+    empty_root.c[2] = empty_root.c[3] = 0;
+    if (ntri == 0) {
+        out.nodes.push_back(empty_root);
+        return true;
+    }
+    Builder b;
+    b.tris = tris;
+    try {
+        b.tlo.resize(3 * (size_t)ntri);
+        b.thi.resize(3 * (size_t)ntri);
+        b.cen.resize(3 * (size_t)ntri);
+        b.idx.resize(ntri);
+        b.nodes.resize(2 * (size_t)ntri + 1);
+    } catch (...) {
+        err = "host allocation failed";
+        return false;
+    }
+    for (uint32_t i = 0; i < ntri; ++i) {
+        const float* v = tris + 9 * (size_t)i;
+        for (int a = 0; a < 3; ++a) {
+            float x0 = v[a], x1 = v[3 + a], x2 = v[6 + a];
+            b.tlo[3 * (size_t)i + a] = std::min(x0, std::min(x1, x2));
+            b.thi[3 * (size_t)i + a] = std::max(x0, std::max(x1, x2));
+            b.cen[3 * (size_t)i + a] = (float)(((double)x0 + (double)x1 + (double)x2) / 3.0);
+        }
+        b.idx[i] = i;
+    }
+    b.threads_left = (int)std::max(1u, std::min(32u, std::thread::hardware_concurrency())) - 1;
+    uint32_t root = b.alloc();
+    b.build(root, 0, ntri, 0);
+
+    // number inner nodes depth-first (left subtree right after its parent)
+    const BNode& rn = b.nodes[root];
+    double root_area = rn.box.half_area();
+    if (!(root_area > 0.0)) root_area = 1.0;
+    if (rn.left < 0) {
+        BvhNode n = empty_root;
+        const Box& bx = rn.box;
+        n.f[0] = bx.lo[0]; n.f[1] = bx.hi[0]; n.f[2] = bx.lo[1]; n.f[3] = bx.hi[1];
+        n.f[8] = bx.lo[2]; n.f[9] = bx.hi[2];
+        n.c[0] = leaf_code(rn);
+        out.nodes.push_back(n);
+        out.max_leaf = rn.count;
+        out.sah_cost = rn.count;
+    } else {
+        std::vector<uint32_t> stack{root};
+        std::vector<int32_t> index(b.nnodes.load(), -1);
+        // pass 1: preorder numbering of inner nodes
+        std::vector<uint32_t> pre;
+        while (!stack.empty()) {
+            uint32_t x = stack.back();
+            stack.pop_back();
+            const BNode& nd = b.nodes[x];
+            if (nd.left < 0) continue;
+            index[x] = (int32_t)pre.size();
+            pre.push_back(x);
+            stack.push_back((uint32_t)nd.right);
+            stack.push_back((uint32_t)nd.left);
+        }
+        out.nodes.resize(pre.size());
+        double cost = 0.0;
+        for (size_t k = 0; k < pre.size(); ++k) {
+            const BNode& nd = b.nodes[pre[k]];
+            const BNode& A = b.nodes[nd.left];
+            const BNode& B = b.nodes[nd.right];
+            BvhNode& o = out.nodes[k];
+            o.f[0] = A.box.lo[0]; o.f[1] = A.box.hi[0]; o.f[2] = A.box.lo[1]; o.f[3] = A.box.hi[1];
+            o.f[4] = B.box.lo[0]; o.f[5] = B.box.hi[0]; o.f[6] = B.box.lo[1]; o.f[7] = B.box.hi[1];
+            o.f[8] = A.box.lo[2]; o.f[9] = A.box.hi[2]; o.f[10] = B.box.lo[2]; o.f[11] = B.box.hi[2];
+            o.c[0] = A.left < 0 ? leaf_code(A) : index[nd.left];
+            o.c[1] = B.left < 0 ? leaf_code(B) : index[nd.right];
+            o.c[2] = o.c[3] = 0;
+            cost += nd.box.half_area() / root_area;
+            for (const BNode* ch : {&A, &B})
+                if (ch->left < 0) {
+                    cost += ch->box.half_area() / root_area * ch->count;
+                    out.max_leaf = std::max(out.max_leaf, ch->count);
+                    out.max_depth = std::max(out.max_depth, ch->depth);
+                }
+        }
+        out.sah_cost = cost;
+    }
+    out.order = std::move(b.idx);
+    return true;
+}
+
+}  // namespace pt

@@ -1,0 +1,71 @@
+// Kernel launch interface of libpt (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pt_internal.h"
+
+namespace pt {
+
+// Scene as the kernels see it (device pointers into the caller's arena).
+struct DevScene {
+    const float4* nodes;     // [nnodes][4]  child-pair nodes
+    const float4* btris;     // [ntri][3]    BVH order; v0.w = original triangle id (int bits)
+    const float4* otris;     // [ntri][3]    original order
+    const uint32_t* tri_mat; // [ntri]
+    const pt_material* mats; // [nmat]
+    uint32_t ntri, nmat;
+    float env[3];
+    float lo[3], hi[3];
+};
+
+// One frame's launch constants.
+struct Frame {
+    int w, h, spp, B, mode;
+    int W, H, K, WH, reuse_max;
+    int SW, SH, TS, cols;     // super tile (one workgroup of the shade kernel)
+    int nstx, nsty, ntx;      // super tiles per row/column, reuse tiles per row
+    uint32_t nslots;
+    uint64_t seed;
+    float cpos[3], cfwd[3], cright[3], cup[3];
+    float th, thx;
+};
+
+// Ray queue record: {ox, oy, oz, excluded prim} {dx, dy, dz, pixel}; pixel = kNoRay: no ray.
+constexpr uint32_t kNoRay = 0xFFFFFFFFu;
+constexpr int kTraceBlock = 64;    // one wave per workgroup
+constexpr int kStackLds = 16;      // LDS stack entries per lane
+constexpr int kStackOvf = kMaxDepth - kStackLds + 16; // global overflow entries per lane
+constexpr int kMaxTraceBlocks = 256 * 24;  // cap of the persistent grid (bounds the overflow area)
+
+struct TraceArgs {
+    const float4* rays;
+    uint32_t n;
+    const uint32_t* n_dev;     // optional device-side count (sorted mode: live rays)
+    uint32_t* work;            // work counter (zeroed before launch)
+    int32_t* out_prim;         // indexed by pixel (by_pixel) or by ray
+    float* out_t;
+    uint32_t* ray_count;       // optional
+    unsigned long long* stats; // optional [2]
+    int32_t* ovf;              // [kStackOvf][grid threads]
+    int by_pixel;
+};
+
+int trace_grid_blocks();   // persistent grid size (workgroups), <= kMaxTraceBlocks
+hipError_t launch_trace(const DevScene& sc, const TraceArgs& a, bool stats, hipStream_t st);
+hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t st);
+hipError_t launch_raygen(const Frame& f, int s, float4* q, float4* state, float4* rays_out, hipStream_t st);
+hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const float4* q_in, float4* q_out,
+                        float4* state, int32_t* hit_prim, float* hit_t, float* radiance, float4* rays_out,
+                        hipStream_t st);
+hipError_t launch_keys(const DevScene& sc, const float4* q, uint32_t n, uint32_t* keys, uint32_t* vals,
+                       uint32_t* n_live, hipStream_t st);
+hipError_t launch_gather(const float4* q, const uint32_t* idx, uint32_t n, float4* out, hipStream_t st);
+
+// stable LSD radix sort (4 passes of 8 bits)
+size_t sort_workspace_bytes(uint32_t n);
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t n, void* ws, hipStream_t st);
+
+}  // namespace pt

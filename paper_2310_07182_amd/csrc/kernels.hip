@@ -1,0 +1,823 @@
+// HIP kernels of libpt for gfx950 (MI355X).
+//
+// Wavefront path tracer: raygen -> [key -> sort -> gather] -> trace -> shade, per
+// bounce.  Arithmetic on the ray chain is binary32 without FMA contraction (the
+// library is compiled with -ffp-contract=off), correctly rounded division and
+// square root, in the operation order fixed by the arithmetic contract, so that
+// hit ids are reproducible bit for bit.  Box tests only prune and use explicit
+// conservative margins.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace pt {
+namespace {
+
+// ------------------------------------------------------------------ vector helpers
+struct V3 {
+    float x, y, z;
+};
+__device__ __forceinline__ V3 mk3(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 sub3(V3 a, V3 b) { return mk3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ V3 add3(V3 a, V3 b) { return mk3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ V3 scl3(V3 a, float s) { return mk3(a.x * s, a.y * s, a.z * s); }
+__device__ __forceinline__ float dot3(V3 a, V3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+__device__ __forceinline__ V3 cross3(V3 a, V3 b) {
+    return mk3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ V3 unit3(V3 v) {
+    float inv = 1.0f / sqrtf(dot3(v, v));
+    return scl3(v, inv);
+}
+__device__ __forceinline__ V3 xyz(float4 v) { return mk3(v.x, v.y, v.z); }
+
+// ------------------------------------------------------------------ Philox4x64-10
+struct U64x4 {
+    uint64_t v[4];
+};
+__device__ __forceinline__ U64x4 philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    uint64_t k1 = 0;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
+        uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    return U64x4{{c0, c1, c2, c3}};
+}
+__device__ __forceinline__ float unit01(uint64_t x) { return (float)(uint32_t)(x >> 40) * 0x1p-24f; }
+
+// sin and cos of 2*pi*u: exact octant reduction, Taylor polynomials on [0, pi/4]
+__device__ __forceinline__ void sincos_turn(float u, float& sn, float& cs) {
+    const float kQuarterPi = (float)(3.14159265358979323846 / 4.0);
+    const float s3 = (float)(-1.0 / 6.0), s5 = (float)(1.0 / 120.0);
+    const float s7 = (float)(-1.0 / 5040.0), s9 = (float)(1.0 / 362880.0);
+    const float c2 = -0.5f, c4 = (float)(1.0 / 24.0), c6 = (float)(-1.0 / 720.0);
+    const float c8 = (float)(1.0 / 40320.0), c10 = (float)(-1.0 / 3628800.0);
+    float v = u * 8.0f;
+    int oct = (int)v;
+    float f = v - (float)oct;
+    float g = (oct & 1) ? 1.0f - f : f;
+    float a = g * kQuarterPi;
+    float a2 = a * a;
+    float s = a + (a * a2) * (s3 + a2 * (s5 + a2 * (s7 + a2 * s9)));
+    float c = 1.0f + a2 * (c2 + a2 * (c4 + a2 * (c6 + a2 * (c8 + a2 * c10))));
+    // (sin, cos) by octant: (s,c) (c,s) (c,-s) (s,-c) (-s,-c) (-c,-s) (-c,s) (-s,c)
+    oct &= 7;
+    bool swap = ((oct + 1) & 2) != 0;       // octants 1,2,5,6
+    float p = swap ? c : s, q = swap ? s : c;
+    sn = (oct >= 4) ? -p : p;
+    cs = (oct >= 2 && oct <= 5) ? -q : q;
+}
+
+// ------------------------------------------------------------------ frame
+__device__ __forceinline__ V3 push_off(V3 p, V3 n) {
+    // Waechter & Binder integer-ulp offset along n
+    const float kOrigin = 1.0f / 32.0f, kFloatScale = 1.0f / 65536.0f, kIntScale = 256.0f;
+    int ox = (int)(kIntScale * n.x), oy = (int)(kIntScale * n.y), oz = (int)(kIntScale * n.z);
+    float px = __int_as_float(__float_as_int(p.x) + (p.x < 0.0f ? -ox : ox));
+    float py = __int_as_float(__float_as_int(p.y) + (p.y < 0.0f ? -oy : oy));
+    float pz = __int_as_float(__float_as_int(p.z) + (p.z < 0.0f ? -oz : oz));
+    return mk3(fabsf(p.x) < kOrigin ? p.x + kFloatScale * n.x : px,
+               fabsf(p.y) < kOrigin ? p.y + kFloatScale * n.y : py,
+               fabsf(p.z) < kOrigin ? p.z + kFloatScale * n.z : pz);
+}
+
+__device__ __forceinline__ void frame_of(V3 n, V3& t, V3& bt) {
+    float s = copysignf(1.0f, n.z);
+    float a = -1.0f / (s + n.z);
+    float b = (n.x * n.y) * a;
+    t = mk3(1.0f + ((s * n.x) * n.x) * a, s * b, -(s * n.x));
+    bt = mk3(b, s + (n.y * n.y) * a, -n.y);
+}
+
+__device__ __forceinline__ V3 tangent_to_world(V3 q, V3 t, V3 bt, V3 n) {
+    return mk3((q.x * t.x + q.y * bt.x) + q.z * n.x, (q.x * t.y + q.y * bt.y) + q.z * n.y,
+               (q.x * t.z + q.y * bt.z) + q.z * n.z);
+}
+
+// ------------------------------------------------------------------ BSDF sampling (tangent space)
+__device__ __forceinline__ V3 cosine_dir(float u2, float u3) {
+    float r = sqrtf(u2);
+    float sn, cs;
+    sincos_turn(u3, sn, cs);
+    float z2 = 1.0f - u2;
+    return mk3(r * cs, r * sn, sqrtf(z2 > 0.0f ? z2 : 0.0f));
+}
+
+__device__ __forceinline__ float g1_smith(float z, float a2) {
+    float z2 = z * z;
+    float num = 1.0f - z2;
+    float tan2 = (num > 0.0f ? num : 0.0f) / z2;
+    return 2.0f / (1.0f + sqrtf(1.0f + a2 * tan2));
+}
+
+// GGX exit (Walter et al. 2007 sampling of the normal, Smith G, Schlick F), written
+// without early returns: the caller selects by the returned validity.
+__device__ __forceinline__ bool ggx_dir(V3 wi, float alpha, const float* f0, float u2, float u3, V3& wo, float* w) {
+    const float a2 = alpha * alpha;
+    const float tan2m = (a2 * u2) / (1.0f - u2);
+    const float cm = 1.0f / sqrtf(1.0f + tan2m);
+    const float sm2 = 1.0f - cm * cm;
+    const float sm = sqrtf(sm2 > 0.0f ? sm2 : 0.0f);
+    float sn, cs;
+    sincos_turn(u3, sn, cs);
+    const V3 m = mk3(sm * cs, sm * sn, cm);
+    const float wim = dot3(wi, m);
+    const float k = 2.0f * wim;
+    const V3 o = mk3(k * m.x - wi.x, k * m.y - wi.y, k * m.z - wi.z);
+    const float g = ((g1_smith(wi.z, a2) * g1_smith(o.z, a2)) * wim) / (wi.z * cm);
+    const float c = 1.0f - wim;
+    const float c5 = ((c * c) * (c * c)) * c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) w[i] = (f0[i] + (1.0f - f0[i]) * c5) * g;
+    wo = o;
+    return wi.z > 0.0f && wim > 0.0f && o.z > 0.0f;
+}
+
+// ------------------------------------------------------------------ watertight ray/triangle
+struct RayPre {
+    float ox, oy, oz;   // origin, permuted to (kx, ky, kz)
+    float sx, sy, sz;
+    int kx, ky, kz;
+};
+
+__device__ __forceinline__ float pick(float a, float b, float c, int k) { return k == 0 ? a : (k == 1 ? b : c); }
+
+__device__ __forceinline__ RayPre prepare(V3 o, V3 d) {
+    RayPre r;
+    float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+    int kz = 0;
+    float m = ax;
+    if (ay > m) {
+        kz = 1;
+        m = ay;
+    }
+    if (az > m) kz = 2;
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    float dkz = pick(d.x, d.y, d.z, kz);
+    if (dkz < 0.0f) {
+        int t = kx;
+        kx = ky;
+        ky = t;
+    }
+    r.kx = kx;
+    r.ky = ky;
+    r.kz = kz;
+    r.sx = pick(d.x, d.y, d.z, kx) / dkz;
+    r.sy = pick(d.x, d.y, d.z, ky) / dkz;
+    r.sz = 1.0f / dkz;
+    r.ox = pick(o.x, o.y, o.z, kx);
+    r.oy = pick(o.x, o.y, o.z, ky);
+    r.oz = pick(o.x, o.y, o.z, kz);
+    return r;
+}
+
+__device__ __forceinline__ float dprod_diff(float a, float b, float c, float d) {
+    return (float)((double)a * (double)b - (double)c * (double)d);
+}
+
+// hit with 0 < t < inf: returns true and t
+__device__ __forceinline__ bool tri_test(const RayPre& r, float4 p0, float4 p1, float4 p2, float& t_out) {
+    float Ax = pick(p0.x, p0.y, p0.z, r.kx) - r.ox, Ay = pick(p0.x, p0.y, p0.z, r.ky) - r.oy;
+    float Az0 = pick(p0.x, p0.y, p0.z, r.kz) - r.oz;
+    float Bx = pick(p1.x, p1.y, p1.z, r.kx) - r.ox, By = pick(p1.x, p1.y, p1.z, r.ky) - r.oy;
+    float Bz0 = pick(p1.x, p1.y, p1.z, r.kz) - r.oz;
+    float Cx = pick(p2.x, p2.y, p2.z, r.kx) - r.ox, Cy = pick(p2.x, p2.y, p2.z, r.ky) - r.oy;
+    float Cz0 = pick(p2.x, p2.y, p2.z, r.kz) - r.oz;
+    Ax = Ax - r.sx * Az0;
+    Ay = Ay - r.sy * Az0;
+    Bx = Bx - r.sx * Bz0;
+    By = By - r.sy * Bz0;
+    Cx = Cx - r.sx * Cz0;
+    Cy = Cy - r.sy * Cz0;
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = dprod_diff(Cx, By, Cy, Bx);
+        V = dprod_diff(Ax, Cy, Ay, Cx);
+        W = dprod_diff(Bx, Ay, By, Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    float det = (U + V) + W;
+    if (det == 0.0f) return false;
+    float Az = r.sz * Az0, Bz = r.sz * Bz0, Cz = r.sz * Cz0;
+    float T = (U * Az + V * Bz) + W * Cz;
+    float t = T / det;
+    if (!(t > 0.0f) || !(t < INFINITY)) return false;
+    t_out = t;
+    return true;
+}
+
+// ------------------------------------------------------------------ traversal
+// Slab test of one child box; conservative: the far distance is widened by
+// (1 + 2*gamma_3) (Ize, "Robust BVH Ray Traversal", JCGT 2013) and the caller
+// culls against the best distance widened by 2^-18.
+constexpr float kFarScale = 1.0f + 2.0f * (3.0f * 0x1p-24f) / (1.0f - 3.0f * 0x1p-24f);
+constexpr float kCullScale = 1.0f + 0x1p-18f;
+
+__device__ __forceinline__ float slab(float lx, float hx, float ly, float hy, float lz, float hz, V3 o, V3 inv,
+                                      float tcull, bool& hit) {
+    float x0 = (lx - o.x) * inv.x, x1 = (hx - o.x) * inv.x;
+    float y0 = (ly - o.y) * inv.y, y1 = (hy - o.y) * inv.y;
+    float z0 = (lz - o.z) * inv.z, z1 = (hz - o.z) * inv.z;
+    float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
+    float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fmaxf(z0, z1)) * kFarScale;
+    hit = tn <= tf && tn <= tcull;
+    return tn;
+}
+
+constexpr int32_t kDone = INT32_MIN;   // = kEmpty: never a node or leaf code
+
+template <bool STATS>
+__global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a, uint32_t gthreads) {
+    __shared__ int32_t stk[kStackLds][kTraceBlock];
+    const int lane = threadIdx.x;
+    const uint32_t gtid = blockIdx.x * kTraceBlock + lane;
+    uint32_t n = a.n;
+    if (a.n_dev) n = min(n, *a.n_dev);
+    unsigned long long nv = 0, nt = 0;
+    for (;;) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(a.work, (uint32_t)kTraceBlock);
+        base = __shfl(base, 0);
+        if (base >= n) break;
+        const uint32_t i = base + lane;
+        bool valid = i < n;
+        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+        if (valid) {
+            r0 = a.rays[2 * (size_t)i];
+            r1 = a.rays[2 * (size_t)i + 1];
+        }
+        const uint32_t pix = __float_as_uint(r1.w);
+        if (a.by_pixel) valid = valid && pix != kNoRay;
+        float best_t = INFINITY;
+        int32_t best_p = INT32_MAX;
+        if (valid) {
+            const V3 o = xyz(r0), d = xyz(r1);
+            const int32_t excl = __float_as_int(r0.w);
+            const V3 inv = mk3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
+            const RayPre rp = prepare(o, d);
+            int sp = 0, novf = 0;
+            int32_t cur = 0;   // root node
+            while (cur != kDone) {
+                if (cur >= 0) {
+                    const float4* nd = sc.nodes + 4 * (size_t)cur;
+                    const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
+                    if (STATS) ++nv;
+                    const float tcull = best_t * kCullScale;
+                    const int32_t c0 = __float_as_int(n3.x), c1 = __float_as_int(n3.y);
+                    bool h0, h1;
+                    const float t0 = slab(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, o, inv, tcull, h0);
+                    const float t1 = slab(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, o, inv, tcull, h1);
+                    h0 = h0 && c0 != kEmpty;
+                    h1 = h1 && c1 != kEmpty;
+                    if (h0 && h1) {
+                        const bool swp = t1 < t0;
+                        const int32_t far = swp ? c0 : c1;
+                        cur = swp ? c1 : c0;
+                        if (sp == kStackLds) {
+                            // the BVH depth bound keeps the stack within kStackLds + kStackOvf
+                            // entries; the check keeps every access in bounds regardless
+                            if (novf + kStackLds / 2 > kStackOvf) {
+                                cur = kDone;
+                                continue;
+                            }
+                            // spill the lower half of the LDS stack to this lane's overflow column
+                            for (int e = 0; e < kStackLds / 2; ++e)
+                                a.ovf[(size_t)(novf + e) * gthreads + gtid] = stk[e][lane];
+                            for (int e = 0; e < kStackLds / 2; ++e) stk[e][lane] = stk[e + kStackLds / 2][lane];
+                            novf += kStackLds / 2;
+                            sp = kStackLds / 2;
+                        }
+                        stk[sp++][lane] = far;
+                        continue;
+                    }
+                    if (h0) {
+                        cur = c0;
+                        continue;
+                    }
+                    if (h1) {
+                        cur = c1;
+                        continue;
+                    }
+                } else {
+                    const uint32_t code = ~(uint32_t)cur;
+                    const uint32_t first = code >> 3, cnt = (code & 7u) + 1u;
+                    for (uint32_t k = 0; k < cnt; ++k) {
+                        const float4* tp = sc.btris + 3 * (size_t)(first + k);
+                        const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
+                        const int32_t pid = __float_as_int(p0.w);
+                        if (pid == excl) continue;
+                        if (STATS) ++nt;
+                        float t;
+                        if (tri_test(rp, p0, p1, p2, t) && (t < best_t || (t == best_t && pid < best_p))) {
+                            best_t = t;
+                            best_p = pid;
+                        }
+                    }
+                }
+                // pop
+                if (sp == 0) {
+                    if (novf == 0) {
+                        cur = kDone;
+                        continue;
+                    }
+                    const int m = novf < kStackLds / 2 ? novf : kStackLds / 2;
+                    for (int e = 0; e < m; ++e) stk[e][lane] = a.ovf[(size_t)(novf - m + e) * gthreads + gtid];
+                    novf -= m;
+                    sp = m;
+                }
+                cur = stk[--sp][lane];
+            }
+            const uint32_t oi = a.by_pixel ? pix : i;
+            a.out_prim[oi] = best_p == INT32_MAX ? -1 : best_p;
+            a.out_t[oi] = best_t;
+        }
+        if (a.ray_count) {
+            const unsigned long long m = __ballot(valid);
+            if (lane == 0 && m) atomicAdd(a.ray_count, (uint32_t)__popcll(m));
+        }
+    }
+    if (STATS) {
+        for (int off = 32; off > 0; off >>= 1) {
+            nv += __shfl_down(nv, off);
+            nt += __shfl_down(nt, off);
+        }
+        if (lane == 0) {
+            atomicAdd(a.stats, nv);
+            atomicAdd(a.stats + 1, nt);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ slot <-> pixel mapping
+struct SlotPix {
+    int x, y, tin, i;
+    bool inside;
+};
+__device__ __forceinline__ SlotPix slot_pixel(const Frame& f, uint32_t block, int l) {
+    SlotPix r;
+    const int stx = (int)(block % (uint32_t)f.nstx), sty = (int)(block / (uint32_t)f.nstx);
+    r.tin = l / f.WH;
+    r.i = l - r.tin * f.WH;
+    const int tcol = r.tin % f.cols, trow = r.tin / f.cols;
+    r.x = stx * f.SW + tcol * f.W + (r.i % f.W);
+    r.y = sty * f.SH + trow * f.H + (r.i / f.W);
+    r.inside = r.x < f.w && r.y < f.h;
+    return r;
+}
+
+__global__ __launch_bounds__(1024) void k_raygen(Frame f, int s, float4* q, float4* state, float4* rays_out) {
+    const int l = threadIdx.x;
+    const uint32_t p = blockIdx.x * (uint32_t)f.TS + (uint32_t)l;
+    const SlotPix sp = slot_pixel(f, blockIdx.x, l);
+    float4 r0 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1)), r1 = make_float4(0.f, 0.f, 0.f, __uint_as_float(kNoRay));
+    float4 s0 = make_float4(1.f, 1.f, 1.f, __uint_as_float(0u)), s1 = make_float4(0.f, 0.f, 0.f, __uint_as_float(p));
+    if (sp.inside) {
+        const uint32_t pix = (uint32_t)sp.y * (uint32_t)f.w + (uint32_t)sp.x;
+        const U64x4 rnd = philox(pix, (uint64_t)s, 0, 0, f.seed);
+        const float u0 = unit01(rnd.v[0]), u1 = unit01(rnd.v[1]);
+        const float px = ((float)sp.x + u0) / (float)f.w;
+        const float py = ((float)sp.y + u1) / (float)f.h;
+        const float fx = (2.0f * px - 1.0f) * f.thx;
+        const float fy = (1.0f - 2.0f * py) * f.th;
+        V3 d = mk3((fx * f.cright[0] + fy * f.cup[0]) + f.cfwd[0], (fx * f.cright[1] + fy * f.cup[1]) + f.cfwd[1],
+                   (fx * f.cright[2] + fy * f.cup[2]) + f.cfwd[2]);
+        d = unit3(d);
+        r0 = make_float4(f.cpos[0], f.cpos[1], f.cpos[2], __int_as_float(-1));
+        r1 = make_float4(d.x, d.y, d.z, __uint_as_float(pix));
+        s0.w = __uint_as_float(1u);
+        if (rays_out) {
+            const size_t at = 2 * ((size_t)s * f.w * f.h + pix);
+            rays_out[at] = r0;
+            rays_out[at + 1] = r1;
+        }
+    }
+    q[2 * (size_t)p] = r0;
+    q[2 * (size_t)p + 1] = r1;
+    state[2 * (size_t)p] = s0;
+    state[2 * (size_t)p + 1] = s1;
+}
+
+// ------------------------------------------------------------------ shade + next direction
+// One workgroup = one super tile (whole reuse tiles), one thread per slot.
+__global__ __launch_bounds__(1024) void k_shade(DevScene sc, Frame f, int b, int s, const float4* __restrict__ q_in,
+                                                float4* __restrict__ q_out, float4* state, int32_t* hit_prim,
+                                                float* hit_t, float* radiance, float4* rays_out) {
+    // group exchange in LDS, TS entries each: own tangent exit, tree sums, info bits, min active slot
+    extern __shared__ float lds[];
+    const int TS = f.TS;
+    float* sq0 = lds;
+    float* sq1 = lds + TS;
+    float* sq2 = lds + 2 * TS;
+    float* ss0 = lds + 3 * TS;
+    float* ss1 = lds + 4 * TS;
+    float* ss2 = lds + 5 * TS;
+    int* sinfo = (int*)(lds + 6 * TS);
+    int* srep = (int*)(lds + 7 * TS);
+    const int l = threadIdx.x;
+    const uint32_t p = blockIdx.x * (uint32_t)f.TS + (uint32_t)l;
+    const SlotPix spx = slot_pixel(f, blockIdx.x, l);
+    const uint32_t pix = spx.inside ? (uint32_t)spx.y * (uint32_t)f.w + (uint32_t)spx.x : 0u;
+    float4 s0 = state[2 * (size_t)p], s1 = state[2 * (size_t)p + 1];
+    float T[3] = {s0.x, s0.y, s0.z}, L[3] = {s1.x, s1.y, s1.z};
+    const bool alive_in = (__float_as_uint(s0.w) & 1u) != 0;
+    bool alive = alive_in;
+    const uint32_t qpos = __float_as_uint(s1.w);
+    const size_t plane = (size_t)f.w * (size_t)f.h;
+    const size_t hb = ((size_t)b * f.spp + s) * plane;
+    // The shading below is straight-line code: every lane evaluates every candidate
+    // exit and the results are selected by material kind.  (A divergent three-way
+    // branch here was miscompiled: registers live into the last branch were reused
+    // by the others.)  The arithmetic of each candidate is unchanged.
+    int32_t prim = -1;
+    float t = 0.0f;
+    if (alive_in) {
+        prim = hit_prim[hb + pix];
+        t = hit_t[hb + pix];
+    }
+    const float4 r0 = q_in[2 * (size_t)qpos], r1 = q_in[2 * (size_t)qpos + 1];
+    const V3 o = xyz(r0), d = xyz(r1);
+    const bool hit = alive_in && prim >= 0;
+    pt_material m;
+    m.kind = 0;
+    for (int c = 0; c < 3; ++c) {
+        m.albedo[c] = 0.0f;
+        m.emission[c] = 0.0f;
+    }
+    m.alpha = 0.0f;
+    float4 tv0 = make_float4(0.f, 0.f, 0.f, 0.f), tv1 = tv0, tv2 = tv0;
+    if (hit) {
+        m = sc.mats[sc.tri_mat[prim]];
+        const float4* tp = sc.otris + 3 * (size_t)prim;
+        tv0 = tp[0];
+        tv1 = tp[1];
+        tv2 = tp[2];
+    }
+    for (int c = 0; c < 3; ++c) {
+        const float le = hit ? m.emission[c] : sc.env[c];
+        L[c] = alive_in ? L[c] + T[c] * le : L[c];
+    }
+    const bool absorb = m.albedo[0] == 0.0f && m.albedo[1] == 0.0f && m.albedo[2] == 0.0f;
+    const bool active = hit && b < f.B && !absorb;
+    bool died = alive_in && !active;
+    const uint32_t kind = m.kind;
+    V3 n = unit3(cross3(sub3(xyz(tv1), xyz(tv0)), sub3(xyz(tv2), xyz(tv0))));
+    if (dot3(n, d) > 0.0f) n = mk3(-n.x, -n.y, -n.z);
+    const V3 hp = mk3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
+    const V3 origin = push_off(hp, n);
+    V3 tt, bt;
+    frame_of(n, tt, bt);
+    const V3 md = mk3(-d.x, -d.y, -d.z);
+    const V3 wi = mk3(dot3(md, tt), dot3(md, bt), dot3(md, n));
+    const U64x4 rnd = philox(pix, (uint64_t)s, (uint64_t)b, 0, f.seed);
+    const float u2 = unit01(rnd.v[2]), u3 = unit01(rnd.v[3]);
+    const V3 lam = cosine_dir(u2, u3);
+    V3 gg;
+    float gw[3];
+    const bool g_ok = ggx_dir(wi, m.alpha, m.albedo, u2, u3, gg, gw);
+    const V3 mir = mk3(-wi.x, -wi.y, wi.z);
+    const V3 own = kind == 0 ? lam : (kind == 1 ? gg : mir);
+    const bool own_ok = active && (kind == 0 ? true : (kind == 1 ? g_ok : mir.z > 0.0f));
+    float w3[3];
+    for (int c = 0; c < 3; ++c) w3[c] = kind == 1 ? gw[c] : m.albedo[c];
+    V3 use = own;
+    bool use_ok = own_ok;
+    uint32_t newpos = p;
+    const bool reuse = f.mode == PT_MODE_REUSE && b < f.B && b + 1 <= f.reuse_max;
+    if (reuse) {
+        // interleaved grouping: shuffle screen-order numbers inside the tile
+        uint32_t slot = 0;
+        {
+            const uint32_t tile = (uint32_t)(spx.y / f.H) * (uint32_t)f.ntx + (uint32_t)(spx.x / f.W);
+            const U64x4 rnd = philox(tile, (uint64_t)s, (uint64_t)b, 1, f.seed);
+            uint32_t ma = 1, mc = 0;
+            if (f.WH > 1) {
+                ma = 2u * (uint32_t)(rnd.v[0] & (uint64_t)(f.WH / 2 - 1)) + 1u;
+                mc = (uint32_t)(rnd.v[1] & (uint64_t)(f.WH - 1));
+            }
+            slot = (ma * (uint32_t)spx.i + mc) & (uint32_t)(f.WH - 1);
+        }
+        const int e = spx.tin * f.WH + (int)slot;
+        const bool gl_exit = active && kind != 0 && own_ok;
+        sq0[e] = own.x;
+        sq1[e] = own.y;
+        sq2[e] = own.z;
+        ss0[e] = gl_exit ? own.x : 0.0f;
+        ss1[e] = gl_exit ? own.y : 0.0f;
+        ss2[e] = gl_exit ? own.z : 0.0f;
+        sinfo[e] = (active ? (kind == 0 ? 1 : 2) : 0) | (gl_exit ? 4 : 0);
+        srep[e] = active ? (int)slot : 0x7FFFFFFF;
+        __syncthreads();
+        // pairwise tree over each group's K consecutive entries (in place, stride doubling)
+        for (int stride = 1; stride < f.K; stride <<= 1) {
+            if ((l & (2 * stride - 1)) == 0) {
+                ss0[l] = ss0[l] + ss0[l + stride];
+                ss1[l] = ss1[l] + ss1[l + stride];
+                ss2[l] = ss2[l] + ss2[l + stride];
+                sinfo[l] |= sinfo[l + stride];
+                srep[l] = min(srep[l], srep[l + stride]);
+            }
+            __syncthreads();
+        }
+        const int root = spx.tin * f.WH + ((int)slot / f.K) * f.K;
+        const int info = sinfo[root];
+        const int rslot = srep[root] < f.WH ? srep[root] : 0;
+        const int r = spx.tin * f.WH + rslot;
+        // diffuse group: every member takes the representative's tangent direction
+        const bool take_rep = active && kind == 0 && !(info & 2);
+        // hybrid group: diffuse members take the normalized sum of the glossy/specular exits
+        const bool take_avg = active && kind == 0 && (info & 2) && (info & 4);
+        const V3 repq = mk3(sq0[r], sq1[r], sq2[r]);
+        const V3 avgq = unit3(mk3(ss0[root], ss1[root], ss2[root]));
+        use = take_rep ? repq : (take_avg ? avgq : use);
+        use_ok = (take_rep || take_avg) ? true : use_ok;
+        newpos = blockIdx.x * (uint32_t)TS + (uint32_t)e;
+    }
+    if (b < f.B) {
+        float4 o0 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1)), o1 = make_float4(0.f, 0.f, 0.f, __uint_as_float(kNoRay));
+        if (active && use_ok) {
+            const V3 nd = tangent_to_world(use, tt, bt, n);
+            for (int c = 0; c < 3; ++c) T[c] = T[c] * w3[c];
+            o0 = make_float4(origin.x, origin.y, origin.z, __int_as_float(prim));
+            o1 = make_float4(nd.x, nd.y, nd.z, __uint_as_float(pix));
+            if (rays_out) {
+                const size_t at = 2 * (((size_t)(b + 1) * f.spp + s) * plane + pix);
+                rays_out[at] = o0;
+                rays_out[at + 1] = o1;
+            }
+        } else if (active) {
+            died = true;
+        }
+        q_out[2 * (size_t)newpos] = o0;
+        q_out[2 * (size_t)newpos + 1] = o1;
+    }
+    if (died) {
+        alive = false;
+        float* rp = radiance + 3 * (size_t)pix;
+        for (int c = 0; c < 3; ++c) {
+            float v = s == 0 ? L[c] : rp[c] + L[c];
+            if (s == f.spp - 1) v = v / (float)f.spp;
+            rp[c] = v;
+        }
+        for (int bb = b + 1; bb <= f.B; ++bb) {
+            const size_t at = ((size_t)bb * f.spp + s) * plane + pix;
+            hit_prim[at] = -2;
+            hit_t[at] = INFINITY;
+        }
+    }
+    state[2 * (size_t)p] = make_float4(T[0], T[1], T[2], __uint_as_float(alive ? 1u : 0u));
+    state[2 * (size_t)p + 1] = make_float4(L[0], L[1], L[2], __uint_as_float(newpos));
+}
+
+// ------------------------------------------------------------------ two-point key, gather
+__device__ __forceinline__ uint32_t q5(float x, float lo, float ext) {
+    if (!(ext > 0.0f)) return 0u;
+    const float f = ((x - lo) / ext) * 32.0f;
+    if (!(f > 0.0f)) return 0u;
+    if (f >= 31.0f) return 31u;
+    return (uint32_t)f;
+}
+
+__global__ __launch_bounds__(256) void k_keys(DevScene sc, const float4* q, uint32_t n, uint32_t* keys,
+                                              uint32_t* vals, uint32_t* n_live) {
+    const uint32_t j = blockIdx.x * 256u + threadIdx.x;
+    bool live = false;
+    if (j < n) {
+        const float4 r0 = q[2 * (size_t)j], r1 = q[2 * (size_t)j + 1];
+        live = __float_as_uint(r1.w) != kNoRay;
+        uint32_t key = 0xFFFFFFFFu;
+        if (live) {
+            const float ex = sc.hi[0] - sc.lo[0], ey = sc.hi[1] - sc.lo[1], ez = sc.hi[2] - sc.lo[2];
+            float mx = ex;
+            if (ey > mx) mx = ey;
+            if (ez > mx) mx = ez;
+            const float len = 0.25f * mx;
+            const uint32_t qc[6] = {q5(r0.x, sc.lo[0], ex), q5(r0.y, sc.lo[1], ey), q5(r0.z, sc.lo[2], ez),
+                                    q5(r0.x + len * r1.x, sc.lo[0], ex), q5(r0.y + len * r1.y, sc.lo[1], ey),
+                                    q5(r0.z + len * r1.z, sc.lo[2], ez)};
+            key = 0;
+#pragma unroll
+            for (int bit = 4; bit >= 0; --bit)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) key = (key << 1) | ((qc[c] >> bit) & 1u);
+        }
+        keys[j] = key;
+        if (vals) vals[j] = j;
+    }
+    if (n_live) {
+        const unsigned long long m = __ballot(live);
+        if ((threadIdx.x & 63) == 0 && m) atomicAdd(n_live, (uint32_t)__popcll(m));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gather(const float4* q, const uint32_t* idx, uint32_t n, float4* out) {
+    const uint32_t j = blockIdx.x * 256u + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t src = idx[j];
+    out[2 * (size_t)j] = q[2 * (size_t)src];
+    out[2 * (size_t)j + 1] = q[2 * (size_t)src + 1];
+}
+
+__global__ __launch_bounds__(256) void k_zero(uint32_t* p, size_t n) {
+    const size_t j = (size_t)blockIdx.x * 256u + threadIdx.x;
+    if (j < n) p[j] = 0u;
+}
+
+// ------------------------------------------------------------------ stable LSD radix sort
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr uint32_t kSortTile = kSortThreads * kSortItems;
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* keys, uint32_t n, int shift,
+                                                            uint32_t* hist, uint32_t nblocks) {
+    __shared__ uint32_t h[256];
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint32_t j = base + (uint32_t)r * kSortThreads + (uint32_t)tid;
+        if (j < n) atomicAdd(&h[(keys[j] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)tid * nblocks + blockIdx.x] = h[tid];
+}
+
+// exclusive scan of m counts, one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* hist, uint32_t m) {
+    __shared__ uint32_t part[1024];
+    const int tid = threadIdx.x;
+    const uint32_t seg = (m + 1023u) / 1024u;
+    const uint32_t b0 = (uint32_t)tid * seg, b1 = min(m, b0 + seg);
+    uint32_t sum = 0;
+    for (uint32_t j = b0; j < b1; ++j) sum += hist[j];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = tid >= off ? part[tid - off] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - sum;
+    for (uint32_t j = b0; j < b1; ++j) {
+        const uint32_t v = hist[j];
+        hist[j] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
+                                                               uint32_t* vout, uint32_t n, int shift,
+                                                               const uint32_t* offs, uint32_t nblocks) {
+    __shared__ uint32_t base_digit[256];
+    __shared__ uint32_t wave_cnt[kSortThreads / 64][256];
+    __shared__ uint32_t gofs[256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    base_digit[tid] = 0;
+    gofs[tid] = offs[(size_t)tid * nblocks + blockIdx.x];
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const uint32_t tile = blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        for (int w = 0; w < kSortThreads / 64; ++w) wave_cnt[w][tid] = 0;
+        __syncthreads();
+        const uint32_t j = tile + (uint32_t)r * kSortThreads + (uint32_t)tid;
+        const bool valid = j < n;
+        const uint32_t key = valid ? kin[j] : 0u;
+        const uint32_t dg = (key >> shift) & 255u;
+        unsigned long long same = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const unsigned long long bb = __ballot((dg >> bit) & 1u);
+            same &= ((dg >> bit) & 1u) ? bb : ~bb;
+        }
+        const uint32_t rank = (uint32_t)__popcll(same & lt);
+        if (valid && rank == 0) wave_cnt[wave][dg] = (uint32_t)__popcll(same);
+        __syncthreads();
+        if (valid) {
+            uint32_t before = base_digit[dg];
+            for (int w = 0; w < wave; ++w) before += wave_cnt[w][dg];
+            const uint32_t dst = gofs[dg] + before + rank;
+            kout[dst] = key;
+            vout[dst] = vin[j];
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int w = 0; w < kSortThreads / 64; ++w) add += wave_cnt[w][tid];
+        base_digit[tid] += add;
+        __syncthreads();
+    }
+}
+
+int g_trace_blocks[64] = {0};
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+int trace_grid_blocks() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (g_trace_blocks[dev] == 0) {
+        int cus = 0, per = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace<false>, kTraceBlock, 0) != hipSuccess || per <= 0)
+            per = 8;
+        int g = cus * per;
+        if (g > kMaxTraceBlocks) g = kMaxTraceBlocks;
+        g_trace_blocks[dev] = g;
+    }
+    return g_trace_blocks[dev];
+}
+
+hipError_t launch_trace(const DevScene& sc, const TraceArgs& a, bool stats, hipStream_t st) {
+    const int g = trace_grid_blocks();
+    const uint32_t gthreads = (uint32_t)g * kTraceBlock;
+    if (stats)
+        hipLaunchKernelGGL(k_trace<true>, dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads);
+    else
+        hipLaunchKernelGGL(k_trace<false>, dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_raygen(const Frame& f, int s, float4* q, float4* state, float4* rays_out, hipStream_t st) {
+    const unsigned blocks = (unsigned)(f.nslots / (uint32_t)f.TS);
+    hipLaunchKernelGGL(k_raygen, dim3(blocks), dim3(f.TS), 0, st, f, s, q, state, rays_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const float4* q_in, float4* q_out,
+                        float4* state, int32_t* hit_prim, float* hit_t, float* radiance, float4* rays_out,
+                        hipStream_t st) {
+    const unsigned blocks = (unsigned)(f.nslots / (uint32_t)f.TS);
+    const size_t lds = (f.mode == PT_MODE_REUSE) ? (size_t)f.TS * 8 * sizeof(float) : 0;
+    hipLaunchKernelGGL(k_shade, dim3(blocks), dim3(f.TS), lds, st, sc, f, b, s, q_in, q_out, state, hit_prim, hit_t,
+                       radiance, rays_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_keys(const DevScene& sc, const float4* q, uint32_t n, uint32_t* keys, uint32_t* vals,
+                       uint32_t* n_live, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keys, dim3((n + 255) / 256), dim3(256), 0, st, sc, q, n, keys, vals, n_live);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const float4* q, const uint32_t* idx, uint32_t n, float4* out, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, st, q, idx, n, out);
+    return hipGetLastError();
+}
+
+size_t sort_workspace_bytes(uint32_t n) {
+    const size_t nb = (n + kSortTile - 1) / kSortTile;
+    return 2 * (size_t)n * sizeof(uint32_t) + 256 * nb * sizeof(uint32_t) + 256;
+}
+
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t n, void* ws, hipStream_t st) {
+    if (n <= 1) return hipSuccess;
+    const uint32_t nb = (n + kSortTile - 1) / kSortTile;
+    uint32_t* kalt = (uint32_t*)ws;
+    uint32_t* valt = kalt + n;
+    uint32_t* hist = valt + n;
+    uint32_t* kin = keys;
+    uint32_t* vin = vals;
+    uint32_t* kout = kalt;
+    uint32_t* vout = valt;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(kSortThreads), 0, st, kin, n, shift, hist, nb);
+        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, st, hist, 256u * nb);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, n, shift, hist, nb);
+        uint32_t* tk = kin;
+        kin = kout;
+        kout = tk;
+        uint32_t* tv = vin;
+        vin = vout;
+        vout = tv;
+    }
+    return hipGetLastError();   // 4 passes: the result is back in keys/vals
+}
+
+}  // namespace pt

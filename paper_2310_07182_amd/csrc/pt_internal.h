@@ -1,0 +1,42 @@
+// Internal declarations of libpt (not part of the C ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pt.h"
+
+namespace pt {
+
+// Child-pair BVH2 node, 64 bytes: the boxes of both children and their codes.
+//   f[0..3]  = c0.lo.x c0.hi.x c0.lo.y c0.hi.y
+//   f[4..7]  = c1.lo.x c1.hi.x c1.lo.y c1.hi.y
+//   f[8..11] = c0.lo.z c0.hi.z c1.lo.z c1.hi.z
+//   i[12]    = code of c0, i[13] = code of c1, i[14..15] = 0
+// code >= 0: inner node index; code == kEmpty: no child;
+// otherwise leaf: ~code = (first << 3) | (count - 1), triangles [first, first+count)
+// of the BVH-ordered triangle array.
+constexpr int32_t kEmpty = INT32_MIN;
+constexpr int kMaxLeaf = 4;
+constexpr int kMaxDepth = 64;   // the traversal stack holds at most kMaxDepth entries
+constexpr uint32_t kMaxTris = (1u << 28) - 2;
+
+struct BvhNode {
+    float f[12];
+    int32_t c[4];
+};
+static_assert(sizeof(BvhNode) == 64, "node size");
+
+struct HostBvh {
+    std::vector<BvhNode> nodes;
+    std::vector<uint32_t> order;   // BVH slot -> original triangle id
+    uint32_t max_depth = 0;
+    uint32_t max_leaf = 0;
+    double sah_cost = 0.0;
+};
+
+// Binned-SAH build over the triangles (host, multi-threaded, deterministic output).
+bool build_bvh(const float* tris, uint32_t ntri, HostBvh& out, std::string& err);
+
+}  // namespace pt

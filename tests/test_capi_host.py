@@ -1,0 +1,190 @@
+"""Host-side checks of libpt (no GPU): exported symbols, argument checks,
+workspace sizes, and the validity of the host BVH build."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2310_07182_amd import capi, scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(capi.LIB_PATH):
+        from paper_2310_07182_amd import build
+        build.build()
+    return capi.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    hdr = open(os.path.join(ROOT, "include", "pt.h")).read()
+    decl = set(re.findall(r"^(?:pt_status|size_t|const char\*)\s+(pt_[a-z_]+)\s*\(", hdr, re.M))
+    assert len(decl) >= 18
+    for name in sorted(decl):
+        assert hasattr(L, name), name
+    assert decl == set(capi.PROTOTYPES), decl ^ set(capi.PROTOTYPES)
+
+
+def _desc(scene):
+    tris = np.ascontiguousarray(scene["tris"], np.float32)
+    mat = np.ascontiguousarray(scene["tri_mat"], np.uint32)
+    mats = np.ascontiguousarray(scene["mats"])
+    d = capi.SceneDesc()
+    d.tris, d.ntri, d.tri_mat, d.mats, d.nmat = tris.ctypes.data, len(tris), mat.ctypes.data, mats.ctypes.data, len(mats)
+    d.env_radiance[:] = [float(v) for v in scene["env"]]
+    return d, (tris, mat, mats)
+
+
+def _create(L, scene):
+    d, keep = _desc(scene)
+    h = C.c_void_p()
+    st = L.pt_scene_create(C.byref(d), C.byref(h))
+    return st, h, keep
+
+
+def _bvh(L, h):
+    info = capi.SceneInfo()
+    assert L.pt_scene_get_info(h, C.byref(info)) == 0
+    nodes = np.zeros((info.nnodes, 16), np.float32)
+    order = np.zeros(info.ntri, np.uint32)
+    assert L.pt_scene_export_bvh(h, nodes.ctypes.data, order.ctypes.data) == 0
+    return info, nodes, order
+
+
+def _check_bvh(tris, info, nodes, order):
+    codes = nodes[:, 12:14].view(np.int32)
+    assert np.array_equal(np.sort(order), np.arange(len(tris)))
+    seen = np.zeros(len(tris), np.int32)
+    EMPTY = np.iinfo(np.int32).min
+    stack = [(0, 0)]
+    max_depth = 0
+    while stack:
+        ni, depth = stack.pop()
+        f = nodes[ni]
+        boxes = [((f[0], f[2], f[8]), (f[1], f[3], f[9])), ((f[4], f[6], f[10]), (f[5], f[7], f[11]))]
+        for c in range(2):
+            code = int(codes[ni, c])
+            if code == EMPTY:
+                continue
+            lo, hi = np.array(boxes[c][0]), np.array(boxes[c][1])
+            if code >= 0:
+                g = nodes[code]
+                # the child's children lie inside the child's box
+                for cc in range(2):
+                    if int(codes[code, cc]) == EMPTY:
+                        continue
+                    glo = np.array([g[0 + 4 * cc], g[2 + 4 * cc], g[8 + 2 * cc]])
+                    ghi = np.array([g[1 + 4 * cc], g[3 + 4 * cc], g[9 + 2 * cc]])
+                    assert (glo >= lo).all() and (ghi <= hi).all()
+                stack.append((code, depth + 1))
+            else:
+                v = ~code & 0xFFFFFFFF
+                first, cnt = v >> 3, (v & 7) + 1
+                assert cnt <= 4
+                max_depth = max(max_depth, depth + 1)
+                for j in range(first, first + cnt):
+                    tv = tris[order[j]]
+                    assert (tv.min(0) >= lo).all() and (tv.max(0) <= hi).all()
+                    seen[order[j]] += 1
+    assert (seen == 1).all()
+    assert max_depth <= 64
+    return max_depth
+
+
+@pytest.mark.parametrize("fn", [scenes.tiny, scenes.furnace, scenes.mixed_small])
+def test_bvh_valid(L, fn):
+    s = fn()
+    st, h, keep = _create(L, s)
+    assert st == 0
+    info, nodes, order = _bvh(L, h)
+    assert info.ntri == len(s["tris"])
+    assert np.allclose(info.lo, s["tris"].reshape(-1, 3).min(0)) and np.allclose(info.hi, s["tris"].reshape(-1, 3).max(0))
+    _check_bvh(s["tris"], info, nodes, order)
+    L.pt_scene_free(h)
+
+
+def test_bvh_deterministic(L):
+    s = scenes.mixed_small()
+    outs = []
+    for _ in range(2):
+        st, h, keep = _create(L, s)
+        info, nodes, order = _bvh(L, h)
+        outs.append((nodes.copy(), order.copy()))
+        L.pt_scene_free(h)
+    assert np.array_equal(outs[0][0].view(np.uint32), outs[1][0].view(np.uint32))
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_bvh_degenerate_inputs(L):
+    # all triangles identical (no SAH split possible) and tiny counts
+    tri = np.array([[[0, 0, 0], [1, 0, 0], [0, 1, 0]]], np.float32)
+    mats = np.array([(0, (0.5, 0.5, 0.5), 0.0, (0, 0, 0))], dtype=scenes.MATERIAL_DTYPE)
+    for n in (1, 3, 4, 5, 37, 1000):
+        s = dict(tris=np.repeat(tri, n, 0), tri_mat=np.zeros(n, np.uint32), mats=mats, env=np.ones(3, np.float32))
+        st, h, keep = _create(L, s)
+        assert st == 0
+        info, nodes, order = _bvh(L, h)
+        _check_bvh(s["tris"], info, nodes, order)
+        L.pt_scene_free(h)
+
+
+def test_empty_scene(L):
+    mats = np.array([(0, (0.5, 0.5, 0.5), 0.0, (0, 0, 0))], dtype=scenes.MATERIAL_DTYPE)
+    s = dict(tris=np.zeros((0, 3, 3), np.float32), tri_mat=np.zeros(0, np.uint32), mats=mats, env=np.ones(3, np.float32))
+    st, h, keep = _create(L, s)
+    assert st == 0
+    info, nodes, order = _bvh(L, h)
+    assert info.nnodes == 1 and info.ntri == 0
+    L.pt_scene_free(h)
+
+
+def test_scene_errors(L):
+    s = scenes.furnace()
+    bad = dict(s)
+    bad["tri_mat"] = s["tri_mat"].copy()
+    bad["tri_mat"][3] = 7
+    st, h, keep = _create(L, bad)
+    assert st == capi.PT_EINVAL and b"material" in L.pt_last_error()
+    bad = dict(s)
+    bad["tris"] = s["tris"].copy()
+    bad["tris"][2, 1, 0] = np.nan
+    st, h, keep = _create(L, bad)
+    assert st == capi.PT_EINVAL and b"non-finite" in L.pt_last_error()
+    assert L.pt_scene_create(None, None) == capi.PT_EINVAL
+
+
+def _group(w, h, k, r=4):
+    g = capi.Group()
+    g.tile_w, g.tile_h, g.k, g.reuse_max_bounce = w, h, k, r
+    return g
+
+
+def test_workspace_sizes(L):
+    ok = L.pt_render_workspace_bytes(1920, 1080, 1, 4, 2, _group(8, 8, 8))
+    assert ok > 3 * 1920 * 1080 * 32
+    srt = L.pt_render_workspace_bytes(1920, 1080, 1, 4, 1, _group(8, 8, 8))
+    assert srt > ok
+    for g in (_group(3, 4, 1), _group(8, 8, 3), _group(4, 4, 32), _group(64, 32, 8), _group(0, 8, 1)):
+        assert L.pt_render_workspace_bytes(64, 64, 1, 2, 2, g) == 0
+    assert L.pt_render_workspace_bytes(0, 64, 1, 2, 0, _group(4, 4, 2)) == 0
+    assert L.pt_render_workspace_bytes(64, 64, 0, 2, 0, _group(4, 4, 2)) == 0
+    assert L.pt_render_workspace_bytes(64, 64, 1, -1, 0, _group(4, 4, 2)) == 0
+    assert L.pt_render_workspace_bytes(64, 64, 1, 0, 0, _group(32, 32, 1024)) > 0
+    assert L.pt_sort_workspace_bytes(0) > 0 and L.pt_sort_workspace_bytes(10 ** 6) >= 8 * 10 ** 6
+    assert L.pt_trace_workspace_bytes() > 0
+
+
+def test_render_rejects_before_touching_device(L):
+    s = scenes.furnace()
+    st, h, keep = _create(L, s)
+    cam = capi.Camera()
+    out = capi.Outputs()
+    # not uploaded
+    st = L.pt_render(h, C.byref(cam), 8, 8, 1, 1, 0, _group(4, 4, 2), 1, None, 0, C.byref(out), None)
+    assert st == capi.PT_EINVAL
+    assert L.pt_render(None, C.byref(cam), 8, 8, 1, 1, 0, _group(4, 4, 2), 1, None, 0, C.byref(out), None) == capi.PT_EINVAL
+    L.pt_scene_free(h)

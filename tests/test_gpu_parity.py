@@ -1,0 +1,221 @@
+"""GPU parity: libpt (through the C ABI) against the CPU oracle, element by
+element on the same seeded inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2310_07182_amd import scenes
+from tests.parity import compare_render
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def api(torch_dev):
+    from paper_2310_07182_amd import api as A
+    return A
+
+
+_cache = {}
+
+
+def both(api, orc, name):
+    if name not in _cache:
+        s = getattr(scenes, name)()
+        _cache[name] = (s, api.Scene(s), orc.OracleScene(s))
+    return _cache[name]
+
+
+def gpu_render(api, sc, w, h, spp, B, mode, tile, k, seed, rmax=None, camera=None):
+    _say(f"[gpu] render {w}x{h} spp={spp} B={B} mode={mode} tile={tile} k={k} seed={seed} rmax={rmax}")
+    r = api.render(sc, w, h, spp, B, mode, tile, k, rmax, seed, camera)
+    import torch
+    torch.cuda.synchronize()
+    return r
+
+
+# ------------------------------------------------------------------ traversal alone
+@pytest.mark.parametrize("name", ["tiny", "mixed_small"])
+def test_trace_parity_random_rays(api, orc, torch_dev, name):
+    s, sc, osc = both(api, orc, name)
+    rng = np.random.default_rng(17)
+    tris = s["tris"].astype(np.float64)
+    lo, hi = tris.reshape(-1, 3).min(0), tris.reshape(-1, 3).max(0)
+    n = 20011
+    o = rng.uniform(lo, hi, (n, 3)).astype(np.float32)
+    d = rng.normal(size=(n, 3))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    ex = rng.integers(-1, len(tris), n).astype(np.int32)
+    rays = orc.pack_rays(o, d, ex)
+    _say(f"[gpu] trace {name} n={n}")
+    prim, t = api.trace(sc, torch_dev.from_numpy(rays).cuda())
+    prim, t = prim.cpu().numpy(), t.cpu().numpy()
+    po, to, t2 = osc.trace(rays)
+    tie = (t2 - to) <= 1e-6 * to
+    assert np.all((prim == po) | tie)
+    same = prim == po
+    assert np.array_equal(t[same].view(np.uint32), to[same].view(np.uint32))
+
+
+def test_trace_empty_and_tiny_batches(api, orc, torch_dev):
+    s, sc, osc = both(api, orc, "tiny")
+    for n in (1, 63, 64, 65):
+        rays = orc.pack_rays(np.full((n, 3), 5.0, np.float32), np.tile(np.array([[0, 0, -1]], np.float32), (n, 1)))
+        _say(f"[gpu] trace tiny n={n}")
+        prim, t = api.trace(sc, torch_dev.from_numpy(rays).cuda())
+        po, to, _ = osc.trace(rays)
+        assert np.array_equal(prim.cpu().numpy(), po)
+
+
+# ------------------------------------------------------------------ whole frame
+@pytest.mark.parametrize("mode,tile,k", [("incoherent", (4, 4), 2), ("sorted", (4, 4), 2), ("reuse", (4, 4), 2),
+                                         ("reuse", (4, 4), 1), ("reuse", (4, 4), 16), ("reuse", (8, 8), 8),
+                                         ("reuse", (8, 8), 64), ("reuse", (2, 2), 4), ("reuse", (1, 1), 1)])
+def test_render_parity_tiny(api, orc, torch_dev, mode, tile, k):
+    s, sc, osc = both(api, orc, "tiny")
+    g = gpu_render(api, sc, 64, 64, 1, 2, mode, tile, k, 2310071820)
+    o = osc.render(64, 64, 1, 2, mode=mode, tile=tile, k=k, seed=2310071820)
+    res = compare_render(g, o, tile, mode)
+    _say("  ", res)
+    assert np.array_equal(g["rays_per_bounce"].cpu().numpy(), o["rays_per_bounce"].astype(np.int64))
+
+
+@pytest.mark.parametrize("mode,tile,k,w,h,spp,B", [
+    ("reuse", (4, 4), 4, 96, 72, 2, 3),
+    ("reuse", (8, 8), 8, 101, 67, 1, 4),
+    ("reuse", (16, 16), 32, 100, 70, 1, 3),
+    ("reuse", (32, 8), 32, 77, 41, 2, 2),
+    ("reuse", (32, 32), 128, 70, 66, 1, 2),
+    ("reuse", (16, 2), 4, 50, 30, 1, 3),
+    ("incoherent", (8, 8), 8, 101, 67, 2, 4),
+    ("sorted", (8, 8), 8, 101, 67, 2, 4),
+    ("sorted", (16, 16), 32, 77, 41, 1, 3),
+])
+def test_render_parity_mixed(api, orc, torch_dev, mode, tile, k, w, h, spp, B):
+    s, sc, osc = both(api, orc, "mixed_small")
+    g = gpu_render(api, sc, w, h, spp, B, mode, tile, k, 99)
+    o = osc.render(w, h, spp, B, mode=mode, tile=tile, k=k, seed=99)
+    res = compare_render(g, o, tile, mode)
+    _say("  ", res)
+
+
+def test_reuse_max_bounce_one(api, orc, torch_dev):
+    s, sc, osc = both(api, orc, "mixed_small")
+    g = gpu_render(api, sc, 64, 48, 1, 3, "reuse", (8, 8), 8, 5, rmax=1)
+    o = osc.render(64, 48, 1, 3, mode="reuse", tile=(8, 8), k=8, seed=5, reuse_max_bounce=1)
+    compare_render(g, o, (8, 8), "reuse")
+
+
+def test_glossy_only_reuse_equals_incoherent_gpu(api, orc, torch_dev):
+    s, sc, osc = both(api, orc, "glossy_only")
+    a = gpu_render(api, sc, 64, 64, 1, 3, "incoherent", (8, 8), 8, 8)
+    a = {k: v.clone() for k, v in a.items()}
+    b = gpu_render(api, sc, 64, 64, 1, 3, "reuse", (8, 8), 8, 8)
+    for key in ("hit_prim", "hit_t", "radiance"):
+        assert torch_dev.equal(a[key], b[key]), key
+
+
+def test_furnace_gpu(api, orc, torch_dev):
+    s, sc, osc = both(api, orc, "furnace")
+    for mode, k in (("incoherent", 1), ("sorted", 1), ("reuse", 4)):
+        g = gpu_render(api, sc, 16, 16, 2, 3, mode, (4, 4), k, 11)
+        rad = g["radiance"].cpu().numpy()
+        assert np.allclose(rad, 1.0 + 0.5 + 0.25 + 0.125, rtol=1e-5)
+
+
+def test_bounces_zero_and_empty_scene(api, orc, torch_dev):
+    s, sc, osc = both(api, orc, "tiny")
+    g = gpu_render(api, sc, 33, 17, 1, 0, "reuse", (4, 4), 2, 3)
+    o = osc.render(33, 17, 1, 0, mode="reuse", tile=(4, 4), k=2, seed=3)
+    compare_render(g, o, (4, 4), "reuse")
+    mats = np.array([(0, (0.5, 0.5, 0.5), 0.0, (0, 0, 0))], dtype=scenes.MATERIAL_DTYPE)
+    empty = dict(tris=np.zeros((0, 3, 3), np.float32), tri_mat=np.zeros(0, np.uint32), mats=mats,
+                 env=np.array([0.25, 0.5, 1.0], np.float32), camera=s["camera"])
+    esc = api.Scene(empty)
+    g = gpu_render(api, esc, 20, 12, 1, 2, "reuse", (4, 4), 2, 3)
+    assert (g["hit_prim"][0] == -1).all() and (g["hit_prim"][1:] == -2).all()
+    assert np.allclose(g["radiance"].cpu().numpy(), [0.25, 0.5, 1.0])
+
+
+# ------------------------------------------------------------------ sorted-mode kernels alone
+def test_ray_keys_parity(api, orc, torch_dev):
+    s, sc, osc = both(api, orc, "mixed_small")
+    lo, hi = osc.bounds()
+    rng = np.random.default_rng(4)
+    n = 3001
+    o = rng.uniform(lo - 1.0, hi + 1.0, (n, 3)).astype(np.float32)
+    d = rng.normal(size=(n, 3))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    rays = orc.pack_rays(o, d)
+    _say(f"[gpu] keys n={n}")
+    keys = api.ray_keys(sc, torch_dev.from_numpy(rays).cuda()).cpu().numpy().view(np.uint32)
+    ref = np.array([orc.ray_key(lo, hi, o[i], d[i]) for i in range(n)], np.uint32)
+    assert np.array_equal(keys, ref)
+
+
+@pytest.mark.parametrize("n", [1, 17, 2048, 2049, 100003, 2100000])
+def test_radix_sort_stable(api, torch_dev, n):
+    rng = np.random.default_rng(n)
+    keys = rng.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    keys[rng.integers(0, n, n // 3)] = 0xFFFFFFFF
+    keys[: n // 4] = keys[: n // 4] & 0x3FF        # many duplicates
+    vals = np.arange(n, dtype=np.uint32)
+    _say(f"[gpu] sort n={n}")
+    k = torch_dev.from_numpy(keys.view(np.int32).copy()).cuda()
+    v = torch_dev.from_numpy(vals.view(np.int32).copy()).cuda()
+    api.sort_pairs(k, v)
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(v.cpu().numpy().view(np.uint32), order.astype(np.uint32))
+    assert np.array_equal(k.cpu().numpy().view(np.uint32), keys[order])
+
+
+def test_workspace_too_small_is_enomem(api, torch_dev):
+    from paper_2310_07182_amd import capi
+    import ctypes as C
+    s = scenes.furnace()
+    sc = api.Scene(s)
+    r = api.Renderer(sc, api.RenderConfig(16, 16, 1, 1, "reuse", (4, 4), 2))
+    cam = api.camera_struct(s["camera"])
+    st = capi.lib().pt_render(sc.handle, C.byref(cam), 16, 16, 1, 1, 2, r.group, 1, r.workspace.data_ptr(),
+                              100, C.byref(r.out), None)
+    assert st == capi.PT_ENOMEM
+
+
+# ------------------------------------------------------------------ full-size workload, sampled tiles
+@pytest.mark.parametrize("mode", ["reuse", "incoherent", "sorted"])
+def test_indoor_full_size_sampled_tiles(api, orc, torch_dev, mode):
+    s, sc, osc = both(api, orc, "indoor")
+    cfg = scenes.CONFIGS["indoor"]
+    w, h, B, tile, k = cfg["w"], cfg["h"], cfg["bounces"], cfg["tile"], cfg["k"]
+    seed = 2310071821
+    g = gpu_render(api, sc, w, h, 1, B, mode, tile, k, seed)
+    ntx, nty = (w + tile[0] - 1) // tile[0], (h + tile[1] - 1) // tile[1]
+    rng = np.random.default_rng(123)
+    pick = rng.choice(ntx * nty, 24, replace=False)
+    pick = np.concatenate([pick, [0, ntx - 1, ntx * nty - 1, ntx * (nty // 2) + ntx // 2]])
+    mask = np.zeros(ntx * nty, np.uint8)
+    mask[pick] = 1
+    o = osc.render(w, h, 1, B, mode=mode, tile=tile, k=k, seed=seed, tile_mask=mask)
+    pm = np.zeros((h, w), bool)
+    for t in np.where(mask)[0]:
+        ty, tx = divmod(int(t), ntx)
+        pm[ty * tile[1]:(ty + 1) * tile[1], tx * tile[0]:(tx + 1) * tile[0]] = True
+    res = compare_render(g, o, tile, mode, pixel_mask=pm)
+    _say("  ", res)
+    # property over the whole image: rays per bounce count the traced rays
+    hp = g["hit_prim"].cpu().numpy()
+    assert np.array_equal(g["rays_per_bounce"].cpu().numpy(), (hp != -2).reshape(B + 1, -1).sum(1))
