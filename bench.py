@@ -103,14 +103,19 @@ def cpu_baseline(scene, cfg, budget_s=15.0, seed=2310071821):
     ntx, nty = (w + tile[0] - 1) // tile[0], (h + tile[1] - 1) // tile[1]
     rng = np.random.default_rng(7)
     order = rng.permutation(ntx * nty)
-    # calibrate on a few tiles, then size the sample to the time budget
+    # calibrate: grow the sample until it takes a tenth of the budget, then size it
     mask = np.zeros(ntx * nty, np.uint8)
-    mask[order[:64]] = 1
-    t0 = time.perf_counter()
-    r = osc.render(w, h, 1, B, mode="reuse", tile=tile, k=k, seed=seed, tile_mask=mask)
-    dt = time.perf_counter() - t0
-    per_tile = dt / 64
-    n = int(min(ntx * nty, max(64, budget_s / max(per_tile, 1e-6))))
+    n = 64
+    while True:
+        mask[:] = 0
+        mask[order[:n]] = 1
+        t0 = time.perf_counter()
+        osc.render(w, h, 1, B, mode="reuse", tile=tile, k=k, seed=seed, tile_mask=mask)
+        dt = time.perf_counter() - t0
+        if dt >= 0.1 * budget_s or n >= ntx * nty:
+            break
+        n = min(ntx * nty, n * 4)
+    n = int(min(ntx * nty, max(64, n * budget_s / max(dt, 1e-6))))
     mask[:] = 0
     mask[order[:n]] = 1
     t0 = time.perf_counter()
@@ -132,6 +137,9 @@ def main():
     ap.add_argument("--modes", default="reuse,incoherent,sorted")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--profile", action="store_true",
+                    help="short fixed sequence for rocprofv3: per mode one warm-up and two frames, "
+                         "then a 1 GiB device copy that calibrates the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {args.gpus}); "
@@ -149,6 +157,21 @@ def main():
     build_s = time.perf_counter() - t0
     log(f"[bench] {args.config}: {scene.ntri} triangles, generated in {gen_s:.1f} s, BVH+upload {build_s:.1f} s, "
         f"info {sc.info()}")
+    if args.profile:
+        for i, mode in enumerate(args.modes.split(",")):
+            r = api.Renderer(sc, api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], mode, tuple(cfg["tile"]),
+                                                  cfg["k"]))
+            for j in range(3):
+                r.render(2310071821 + 10 * i + j)
+                torch.cuda.synchronize()
+            log(f"[profile] {mode}: 3 frames ({cfg['bounces'] + 1} traversal launches each)")
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("[profile] copy of 1 GiB done")
+        return
     results = {}
     for i, mode in enumerate(args.modes.split(",")):
         log(f"[bench] mode {mode}: warmup {args.warmup}, steps {args.steps}")

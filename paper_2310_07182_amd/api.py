@@ -31,11 +31,12 @@ def camera_struct(cam: dict) -> capi.Camera:
     return c
 
 
-def group_struct(tile=(8, 8), k=8, reuse_max_bounce=0xFFFF) -> capi.Group:
+def group_struct(tile=(8, 8), k=8, reuse_max_bounce=0xFFFF, refill=0) -> capi.Group:
     g = capi.Group()
     g.tile_w, g.tile_h = int(tile[0]), int(tile[1])
     g.k = int(k)
     g.reuse_max_bounce = int(min(reuse_max_bounce, 0xFFFF))
+    g.refill = int(refill)
     return g
 
 
@@ -138,6 +139,7 @@ class RenderConfig:
     tile: tuple = (8, 8)
     k: int = 8
     reuse_max_bounce: int | None = None
+    refill: int = 0
 
 
 class Renderer:
@@ -150,7 +152,7 @@ class Renderer:
         dev = scene.device
         B = cfg.bounces
         rmax = B if cfg.reuse_max_bounce is None else cfg.reuse_max_bounce
-        self.group = group_struct(cfg.tile, cfg.k, rmax)
+        self.group = group_struct(cfg.tile, cfg.k, rmax, cfg.refill)
         self.mode = capi.MODES[cfg.mode]
         ws = lib().pt_render_workspace_bytes(cfg.w, cfg.h, cfg.spp, B, self.mode, self.group)
         if ws == 0:
@@ -194,14 +196,14 @@ class Renderer:
 
 
 def render(scene: Scene, w, h, spp=1, bounces=2, mode="incoherent", tile=(8, 8), k=8,
-           reuse_max_bounce=None, seed=1, camera=None, stats=False, rays=False) -> dict:
-    r = Renderer(scene, RenderConfig(w, h, spp, bounces, mode, tuple(tile), k, reuse_max_bounce), stats=stats,
-                 rays=rays)
+           reuse_max_bounce=None, seed=1, camera=None, stats=False, rays=False, refill=0) -> dict:
+    r = Renderer(scene, RenderConfig(w, h, spp, bounces, mode, tuple(tile), k, reuse_max_bounce, refill),
+                 stats=stats, rays=rays)
     r.render(seed, camera)
     return r.results()
 
 
-def trace(scene: Scene, rays: torch.Tensor):
+def trace(scene: Scene, rays: torch.Tensor, refill: int = 0):
     """rays: device float32 [n, 8]; returns (prim int32 [n], t float32 [n])."""
     assert rays.dtype == torch.float32 and rays.is_contiguous() and rays.shape[-1] == 8
     dev = scene.device
@@ -210,7 +212,7 @@ def trace(scene: Scene, rays: torch.Tensor):
     t = torch.empty(n, dtype=torch.float32, device=dev)
     ws = torch.empty(lib().pt_trace_workspace_bytes(), dtype=torch.uint8, device=dev)
     with torch.cuda.device(dev):
-        check(lib().pt_trace(scene.handle, rays.data_ptr(), n, prim.data_ptr(), t.data_ptr(), ws.data_ptr(),
+        check(lib().pt_trace(scene.handle, rays.data_ptr(), n, int(refill), prim.data_ptr(), t.data_ptr(), ws.data_ptr(),
                              ws.numel(), _stream_handle(dev)))
     return prim, t
 

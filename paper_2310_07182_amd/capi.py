@@ -35,7 +35,7 @@ class Camera(C.Structure):
 
 class Group(C.Structure):
     _fields_ = [("tile_w", C.c_uint16), ("tile_h", C.c_uint16), ("k", C.c_uint16),
-                ("reuse_max_bounce", C.c_uint16)]
+                ("reuse_max_bounce", C.c_uint16), ("refill", C.c_uint16), ("reserved", C.c_uint16)]
 
 
 class SceneDesc(C.Structure):
@@ -67,7 +67,7 @@ PROTOTYPES = {
     "pt_render": (_st, [_vp, C.POINTER(Camera), _i32, _i32, _i32, _i32, _i32, Group, C.c_uint64, _vp, _sz,
                         C.POINTER(Outputs), _vp]),
     "pt_trace_workspace_bytes": (_sz, []),
-    "pt_trace": (_st, [_vp, _vp, _u32, _vp, _vp, _vp, _sz, _vp]),
+    "pt_trace": (_st, [_vp, _vp, _u32, _i32, _vp, _vp, _vp, _sz, _vp]),
     "pt_ray_keys": (_st, [_vp, _vp, _u32, _vp, _vp]),
     "pt_sort_workspace_bytes": (_sz, [_u32]),
     "pt_sort_pairs": (_st, [_vp, _vp, _u32, _vp, _sz, _vp]),

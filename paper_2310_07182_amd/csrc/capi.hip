@@ -58,6 +58,8 @@ pt_status hip_fail(hipError_t e, const char* what) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+constexpr int kDefaultRefill = 32;
+
 bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 // ---- host side of the arithmetic contract: camera basis
@@ -79,6 +81,7 @@ pt_status check_group(pt_group g, int bounces) {
     const int wh = (int)g.tile_w * (int)g.tile_h;
     if (wh > 1024) return fail(PT_EINVAL, "tile_w * tile_h must be <= 1024 (got %d)", wh);
     if ((int)g.k > wh) return fail(PT_EINVAL, "k (%d) must divide tile_w * tile_h (%d)", g.k, wh);
+    if (g.refill > 64) return fail(PT_EINVAL, "refill must be in [0, 64] (got %d)", g.refill);
     return PT_OK;
 }
 
@@ -122,7 +125,7 @@ Frame make_frame(int w, int h, int spp, int B, pt_mode mode, pt_group g, uint64_
 }
 
 struct Layout {
-    size_t q0, q1, state, work, nlive, keys, vals, qs, sortws, ovf, total;
+    size_t q0, q1, state, work, partial, keys, vals, qs, sortws, ovf, total;
 };
 
 Layout layout(const Frame& f) {
@@ -138,8 +141,8 @@ Layout layout(const Frame& f) {
     o = align256(o + qb);
     L.work = o;
     o = align256(o + launches * 4);
-    L.nlive = o;
-    o = align256(o + launches * 4);
+    L.partial = o;
+    o = align256(o + launches * pt::kMaxTraceBlocks * 4);
     if (f.mode == PT_MODE_SORTED) {
         L.keys = o;
         o = align256(o + (size_t)f.nslots * 4);
@@ -369,6 +372,7 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
     if (dev != scene->device) return fail(PT_EINVAL, "scene was uploaded on device %d, current device is %d", scene->device, dev);
 
     Frame f = make_frame(w, h, spp, B, mode, g, seed);
+    if (mode == PT_MODE_SORTED && f.nslots > (1u << 27)) return fail(PT_EINVAL, "sorted mode supports at most 2^27 rays per bounce");
     const Layout L = layout(f);
     if (ws_bytes < L.total) return fail(PT_ENOMEM, "workspace too small: %zu < %zu", ws_bytes, L.total);
     {
@@ -394,19 +398,18 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
     char* ws = (char*)workspace;
     float4* q[2] = {(float4*)(ws + L.q0), (float4*)(ws + L.q1)};
     float4* state = (float4*)(ws + L.state);
+    uint32_t* partial = (uint32_t*)(ws + L.partial);
     uint32_t* work = (uint32_t*)(ws + L.work);
-    uint32_t* nlive = (uint32_t*)(ws + L.nlive);
     int32_t* ovf = (int32_t*)(ws + L.ovf);
     const size_t launches = (size_t)(B + 1) * (size_t)spp;
     hipError_t e;
     {
         TimerScope ts(out->timer, st, 6, -1);
         e = pt::launch_zero(work, launches, st);
-        if (e == hipSuccess) e = pt::launch_zero(nlive, launches, st);
-        if (e == hipSuccess && out->ray_count) e = pt::launch_zero(out->ray_count, launches, st);
         if (e == hipSuccess && out->stats) e = pt::launch_zero((uint32_t*)out->stats, (size_t)(B + 1) * 4, st);
     }
     if (e != hipSuccess) return hip_fail(e, "launch (zero)");
+    const int grid = pt::trace_grid_blocks();
     const size_t plane = (size_t)w * (size_t)h;
     for (int s = 0; s < spp; ++s) {
         {
@@ -417,15 +420,14 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
         for (int b = 0; b <= B; ++b) {
             const size_t li = (size_t)b * spp + s;
             const float4* tq = q[b & 1];
-            uint32_t n = f.nslots;
-            const uint32_t* ndev = nullptr;
+            const uint32_t n = f.nslots;
             if (mode == PT_MODE_SORTED && b >= 1) {
                 uint32_t* keys = (uint32_t*)(ws + L.keys);
                 uint32_t* vals = (uint32_t*)(ws + L.vals);
                 float4* qs = (float4*)(ws + L.qs);
                 {
                     TimerScope ts(out->timer, st, 3, b);
-                    e = pt::launch_keys(scene->dev, q[b & 1], f.nslots, keys, vals, nlive + li, st);
+                    e = pt::launch_keys(scene->dev, q[b & 1], f.nslots, keys, vals, st);
                 }
                 if (e != hipSuccess) return hip_fail(e, "launch (keys)");
                 {
@@ -438,20 +440,19 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
                     e = pt::launch_gather(q[b & 1], vals, f.nslots, qs, st);
                 }
                 if (e != hipSuccess) return hip_fail(e, "launch (gather)");
-                tq = qs;
-                ndev = nlive + li;
+                tq = qs;   // dead rays (key 0xFFFFFFFF) sort last and are skipped by the trace
             }
             pt::TraceArgs ta{};
             ta.rays = tq;
             ta.n = n;
-            ta.n_dev = ndev;
             ta.work = work + li;
             ta.out_prim = out->hit_prim + li * plane;
             ta.out_t = out->hit_t + li * plane;
-            ta.ray_count = out->ray_count ? out->ray_count + li : nullptr;
+            ta.partial = out->ray_count ? partial + li * pt::kMaxTraceBlocks : nullptr;
             ta.stats = out->stats ? (unsigned long long*)(out->stats + 2 * (size_t)b) : nullptr;
             ta.ovf = ovf;
             ta.by_pixel = 1;
+            ta.refill = g.refill ? g.refill : kDefaultRefill;
             {
                 TimerScope ts(out->timer, st, 0, b);
                 e = pt::launch_trace(scene->dev, ta, out->stats != nullptr, st);
@@ -465,32 +466,37 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
             if (e != hipSuccess) return hip_fail(e, "launch (shade)");
         }
     }
+    if (out->ray_count) {
+        TimerScope ts(out->timer, st, 6, -1);
+        e = pt::launch_count_finalize(partial, pt::kMaxTraceBlocks, grid, (int)launches, out->ray_count, st);
+        if (e != hipSuccess) return hip_fail(e, "launch (count)");
+    }
     return PT_OK;
 }
 
 size_t pt_trace_workspace_bytes(void) {
-    return align256(256) + align256((size_t)pt::kMaxTraceBlocks * pt::kTraceBlock * pt::kStackOvf * 4);
+    return 256 + align256((size_t)pt::kMaxTraceBlocks * pt::kTraceBlock * pt::kStackOvf * 4);
 }
 
-pt_status pt_trace(pt_scene scene, const float* rays, uint32_t n, int32_t* prim, float* t, void* workspace,
-                   size_t ws_bytes, void* stream) {
+pt_status pt_trace(pt_scene scene, const float* rays, uint32_t n, int refill, int32_t* prim, float* t,
+                   void* workspace, size_t ws_bytes, void* stream) {
+    if (refill < 0 || refill > 64) return fail(PT_EINVAL, "refill must be in [0, 64] (got %d)", refill);
     if (!scene || (n > 0 && (!rays || !prim || !t)) || !workspace) return fail(PT_EINVAL, "null argument");
     if (!scene->uploaded) return fail(PT_EINVAL, "scene not uploaded");
     if (ws_bytes < pt_trace_workspace_bytes()) return fail(PT_ENOMEM, "workspace too small");
     if (n == 0) return PT_OK;
     hipStream_t st = (hipStream_t)stream;
-    char* ws = (char*)workspace;
-    uint32_t* work = (uint32_t*)ws;
-    hipError_t e = pt::launch_zero(work, 1, st);
-    if (e != hipSuccess) return hip_fail(e, "launch (zero)");
     pt::TraceArgs ta{};
     ta.rays = (const float4*)rays;
     ta.n = n;
-    ta.work = work;
+    ta.work = (uint32_t*)workspace;
     ta.out_prim = prim;
     ta.out_t = t;
-    ta.ovf = (int32_t*)(ws + align256(256));
+    ta.ovf = (int32_t*)((char*)workspace + 256);
     ta.by_pixel = 0;
+    ta.refill = refill ? refill : kDefaultRefill;
+    hipError_t e = pt::launch_zero(ta.work, 1, st);
+    if (e != hipSuccess) return hip_fail(e, "launch (zero)");
     e = pt::launch_trace(scene->dev, ta, false, st);
     if (e != hipSuccess) return hip_fail(e, "launch (trace)");
     return PT_OK;
@@ -500,7 +506,7 @@ pt_status pt_ray_keys(pt_scene scene, const float* rays, uint32_t n, uint32_t* k
     if (!scene || (n > 0 && (!rays || !keys))) return fail(PT_EINVAL, "null argument");
     if (!scene->uploaded) return fail(PT_EINVAL, "scene not uploaded");
     if (n == 0) return PT_OK;
-    hipError_t e = pt::launch_keys(scene->dev, (const float4*)rays, n, keys, nullptr, nullptr, (hipStream_t)stream);
+    hipError_t e = pt::launch_keys(scene->dev, (const float4*)rays, n, keys, nullptr, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launch (keys)");
     return PT_OK;
 }
@@ -509,6 +515,7 @@ size_t pt_sort_workspace_bytes(uint32_t n) { return pt::sort_workspace_bytes(n);
 
 pt_status pt_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t n, void* workspace, size_t ws_bytes, void* stream) {
     if (n > 0 && (!keys || !vals || !workspace)) return fail(PT_EINVAL, "null argument");
+    if (n > (1u << 27)) return fail(PT_EINVAL, "at most 2^27 pairs (got %u)", n);
     if (ws_bytes < pt::sort_workspace_bytes(n)) return fail(PT_ENOMEM, "workspace too small");
     hipError_t e = pt::radix_sort_pairs(keys, vals, n, workspace, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launch (sort)");

@@ -43,17 +43,17 @@ constexpr int kMaxTraceBlocks = 256 * 24;  // cap of the persistent grid (bounds
 struct TraceArgs {
     const float4* rays;
     uint32_t n;
-    const uint32_t* n_dev;     // optional device-side count (sorted mode: live rays)
-    uint32_t* work;            // work counter (zeroed before launch)
     int32_t* out_prim;         // indexed by pixel (by_pixel) or by ray
     float* out_t;
-    uint32_t* ray_count;       // optional
+    uint32_t* work;            // batch counter, zero at launch
+    uint32_t* partial;         // optional [grid] per-workgroup count of traced rays
     unsigned long long* stats; // optional [2]
     int32_t* ovf;              // [kStackOvf][grid threads]
     int by_pixel;
+    int refill;                // a wave fetches new rays once this many lanes are idle (1..64)
 };
 
-int trace_grid_blocks();   // persistent grid size (workgroups), <= kMaxTraceBlocks
+int trace_grid_blocks();   // persistent grid size (workgroups): a multiple of 8, <= kMaxTraceBlocks
 hipError_t launch_trace(const DevScene& sc, const TraceArgs& a, bool stats, hipStream_t st);
 hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t st);
 hipError_t launch_raygen(const Frame& f, int s, float4* q, float4* state, float4* rays_out, hipStream_t st);
@@ -61,7 +61,10 @@ hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const 
                         float4* state, int32_t* hit_prim, float* hit_t, float* radiance, float4* rays_out,
                         hipStream_t st);
 hipError_t launch_keys(const DevScene& sc, const float4* q, uint32_t n, uint32_t* keys, uint32_t* vals,
-                       uint32_t* n_live, hipStream_t st);
+                       hipStream_t st);
+// ray_count[i] = sum of partial[i * stride + j] for j < parts, i < launches
+hipError_t launch_count_finalize(const uint32_t* partial, int stride, int parts, int launches, uint32_t* ray_count,
+                                 hipStream_t st);
 hipError_t launch_gather(const float4* q, const uint32_t* idx, uint32_t n, float4* out, hipStream_t st);
 
 // stable LSD radix sort (4 passes of 8 bits)

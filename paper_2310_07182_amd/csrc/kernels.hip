@@ -243,116 +243,171 @@ __device__ __forceinline__ float slab(float lx, float hx, float ly, float hy, fl
 
 constexpr int32_t kDone = INT32_MIN;   // = kEmpty: never a node or leaf code
 
+// Closest-hit traversal, one ray per lane, in the structure of Aila & Laine
+// ("Understanding the efficiency of ray traversal on GPUs", HPG 2009):
+//  * while-while: a lane walks inner nodes until every active lane of the wave
+//    holds a leaf (a lane that reaches a leaf early postpones it and keeps walking
+//    inner nodes), then the wave tests leaves together, so the inner-node and
+//    triangle code do not alternate inside one divergent loop;
+//  * persistent lanes with refill: a lane whose ray is finished takes a new ray
+//    from the queue once enough lanes are idle, so a wave is not held by its
+//    slowest ray.
+// Culling only ever prunes (conservative box test), and every leaf that is
+// reached is tested, so the result is the exact (t, prim id) minimum.
+constexpr int32_t kNoLeaf = 0;   // never a leaf code (leaf codes are negative)
+
 template <bool STATS>
 __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a, uint32_t gthreads) {
     __shared__ int32_t stk[kStackLds][kTraceBlock];
     const int lane = threadIdx.x;
     const uint32_t gtid = blockIdx.x * kTraceBlock + lane;
-    uint32_t n = a.n;
-    if (a.n_dev) n = min(n, *a.n_dev);
+    const uint32_t n = a.n;
+    const unsigned long long lt = (1ull << lane) - 1ull;
     unsigned long long nv = 0, nt = 0;
+    uint32_t traced = 0;
+    bool have = false;
+    bool exhausted = false;   // wave-uniform: the queue is used up
+    uint32_t oi = 0;
+    V3 o = mk3(0.f, 0.f, 0.f), inv = o;
+    RayPre rp{};
+    int32_t excl = -1, best_p = INT32_MAX, node = kDone, leaf = kNoLeaf;
+    float best_t = INFINITY, tcull = INFINITY;
+    int sp = 0, novf = 0;
     for (;;) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(a.work, (uint32_t)kTraceBlock);
-        base = __shfl(base, 0);
-        if (base >= n) break;
-        const uint32_t i = base + lane;
-        bool valid = i < n;
-        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
-        if (valid) {
-            r0 = a.rays[2 * (size_t)i];
-            r1 = a.rays[2 * (size_t)i + 1];
-        }
-        const uint32_t pix = __float_as_uint(r1.w);
-        if (a.by_pixel) valid = valid && pix != kNoRay;
-        float best_t = INFINITY;
-        int32_t best_p = INT32_MAX;
-        if (valid) {
-            const V3 o = xyz(r0), d = xyz(r1);
-            const int32_t excl = __float_as_int(r0.w);
-            const V3 inv = mk3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
-            const RayPre rp = prepare(o, d);
-            int sp = 0, novf = 0;
-            int32_t cur = 0;   // root node
-            while (cur != kDone) {
-                if (cur >= 0) {
-                    const float4* nd = sc.nodes + 4 * (size_t)cur;
-                    const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
-                    if (STATS) ++nv;
-                    const float tcull = best_t * kCullScale;
-                    const int32_t c0 = __float_as_int(n3.x), c1 = __float_as_int(n3.y);
-                    bool h0, h1;
-                    const float t0 = slab(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, o, inv, tcull, h0);
-                    const float t1 = slab(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, o, inv, tcull, h1);
-                    h0 = h0 && c0 != kEmpty;
-                    h1 = h1 && c1 != kEmpty;
-                    if (h0 && h1) {
-                        const bool swp = t1 < t0;
-                        const int32_t far = swp ? c0 : c1;
-                        cur = swp ? c1 : c0;
-                        if (sp == kStackLds) {
-                            // the BVH depth bound keeps the stack within kStackLds + kStackOvf
-                            // entries; the check keeps every access in bounds regardless
-                            if (novf + kStackLds / 2 > kStackOvf) {
-                                cur = kDone;
-                                continue;
-                            }
-                            // spill the lower half of the LDS stack to this lane's overflow column
-                            for (int e = 0; e < kStackLds / 2; ++e)
-                                a.ovf[(size_t)(novf + e) * gthreads + gtid] = stk[e][lane];
-                            for (int e = 0; e < kStackLds / 2; ++e) stk[e][lane] = stk[e + kStackLds / 2][lane];
-                            novf += kStackLds / 2;
-                            sp = kStackLds / 2;
-                        }
-                        stk[sp++][lane] = far;
-                        continue;
-                    }
-                    if (h0) {
-                        cur = c0;
-                        continue;
-                    }
-                    if (h1) {
-                        cur = c1;
-                        continue;
-                    }
-                } else {
-                    const uint32_t code = ~(uint32_t)cur;
-                    const uint32_t first = code >> 3, cnt = (code & 7u) + 1u;
-                    for (uint32_t k = 0; k < cnt; ++k) {
-                        const float4* tp = sc.btris + 3 * (size_t)(first + k);
-                        const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
-                        const int32_t pid = __float_as_int(p0.w);
-                        if (pid == excl) continue;
-                        if (STATS) ++nt;
-                        float t;
-                        if (tri_test(rp, p0, p1, p2, t) && (t < best_t || (t == best_t && pid < best_p))) {
-                            best_t = t;
-                            best_p = pid;
-                        }
+        // ---- refill idle lanes with the next rays of the queue
+        const unsigned long long idle = __ballot(!have);
+        if (!exhausted && idle != 0 && (__popcll(idle) >= a.refill || idle == ~0ull)) {
+            const uint32_t need = (uint32_t)__popcll(idle);
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(a.work, need);
+            base = __shfl(base, 0);
+            if (base + need >= n) exhausted = true;
+            if (!have) {
+                const uint32_t i = base + (uint32_t)__popcll(idle & lt);
+                if (i < n) {
+                    const float4 r0 = a.rays[2 * (size_t)i], r1 = a.rays[2 * (size_t)i + 1];
+                    const uint32_t pix = __float_as_uint(r1.w);
+                    if (!a.by_pixel || pix != kNoRay) {
+                        o = xyz(r0);
+                        const V3 d = xyz(r1);
+                        excl = __float_as_int(r0.w);
+                        inv = mk3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
+                        rp = prepare(o, d);
+                        best_t = INFINITY;
+                        tcull = INFINITY;
+                        best_p = INT32_MAX;
+                        sp = 0;
+                        novf = 0;
+                        node = 0;
+                        leaf = kNoLeaf;
+                        oi = a.by_pixel ? pix : i;
+                        have = true;
                     }
                 }
-                // pop
-                if (sp == 0) {
-                    if (novf == 0) {
-                        cur = kDone;
-                        continue;
-                    }
-                    const int m = novf < kStackLds / 2 ? novf : kStackLds / 2;
-                    for (int e = 0; e < m; ++e) stk[e][lane] = a.ovf[(size_t)(novf - m + e) * gthreads + gtid];
-                    novf -= m;
-                    sp = m;
-                }
-                cur = stk[--sp][lane];
             }
-            const uint32_t oi = a.by_pixel ? pix : i;
-            a.out_prim[oi] = best_p == INT32_MAX ? -1 : best_p;
-            a.out_t[oi] = best_t;
         }
-        if (a.ray_count) {
-            const unsigned long long m = __ballot(valid);
-            if (lane == 0 && m) atomicAdd(a.ray_count, (uint32_t)__popcll(m));
+        if (__ballot(have) == 0) {
+            if (exhausted) break;
+            continue;
+        }
+        if (!have) continue;
+        for (;;) {
+            // ---- inner nodes; a leaf that is reached is postponed while the slot is free
+            while (node >= 0) {
+                const float4* nd = sc.nodes + 4 * (size_t)node;
+                const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
+                if (STATS) ++nv;
+                const int32_t c0 = __float_as_int(n3.x), c1 = __float_as_int(n3.y);
+                bool h0, h1;
+                const float t0 = slab(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, o, inv, tcull, h0);
+                const float t1 = slab(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, o, inv, tcull, h1);
+                h0 = h0 && c0 != kEmpty;
+                h1 = h1 && c1 != kEmpty;
+                if (h0 && h1) {
+                    const bool swp = t1 < t0;
+                    const int32_t far = swp ? c0 : c1;
+                    node = swp ? c1 : c0;
+                    if (sp == kStackLds) {
+                        // the BVH depth bound keeps the stack within kStackLds + kStackOvf
+                        // entries; the check keeps every access in bounds regardless
+                        if (novf + kStackLds / 2 > kStackOvf) {
+                            node = kDone;
+                            leaf = kNoLeaf;
+                            break;
+                        }
+                        // spill the lower half of the LDS stack to this lane's overflow column
+                        for (int e = 0; e < kStackLds / 2; ++e)
+                            a.ovf[(size_t)(novf + e) * gthreads + gtid] = stk[e][lane];
+                        for (int e = 0; e < kStackLds / 2; ++e) stk[e][lane] = stk[e + kStackLds / 2][lane];
+                        novf += kStackLds / 2;
+                        sp = kStackLds / 2;
+                    }
+                    stk[sp++][lane] = far;
+                } else if (h0) {
+                    node = c0;
+                } else if (h1) {
+                    node = c1;
+                } else {
+                    node = kDone;   // pop below
+                }
+                if (node == kDone || (node < 0 && leaf == kNoLeaf)) {
+                    if (node != kDone) leaf = node;
+                    // pop
+                    if (sp == 0 && novf > 0) {
+                        const int m = novf < kStackLds / 2 ? novf : kStackLds / 2;
+                        for (int e = 0; e < m; ++e) stk[e][lane] = a.ovf[(size_t)(novf - m + e) * gthreads + gtid];
+                        novf -= m;
+                        sp = m;
+                    }
+                    node = sp > 0 ? stk[--sp][lane] : kDone;
+                }
+                // every active lane holds a leaf: test them together
+                if (__ballot(leaf == kNoLeaf) == 0) break;
+            }
+            // ---- leaves: the postponed one, then the next node while it is a leaf
+            for (;;) {
+                if (leaf == kNoLeaf) {
+                    if (node >= 0 || node == kDone) break;
+                    leaf = node;
+                    if (sp == 0 && novf > 0) {
+                        const int m = novf < kStackLds / 2 ? novf : kStackLds / 2;
+                        for (int e = 0; e < m; ++e) stk[e][lane] = a.ovf[(size_t)(novf - m + e) * gthreads + gtid];
+                        novf -= m;
+                        sp = m;
+                    }
+                    node = sp > 0 ? stk[--sp][lane] : kDone;
+                }
+                const uint32_t code = ~(uint32_t)leaf;
+                const uint32_t first = code >> 3, cnt = (code & 7u) + 1u;
+                for (uint32_t k = 0; k < cnt; ++k) {
+                    const float4* tp = sc.btris + 3 * (size_t)(first + k);
+                    const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
+                    const int32_t pid = __float_as_int(p0.w);
+                    if (STATS) ++nt;
+                    float t;
+                    if (pid != excl && tri_test(rp, p0, p1, p2, t) && (t < best_t || (t == best_t && pid < best_p))) {
+                        best_t = t;
+                        best_p = pid;
+                        tcull = t * kCullScale;
+                    }
+                }
+                leaf = kNoLeaf;
+            }
+            if (node == kDone) {
+                a.out_prim[oi] = best_p == INT32_MAX ? -1 : best_p;
+                a.out_t[oi] = best_t;
+                ++traced;
+                have = false;
+                break;
+            }
+            // too few lanes still busy: leave to refill the idle ones
+            if (!exhausted && __popcll(__ballot(true)) <= 64 - a.refill) break;
         }
     }
+    // per-workgroup count of traced rays (no atomics on a shared counter)
+    unsigned int tsum = traced;
+    for (int off = 32; off > 0; off >>= 1) tsum += __shfl_down(tsum, off);
+    if (a.partial && lane == 0) a.partial[blockIdx.x] = tsum;
     if (STATS) {
         for (int off = 32; off > 0; off >>= 1) {
             nv += __shfl_down(nv, off);
@@ -595,12 +650,11 @@ __device__ __forceinline__ uint32_t q5(float x, float lo, float ext) {
 }
 
 __global__ __launch_bounds__(256) void k_keys(DevScene sc, const float4* q, uint32_t n, uint32_t* keys,
-                                              uint32_t* vals, uint32_t* n_live) {
+                                              uint32_t* vals) {
     const uint32_t j = blockIdx.x * 256u + threadIdx.x;
-    bool live = false;
     if (j < n) {
         const float4 r0 = q[2 * (size_t)j], r1 = q[2 * (size_t)j + 1];
-        live = __float_as_uint(r1.w) != kNoRay;
+        const bool live = __float_as_uint(r1.w) != kNoRay;
         uint32_t key = 0xFFFFFFFFu;
         if (live) {
             const float ex = sc.hi[0] - sc.lo[0], ey = sc.hi[1] - sc.lo[1], ez = sc.hi[2] - sc.lo[2];
@@ -620,10 +674,21 @@ __global__ __launch_bounds__(256) void k_keys(DevScene sc, const float4* q, uint
         keys[j] = key;
         if (vals) vals[j] = j;
     }
-    if (n_live) {
-        const unsigned long long m = __ballot(live);
-        if ((threadIdx.x & 63) == 0 && m) atomicAdd(n_live, (uint32_t)__popcll(m));
+}
+
+__global__ __launch_bounds__(256) void k_count_finalize(const uint32_t* partial, int stride, int parts,
+                                                        uint32_t* ray_count) {
+    __shared__ uint32_t red[256];
+    uint32_t sum = 0;
+    const uint32_t* p = partial + (size_t)blockIdx.x * (size_t)stride;
+    for (int j = threadIdx.x; j < parts; j += 256) sum += p[j];
+    red[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) ray_count[blockIdx.x] = red[0];
 }
 
 __global__ __launch_bounds__(256) void k_gather(const float4* q, const uint32_t* idx, uint32_t n, float4* out) {
@@ -659,27 +724,85 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* keys
     hist[(size_t)tid * nblocks + blockIdx.x] = h[tid];
 }
 
-// exclusive scan of m counts, one workgroup of 1024 threads
-__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* hist, uint32_t m) {
-    __shared__ uint32_t part[1024];
-    const int tid = threadIdx.x;
-    const uint32_t seg = (m + 1023u) / 1024u;
-    const uint32_t b0 = (uint32_t)tid * seg, b1 = min(m, b0 + seg);
-    uint32_t sum = 0;
-    for (uint32_t j = b0; j < b1; ++j) sum += hist[j];
-    part[tid] = sum;
+// Exclusive scan of m counts in three steps: chunk sums, scan of the chunk sums
+// (one workgroup), scan of each chunk plus its offset.  1024 threads x 4 items.
+constexpr uint32_t kScanChunk = 4096;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = tid >= off ? part[tid - off] : 0u;
-        __syncthreads();
-        part[tid] += v;
+    if (wave == 0) {
+        uint32_t w = lane < 16 ? wsum[lane] : 0u;
+        uint32_t z = w;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const uint32_t y = __shfl_up(z, off);
+            if (lane >= off) z += y;
+        }
+        if (lane < 16) wsum[16 + lane] = z - w;   // exclusive prefix of wave sums
+        if (lane == 15) wsum[32] = z;
+    }
+    __syncthreads();
+    total = wsum[32];
+    const uint32_t r = wsum[16 + wave] + x - v;
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_reduce(const uint32_t* in, uint32_t m, uint32_t* sums) {
+    __shared__ uint32_t red[1024];
+    const uint32_t base = blockIdx.x * kScanChunk;
+    uint32_t v = 0;
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t i = base + (uint32_t)j * 1024u + threadIdx.x;
+        if (i < m) v += in[i];
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
-    uint32_t run = part[tid] - sum;
-    for (uint32_t j = b0; j < b1; ++j) {
-        const uint32_t v = hist[j];
-        hist[j] = run;
-        run += v;
+    if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+// exclusive scan of the chunk sums in place (nchunks <= 4096)
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* sums, uint32_t nchunks) {
+    __shared__ uint32_t wsum[40];
+    const uint32_t i0 = threadIdx.x * 4u;
+    uint32_t v[4], t = 0;
+    for (int j = 0; j < 4; ++j) {
+        v[j] = (i0 + j < nchunks) ? sums[i0 + j] : 0u;
+        t += v[j];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(t, wsum, total);
+    for (int j = 0; j < 4; ++j) {
+        if (i0 + j < nchunks) sums[i0 + j] = run;
+        run += v[j];
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_down(uint32_t* data, uint32_t m, const uint32_t* sums) {
+    __shared__ uint32_t wsum[40];
+    const uint32_t i0 = blockIdx.x * kScanChunk + threadIdx.x * 4u;
+    uint32_t v[4], t = 0;
+    for (int j = 0; j < 4; ++j) {
+        v[j] = (i0 + j < m) ? data[i0 + j] : 0u;
+        t += v[j];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(t, wsum, total) + sums[blockIdx.x];
+    for (int j = 0; j < 4; ++j) {
+        if (i0 + j < m) data[i0 + j] = run;
+        run += v[j];
     }
 }
 
@@ -740,6 +863,8 @@ int trace_grid_blocks() {
             per = 8;
         int g = cus * per;
         if (g > kMaxTraceBlocks) g = kMaxTraceBlocks;
+        g &= ~7;   // a multiple of the 8 XCDs
+        if (g < 8) g = 8;
         g_trace_blocks[dev] = g;
     }
     return g_trace_blocks[dev];
@@ -748,6 +873,7 @@ int trace_grid_blocks() {
 hipError_t launch_trace(const DevScene& sc, const TraceArgs& a, bool stats, hipStream_t st) {
     const int g = trace_grid_blocks();
     const uint32_t gthreads = (uint32_t)g * kTraceBlock;
+    if (a.refill < 1 || a.refill > 64) return hipErrorInvalidValue;
     if (stats)
         hipLaunchKernelGGL(k_trace<true>, dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads);
     else
@@ -778,9 +904,16 @@ hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const 
 }
 
 hipError_t launch_keys(const DevScene& sc, const float4* q, uint32_t n, uint32_t* keys, uint32_t* vals,
-                       uint32_t* n_live, hipStream_t st) {
+                       hipStream_t st) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_keys, dim3((n + 255) / 256), dim3(256), 0, st, sc, q, n, keys, vals, n_live);
+    hipLaunchKernelGGL(k_keys, dim3((n + 255) / 256), dim3(256), 0, st, sc, q, n, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_finalize(const uint32_t* partial, int stride, int parts, int launches, uint32_t* ray_count,
+                                 hipStream_t st) {
+    if (launches <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_finalize, dim3(launches), dim3(256), 0, st, partial, stride, parts, ray_count);
     return hipGetLastError();
 }
 
@@ -792,7 +925,9 @@ hipError_t launch_gather(const float4* q, const uint32_t* idx, uint32_t n, float
 
 size_t sort_workspace_bytes(uint32_t n) {
     const size_t nb = (n + kSortTile - 1) / kSortTile;
-    return 2 * (size_t)n * sizeof(uint32_t) + 256 * nb * sizeof(uint32_t) + 256;
+    const size_t m = 256 * nb;
+    const size_t chunks = (m + kScanChunk - 1) / kScanChunk;
+    return 2 * (size_t)n * sizeof(uint32_t) + m * sizeof(uint32_t) + chunks * sizeof(uint32_t) + 256;
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t n, void* ws, hipStream_t st) {
@@ -801,6 +936,10 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t n, void* ws
     uint32_t* kalt = (uint32_t*)ws;
     uint32_t* valt = kalt + n;
     uint32_t* hist = valt + n;
+    const uint32_t m = 256u * nb;
+    const uint32_t chunks = (m + kScanChunk - 1) / kScanChunk;
+    uint32_t* csum = hist + m;
+    if (chunks > 4096u) return hipErrorInvalidValue;   // n > 2^32 / 64: outside the supported range
     uint32_t* kin = keys;
     uint32_t* vin = vals;
     uint32_t* kout = kalt;
@@ -808,7 +947,9 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t n, void* ws
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
         hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(kSortThreads), 0, st, kin, n, shift, hist, nb);
-        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, st, hist, 256u * nb);
+        hipLaunchKernelGGL(k_scan_reduce, dim3(chunks), dim3(1024), 0, st, hist, m, csum);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, csum, chunks);
+        hipLaunchKernelGGL(k_scan_down, dim3(chunks), dim3(1024), 0, st, hist, m, csum);
         hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, n, shift, hist, nb);
         uint32_t* tk = kin;
         kin = kout;

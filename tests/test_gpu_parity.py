@@ -40,17 +40,18 @@ def both(api, orc, name):
     return _cache[name]
 
 
-def gpu_render(api, sc, w, h, spp, B, mode, tile, k, seed, rmax=None, camera=None):
-    _say(f"[gpu] render {w}x{h} spp={spp} B={B} mode={mode} tile={tile} k={k} seed={seed} rmax={rmax}")
-    r = api.render(sc, w, h, spp, B, mode, tile, k, rmax, seed, camera)
+def gpu_render(api, sc, w, h, spp, B, mode, tile, k, seed, rmax=None, camera=None, refill=0):
+    _say(f"[gpu] render {w}x{h} spp={spp} B={B} mode={mode} tile={tile} k={k} seed={seed} rmax={rmax} refill={refill}")
+    r = api.render(sc, w, h, spp, B, mode, tile, k, rmax, seed, camera, refill=refill)
     import torch
     torch.cuda.synchronize()
     return r
 
 
 # ------------------------------------------------------------------ traversal alone
+@pytest.mark.parametrize("refill", [0, 1, 48, 64])
 @pytest.mark.parametrize("name", ["tiny", "mixed_small"])
-def test_trace_parity_random_rays(api, orc, torch_dev, name):
+def test_trace_parity_random_rays(api, orc, torch_dev, name, refill):
     s, sc, osc = both(api, orc, name)
     rng = np.random.default_rng(17)
     tris = s["tris"].astype(np.float64)
@@ -61,8 +62,8 @@ def test_trace_parity_random_rays(api, orc, torch_dev, name):
     d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
     ex = rng.integers(-1, len(tris), n).astype(np.int32)
     rays = orc.pack_rays(o, d, ex)
-    _say(f"[gpu] trace {name} n={n}")
-    prim, t = api.trace(sc, torch_dev.from_numpy(rays).cuda())
+    _say(f"[gpu] trace {name} n={n} refill={refill}")
+    prim, t = api.trace(sc, torch_dev.from_numpy(rays).cuda(), refill)
     prim, t = prim.cpu().numpy(), t.cpu().numpy()
     po, to, t2 = osc.trace(rays)
     tie = (t2 - to) <= 1e-6 * to
@@ -111,6 +112,15 @@ def test_render_parity_mixed(api, orc, torch_dev, mode, tile, k, w, h, spp, B):
     o = osc.render(w, h, spp, B, mode=mode, tile=tile, k=k, seed=99)
     res = compare_render(g, o, tile, mode)
     _say("  ", res)
+
+
+@pytest.mark.parametrize("mode,refill", [("incoherent", 1), ("sorted", 64), ("reuse", 8), ("reuse", 64),
+                                         ("sorted", 1), ("incoherent", 40)])
+def test_render_parity_refill(api, orc, torch_dev, mode, refill):
+    s, sc, osc = both(api, orc, "mixed_small")
+    g = gpu_render(api, sc, 83, 61, 1, 3, mode, (8, 8), 8, 41, refill=refill)
+    o = osc.render(83, 61, 1, 3, mode=mode, tile=(8, 8), k=8, seed=41)
+    compare_render(g, o, (8, 8), mode)
 
 
 def test_reuse_max_bounce_one(api, orc, torch_dev):
