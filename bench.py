@@ -29,6 +29,15 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES, RAY_BYTES, HIT_BYTES = 64, 48, 32, 8
+# 32-bit VALU lane operations per unit of traversal work (counted from the kernel source):
+# a node visit = two slab tests (6 sub, 6 mul, 10 min/max, 1 mul, 2 cmp, 1 and = 26 each)
+# plus the near/far choice (~6); a triangle test = 9 sub, 12 mul, 9 sub of the shear and
+# edge functions, 6 sign tests, 2 add, 3 mul + 2 add for T, the division (~10),
+# 3 compares and 18 component selects.
+OPS_PER_NODE, OPS_PER_TRI = 58, 74
+# MI355X vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit op per lane and cycle
+# (no packed FP32, an FMA counted once) = 39.3 T ops/s.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def log(*a):
@@ -81,6 +90,8 @@ def bench_mode(api, sc, cfg, mode, steps, warmup, seed0):
     launches = int(sec.sum())
     avg_launch_ms = ms[sec].mean()
     bytes_per_launch = bytes_per_ray * sec_rays / B
+    ops_per_ray = nodes_per_ray * OPS_PER_NODE + tris_per_ray * OPS_PER_TRI
+    ops_per_launch = ops_per_ray * sec_rays / B
     kinds = {int(k): float(ms[kind == k].sum() / steps) for k in np.unique(kind)}
     return dict(mode=mode, secondary_mrays_s=mrays, end_to_end_secondary_mrays_s=e2e,
                 frame_ms_mean=float(frame_ms.mean()), frame_ms_p50=float(np.percentile(frame_ms, 50)),
@@ -89,7 +100,8 @@ def bench_mode(api, sc, cfg, mode, steps, warmup, seed0):
                 rays_per_bounce=[int(v) for v in rays], nodes_per_ray=float(nodes_per_ray),
                 tris_per_ray=float(tris_per_ray), bytes_per_ray=float(bytes_per_ray),
                 avg_trace_launch_ms=float(avg_launch_ms), trace_launches=launches,
-                bytes_per_launch=float(bytes_per_launch), ms_by_kind=kinds)
+                bytes_per_launch=float(bytes_per_launch), ops_per_ray=float(ops_per_ray),
+                ops_per_launch=float(ops_per_launch), ms_by_kind=kinds)
 
 
 def cpu_baseline(scene, cfg, budget_s=15.0, seed=2310071821):
@@ -137,6 +149,9 @@ def main():
     ap.add_argument("--modes", default="reuse,incoherent,sorted")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--traffic", type=float, default=None,
+                    help="HBM bytes per traversal launch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE "
+                         "for this kernel version (reported in the roofline object)")
     ap.add_argument("--profile", action="store_true",
                     help="short fixed sequence for rocprofv3: per mode one warm-up and two frames, "
                          "then a 1 GiB device copy that calibrates the HBM byte counters")
@@ -183,7 +198,8 @@ def main():
         log("[bench] cpu baseline (oracle, bounded sample)")
         cpu = cpu_baseline(scene, cfg, args.cpu_budget)
         log(f"[bench] cpu baseline: {cpu}")
-    achieved = head["bytes_per_launch"] / (head["avg_trace_launch_ms"] * 1e-3) / 1e9
+    achieved_ops = head["ops_per_launch"] / (head["avg_trace_launch_ms"] * 1e-3) / 1e12
+    achieved_gbs = head["bytes_per_launch"] / (head["avg_trace_launch_ms"] * 1e-3) / 1e9
     line = {
         "metric": "secondary Mrays/s (reuse vs incoherent vs sorted) + p99 frame latency",
         "value": round(head["secondary_mrays_s"], 3),
@@ -206,10 +222,13 @@ def main():
                       "rays_per_bounce": v["rays_per_bounce"], "nodes_per_ray": round(v["nodes_per_ray"], 2),
                       "tris_per_ray": round(v["tris_per_ray"], 2)} for m, v in results.items()},
         "p99_frame_ms": round(head["frame_ms_p99"], 4),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "roofline": {"bound": "alu", "achieved": round(achieved_ops, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                     "unit": "TFLOP/s", "frac": round(achieved_ops / VALU_PEAK_TOPS, 4), "traffic": args.traffic,
                      "kernel": "k_trace (closest-hit traversal), secondary bounces",
-                     "bytes_per_ray": round(head["bytes_per_ray"], 1)},
+                     "op": "32-bit VALU lane operation (compare/min/max/select counted like add/mul)",
+                     "ops_per_ray": round(head["ops_per_ray"], 1),
+                     "algorithmic_bytes_per_ray": round(head["bytes_per_ray"], 1),
+                     "algorithmic_GBps": round(achieved_gbs, 1), "hbm_peak_GBps": HBM_PEAK_GBS},
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
     }
     print(json.dumps(line), flush=True)

@@ -31,12 +31,13 @@ def camera_struct(cam: dict) -> capi.Camera:
     return c
 
 
-def group_struct(tile=(8, 8), k=8, reuse_max_bounce=0xFFFF, refill=0) -> capi.Group:
+def group_struct(tile=(8, 8), k=8, reuse_max_bounce=0xFFFF, refill=0, waves_per_cu=0) -> capi.Group:
     g = capi.Group()
     g.tile_w, g.tile_h = int(tile[0]), int(tile[1])
     g.k = int(k)
     g.reuse_max_bounce = int(min(reuse_max_bounce, 0xFFFF))
     g.refill = int(refill)
+    g.waves_per_cu = int(waves_per_cu)
     return g
 
 
@@ -140,6 +141,7 @@ class RenderConfig:
     k: int = 8
     reuse_max_bounce: int | None = None
     refill: int = 0
+    waves_per_cu: int = 0
 
 
 class Renderer:
@@ -152,7 +154,7 @@ class Renderer:
         dev = scene.device
         B = cfg.bounces
         rmax = B if cfg.reuse_max_bounce is None else cfg.reuse_max_bounce
-        self.group = group_struct(cfg.tile, cfg.k, rmax, cfg.refill)
+        self.group = group_struct(cfg.tile, cfg.k, rmax, cfg.refill, cfg.waves_per_cu)
         self.mode = capi.MODES[cfg.mode]
         ws = lib().pt_render_workspace_bytes(cfg.w, cfg.h, cfg.spp, B, self.mode, self.group)
         if ws == 0:
@@ -242,3 +244,91 @@ def device_info():
     cu, ma, mi = C.c_int32(), C.c_int32(), C.c_int32()
     check(lib().pt_device_info(C.byref(cu), C.byref(ma), C.byref(mi)))
     return dict(compute_units=cu.value, major=ma.value, minor=mi.value)
+
+
+class JobOutputs:
+    """Device outputs of one batched job (torch tensors)."""
+
+    def __init__(self, w, h, spp, bounces, device):
+        self.radiance = torch.empty((h, w, 3), dtype=torch.float32, device=device)
+        self.hit_prim = torch.empty((bounces + 1, spp, h, w), dtype=torch.int32, device=device)
+        self.hit_t = torch.empty((bounces + 1, spp, h, w), dtype=torch.float32, device=device)
+
+    @property
+    def nbytes(self):
+        return sum(t.numel() * t.element_size() for t in (self.radiance, self.hit_prim, self.hit_t))
+
+
+class Batch:
+    """Jobs in flight over device-resident scenes; merged launches per step (pt_batch_*)."""
+
+    def __init__(self, max_jobs: int, arena_bytes: int, tile=(8, 8), k=8, reuse_max_bounce=0xFFFF, refill=0,
+                 waves_per_cu=0, device="cuda:0"):
+        self.device = _require_cuda(device)
+        self.group = group_struct(tile, k, reuse_max_bounce, refill, waves_per_cu)
+        base = lib().pt_batch_base_bytes(int(max_jobs))
+        if base == 0:
+            raise capi.PtError(capi.PT_EINVAL, "bad max_jobs")
+        with torch.cuda.device(self.device):
+            self.arena = torch.empty(max(int(arena_bytes), base), dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        check(lib().pt_batch_create(int(max_jobs), self.group, self.arena.data_ptr(), self.arena.numel(), C.byref(h)))
+        self.handle = h
+        self.jobs = {}
+
+    @staticmethod
+    def base_bytes(max_jobs: int) -> int:
+        return int(lib().pt_batch_base_bytes(int(max_jobs)))
+
+    def job_struct(self, scene: Scene, w, h, spp, bounces, mode, seed, out: JobOutputs, camera=None) -> capi.Job:
+        j = capi.Job()
+        j.scene = scene.handle.value
+        j.camera = camera_struct(camera or scene.camera)
+        j.w, j.h, j.spp, j.bounces = int(w), int(h), int(spp), int(bounces)
+        j.mode = capi.MODES[mode]
+        j.seed = int(seed)
+        j.radiance, j.hit_prim, j.hit_t = out.radiance.data_ptr(), out.hit_prim.data_ptr(), out.hit_t.data_ptr()
+        return j
+
+    def job_bytes(self, job: capi.Job) -> int:
+        return int(lib().pt_batch_job_bytes(C.byref(job), self.group))
+
+    def submit(self, job: capi.Job, keep=None):
+        """Returns the job id, or None when the batch is full (PT_EBUSY)."""
+        jid = C.c_uint32()
+        st = lib().pt_batch_submit(self.handle, C.byref(job), C.byref(jid))
+        if st == capi.PT_EBUSY:
+            return None
+        check(st)
+        self.jobs[jid.value] = (job, keep)
+        return jid.value
+
+    def step(self) -> int:
+        active = C.c_int32()
+        with torch.cuda.device(self.device):
+            check(lib().pt_batch_step(self.handle, _stream_handle(self.device), C.byref(active)))
+        return active.value
+
+    def done(self, jid: int) -> bool:
+        d = C.c_int32()
+        check(lib().pt_batch_poll(self.handle, int(jid), C.byref(d)))
+        return bool(d.value)
+
+    def release(self, jid: int):
+        check(lib().pt_batch_release(self.handle, int(jid)))
+        self.jobs.pop(jid, None)
+
+    def run(self, use_graph: bool = False, timer: "Timer | None" = None):
+        with torch.cuda.device(self.device):
+            check(lib().pt_batch_run(self.handle, int(bool(use_graph)), timer.handle if timer else None,
+                                     _stream_handle(self.device)))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                torch.cuda.synchronize(self.device)
+                lib().pt_batch_free(h)
+            except Exception:
+                pass
+            self.handle = None

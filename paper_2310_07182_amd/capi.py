@@ -35,7 +35,7 @@ class Camera(C.Structure):
 
 class Group(C.Structure):
     _fields_ = [("tile_w", C.c_uint16), ("tile_h", C.c_uint16), ("k", C.c_uint16),
-                ("reuse_max_bounce", C.c_uint16), ("refill", C.c_uint16), ("reserved", C.c_uint16)]
+                ("reuse_max_bounce", C.c_uint16), ("refill", C.c_uint16), ("waves_per_cu", C.c_uint16)]
 
 
 class SceneDesc(C.Structure):
@@ -52,6 +52,12 @@ class SceneInfo(C.Structure):
 class Outputs(C.Structure):
     _fields_ = [("radiance", C.c_void_p), ("hit_prim", C.c_void_p), ("hit_t", C.c_void_p),
                 ("ray_count", C.c_void_p), ("stats", C.c_void_p), ("rays", C.c_void_p), ("timer", C.c_void_p)]
+
+
+class Job(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("camera", Camera), ("w", C.c_int32), ("h", C.c_int32),
+                ("spp", C.c_int32), ("bounces", C.c_int32), ("mode", C.c_int32), ("reserved", C.c_int32),
+                ("seed", C.c_uint64), ("radiance", C.c_void_p), ("hit_prim", C.c_void_p), ("hit_t", C.c_void_p)]
 
 
 # name -> (restype, argtypes); the full list of exported entry points
@@ -76,6 +82,15 @@ PROTOTYPES = {
     "pt_timer_read": (_st, [_vp, _vp, _vp, _vp, _i32, C.POINTER(_i32)]),
     "pt_timer_free": (_st, [_vp]),
     "pt_device_info": (_st, [C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
+    "pt_batch_job_bytes": (_sz, [C.POINTER(Job), Group]),
+    "pt_batch_base_bytes": (_sz, [_i32]),
+    "pt_batch_create": (_st, [_i32, Group, _vp, _sz, C.POINTER(_vp)]),
+    "pt_batch_submit": (_st, [_vp, C.POINTER(Job), C.POINTER(_u32)]),
+    "pt_batch_step": (_st, [_vp, _vp, C.POINTER(_i32)]),
+    "pt_batch_poll": (_st, [_vp, _u32, C.POINTER(_i32)]),
+    "pt_batch_release": (_st, [_vp, _u32]),
+    "pt_batch_run": (_st, [_vp, _i32, _vp, _vp]),
+    "pt_batch_free": (_st, [_vp]),
     "pt_last_error": (C.c_char_p, []),
 }
 

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -30,6 +31,40 @@ struct pt_scene_s {
     bool uploaded = false;
     int device = -1;
     DevScene dev{};
+};
+
+struct BatchJob {
+    bool used = false;
+    bool finished = false;          // last step enqueued
+    pt_job job{};
+    pt::Frame f{};
+    size_t off = 0, bytes = 0;      // arena range: q0, q1, state
+    int s = 0, b = 0;               // next (sample, bounce) to trace
+    hipEvent_t done_ev = nullptr;   // recorded after the job's last step
+};
+
+constexpr int kBatchRing = 4;       // launch tables in flight
+
+struct pt_batch_s {
+    int max_jobs = 0;
+    pt_group group{};
+    char* arena = nullptr;
+    size_t bytes = 0;
+    size_t table_off = 0, table_stride = 0, counter_off = 0, ovf_off = 0, pool_off = 0;
+    std::vector<BatchJob> jobs;
+    std::map<size_t, size_t> free_ranges;   // offset -> size, coalesced
+    std::vector<std::vector<pt::StepJob>> host_tables;
+    hipEvent_t ring_ev[kBatchRing] = {};
+    bool ring_used[kBatchRing] = {};
+    long long steps = 0;
+    int device = -1;
+    // static-run schedule and its captured graph
+    size_t sched_off = 0, sched_bytes = 0;
+    std::vector<uint32_t> graph_key;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t gstream = nullptr;      // capture / replay stream (the caller's may be the null stream)
+    hipEvent_t gev_in = nullptr, gev_out = nullptr;
 };
 
 struct pt_timer_s {
@@ -122,6 +157,26 @@ Frame make_frame(int w, int h, int spp, int B, pt_mode mode, pt_group g, uint64_
     f.nslots = (uint32_t)f.nstx * (uint32_t)f.nsty * (uint32_t)f.TS;
     f.seed = seed;
     return f;
+}
+
+// camera basis (host side of the arithmetic contract)
+void set_camera(Frame& f, const pt_camera* cam, int w, int h) {
+    H3 pos{cam->pos[0], cam->pos[1], cam->pos[2]};
+    H3 at{cam->look_at[0], cam->look_at[1], cam->look_at[2]};
+    H3 up{cam->up[0], cam->up[1], cam->up[2]};
+    H3 fwd = h_unit(h_sub(at, pos));
+    H3 right = h_unit(h_cross(fwd, up));
+    H3 upv = h_cross(right, fwd);
+    const float th = (float)tan((double)cam->vfov_deg * (3.14159265358979323846 / 360.0));
+    const float vals[4][3] = {{pos.x, pos.y, pos.z}, {fwd.x, fwd.y, fwd.z}, {right.x, right.y, right.z}, {upv.x, upv.y, upv.z}};
+    for (int a = 0; a < 3; ++a) {
+        f.cpos[a] = vals[0][a];
+        f.cfwd[a] = vals[1][a];
+        f.cright[a] = vals[2][a];
+        f.cup[a] = vals[3][a];
+    }
+    f.th = th;
+    f.thx = th * ((float)w / (float)h);
 }
 
 struct Layout {
@@ -375,25 +430,7 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
     if (mode == PT_MODE_SORTED && f.nslots > (1u << 27)) return fail(PT_EINVAL, "sorted mode supports at most 2^27 rays per bounce");
     const Layout L = layout(f);
     if (ws_bytes < L.total) return fail(PT_ENOMEM, "workspace too small: %zu < %zu", ws_bytes, L.total);
-    {
-        // camera basis (host side of the arithmetic contract)
-        H3 pos{cam->pos[0], cam->pos[1], cam->pos[2]};
-        H3 at{cam->look_at[0], cam->look_at[1], cam->look_at[2]};
-        H3 up{cam->up[0], cam->up[1], cam->up[2]};
-        H3 fwd = h_unit(h_sub(at, pos));
-        H3 right = h_unit(h_cross(fwd, up));
-        H3 upv = h_cross(right, fwd);
-        const float th = (float)tan((double)cam->vfov_deg * (3.14159265358979323846 / 360.0));
-        const float vals[4][3] = {{pos.x, pos.y, pos.z}, {fwd.x, fwd.y, fwd.z}, {right.x, right.y, right.z}, {upv.x, upv.y, upv.z}};
-        for (int a = 0; a < 3; ++a) {
-            f.cpos[a] = vals[0][a];
-            f.cfwd[a] = vals[1][a];
-            f.cright[a] = vals[2][a];
-            f.cup[a] = vals[3][a];
-        }
-        f.th = th;
-        f.thx = th * ((float)w / (float)h);
-    }
+    set_camera(f, cam, w, h);
     hipStream_t st = (hipStream_t)stream;
     char* ws = (char*)workspace;
     float4* q[2] = {(float4*)(ws + L.q0), (float4*)(ws + L.q1)};
@@ -409,7 +446,7 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
         if (e == hipSuccess && out->stats) e = pt::launch_zero((uint32_t*)out->stats, (size_t)(B + 1) * 4, st);
     }
     if (e != hipSuccess) return hip_fail(e, "launch (zero)");
-    const int grid = pt::trace_grid_blocks();
+    const int grid = pt::trace_grid_blocks(g.waves_per_cu);
     const size_t plane = (size_t)w * (size_t)h;
     for (int s = 0; s < spp; ++s) {
         {
@@ -453,6 +490,7 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
             ta.ovf = ovf;
             ta.by_pixel = 1;
             ta.refill = g.refill ? g.refill : kDefaultRefill;
+            ta.waves_per_cu = g.waves_per_cu;
             {
                 TimerScope ts(out->timer, st, 0, b);
                 e = pt::launch_trace(scene->dev, ta, out->stats != nullptr, st);
@@ -571,6 +609,452 @@ pt_status pt_timer_free(pt_timer t) {
     for (auto& e : t->ev)
         if (e) (void)hipEventDestroy(e);
     delete t;
+    return PT_OK;
+}
+
+
+// ---------------------------------------------------------------------------- batches
+
+static size_t job_slot_count(const pt_job* j, pt_group g) {
+    return make_frame(j->w, j->h, j->spp, j->bounces, (pt_mode)j->mode, g, 0).nslots;
+}
+
+size_t pt_batch_job_bytes(const pt_job* job, pt_group group) {
+    if (!job || job->w <= 0 || job->h <= 0 || job->spp <= 0 || job->bounces < 0 || job->bounces > 64) return 0;
+    if (check_group(group, job->bounces) != PT_OK) return 0;
+    return 3 * align256(job_slot_count(job, group) * 32);
+}
+
+static size_t batch_table_stride(int max_jobs) { return align256((size_t)max_jobs * sizeof(pt::StepJob)); }
+
+size_t pt_batch_base_bytes(int max_jobs) {
+    if (max_jobs <= 0 || max_jobs > 65536) return 0;
+    return kBatchRing * batch_table_stride(max_jobs) + align256(kBatchRing * 4) +
+           align256((size_t)pt::kMaxTraceBlocks * pt::kTraceBlock * pt::kStackOvf * 4);
+}
+
+static bool pool_alloc(pt_batch bt, size_t n, size_t* off) {
+    for (auto it = bt->free_ranges.begin(); it != bt->free_ranges.end(); ++it) {
+        if (it->second >= n) {
+            *off = it->first;
+            const size_t rest = it->second - n;
+            const size_t at = it->first + n;
+            bt->free_ranges.erase(it);
+            if (rest) bt->free_ranges[at] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+static void pool_free(pt_batch bt, size_t off, size_t n) {
+    auto it = bt->free_ranges.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != bt->free_ranges.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        bt->free_ranges.erase(nx);
+    }
+    if (it != bt->free_ranges.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            bt->free_ranges.erase(it);
+        }
+    }
+}
+
+static void batch_drop_graph(pt_batch bt) {
+    if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
+    bt->gexec = nullptr;
+    bt->graph = nullptr;
+    bt->graph_key.clear();
+    if (bt->sched_bytes) pool_free(bt, bt->sched_off, bt->sched_bytes);
+    bt->sched_bytes = 0;
+}
+
+pt_status pt_batch_create(int max_jobs, pt_group group, void* arena, size_t bytes, pt_batch* out) {
+    if (!out || !arena) return fail(PT_EINVAL, "null argument");
+    *out = nullptr;
+    if (max_jobs <= 0 || max_jobs > 65536) return fail(PT_EINVAL, "max_jobs must be in [1, 65536]");
+    pt_status cs = check_group(group, 0);
+    if (cs != PT_OK) return cs;
+    if (((uintptr_t)arena & 255) != 0) return fail(PT_EINVAL, "arena must be 256-byte aligned");
+    const size_t base = pt_batch_base_bytes(max_jobs);
+    if (bytes < base) return fail(PT_ENOMEM, "arena too small: %zu < %zu", bytes, base);
+    pt_batch bt = new (std::nothrow) pt_batch_s();
+    if (!bt) return fail(PT_ENOMEM, "host allocation failed");
+    bt->max_jobs = max_jobs;
+    bt->group = group;
+    bt->arena = (char*)arena;
+    bt->bytes = bytes;
+    bt->table_stride = batch_table_stride(max_jobs);
+    bt->table_off = 0;
+    bt->counter_off = kBatchRing * bt->table_stride;
+    bt->ovf_off = bt->counter_off + align256(kBatchRing * 4);
+    bt->pool_off = base;
+    try {
+        bt->jobs.resize(max_jobs);
+        bt->host_tables.resize(kBatchRing);
+        for (auto& t : bt->host_tables) t.reserve(max_jobs);
+    } catch (...) {
+        delete bt;
+        return fail(PT_ENOMEM, "host allocation failed");
+    }
+    if (bytes > base) bt->free_ranges[base] = bytes - base;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        delete bt;
+        return hip_fail(e, "hipGetDevice");
+    }
+    bt->device = dev;
+    for (int i = 0; i < kBatchRing; ++i) {
+        e = hipEventCreateWithFlags(&bt->ring_ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            pt_batch_free(bt);
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    for (auto& j : bt->jobs) {
+        e = hipEventCreateWithFlags(&j.done_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            pt_batch_free(bt);
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    e = hipStreamCreateWithFlags(&bt->gstream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->gev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->gev_out, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        pt_batch_free(bt);
+        return hip_fail(e, "stream/event creation");
+    }
+    *out = bt;
+    return PT_OK;
+}
+
+pt_status pt_batch_submit(pt_batch bt, const pt_job* job, uint32_t* job_id) {
+    if (!bt || !job || !job_id) return fail(PT_EINVAL, "null argument");
+    if (!job->scene || !job->scene->uploaded) return fail(PT_EINVAL, "job scene is not uploaded");
+    if (job->scene->device != bt->device) return fail(PT_EINVAL, "job scene lives on another device");
+    if (job->mode != PT_MODE_INCOHERENT && job->mode != PT_MODE_REUSE)
+        return fail(PT_EUNSUPPORTED, "batches support the incoherent and reuse modes");
+    if (job->w <= 0 || job->h <= 0 || job->spp <= 0 || job->bounces < 0 || job->bounces > 64)
+        return fail(PT_EINVAL, "bad job size (w %d, h %d, spp %d, bounces %d)", job->w, job->h, job->spp, job->bounces);
+    if ((long long)job->w * job->h > (1ll << 30)) return fail(PT_EINVAL, "image too large");
+    if (!job->radiance || !job->hit_prim || !job->hit_t) return fail(PT_EINVAL, "job outputs are required");
+    int slot = -1;
+    for (int i = 0; i < bt->max_jobs; ++i)
+        if (!bt->jobs[i].used) {
+            slot = i;
+            break;
+        }
+    if (slot < 0) return fail(PT_EBUSY, "no free job slot");
+    const size_t need = pt_batch_job_bytes(job, bt->group);
+    size_t off = 0;
+    if (!pool_alloc(bt, need, &off)) return fail(PT_EBUSY, "arena has no free range of %zu bytes", need);
+    BatchJob& J = bt->jobs[slot];
+    J.used = true;
+    J.finished = false;
+    J.job = *job;
+    J.f = make_frame(job->w, job->h, job->spp, job->bounces, (pt_mode)job->mode, bt->group, job->seed);
+    set_camera(J.f, &job->camera, job->w, job->h);
+    J.off = off;
+    J.bytes = need;
+    J.s = 0;
+    J.b = 0;
+    *job_id = (uint32_t)slot;
+    batch_drop_graph(bt);
+    return PT_OK;
+}
+
+// fill the launch-table entries of the jobs' current steps; returns jobs, blocks, rays
+static int batch_fill_table(pt_batch bt, const std::vector<int>& ids, std::vector<pt::StepJob>& tab,
+                            const std::vector<int>& bs, const std::vector<int>& ss, uint32_t* blocks,
+                            uint32_t* rays, bool* any_reuse) {
+    tab.clear();
+    uint32_t blk = 0, ray = 0;
+    *any_reuse = false;
+    for (size_t k = 0; k < ids.size(); ++k) {
+        BatchJob& J = bt->jobs[ids[k]];
+        const int b = bs[k], sm = ss[k];
+        char* base = bt->arena + J.off;
+        const size_t qb = align256((size_t)J.f.nslots * 32);
+        float4* q[2] = {(float4*)base, (float4*)(base + qb)};
+        pt::StepJob t{};
+        t.sc = J.job.scene->dev;
+        t.f = J.f;
+        t.b = b;
+        t.s = sm;
+        t.do_raygen = b == 0;
+        t.q_out_raygen = q[0];
+        t.q_in = q[b & 1];
+        t.q_out = q[(b + 1) & 1];
+        t.state = (float4*)(base + 2 * qb);
+        t.hit_prim = J.job.hit_prim;
+        t.hit_t = J.job.hit_t;
+        const size_t plane = (size_t)J.f.w * J.f.h;
+        t.trace_prim = J.job.hit_prim + ((size_t)b * J.f.spp + sm) * plane;
+        t.trace_t = J.job.hit_t + ((size_t)b * J.f.spp + sm) * plane;
+        t.radiance = J.job.radiance;
+        t.block_start = blk;
+        t.ray_start = ray;
+        t.nrays = J.f.nslots;
+        blk += J.f.nslots / (uint32_t)J.f.TS;
+        ray += J.f.nslots;
+        if (J.f.mode == PT_MODE_REUSE) *any_reuse = true;
+        tab.push_back(t);
+    }
+    *blocks = blk;
+    *rays = ray;
+    return (int)tab.size();
+}
+
+static hipError_t batch_launch_step(pt_batch bt, const pt::StepJob* dtab, int njobs, uint32_t blocks, uint32_t rays,
+                                    bool reuse, uint32_t* counter, pt_timer timer, hipStream_t st) {
+    int ts = 0;
+    for (auto& J : bt->jobs)
+        if (J.used) {
+            ts = J.f.TS;
+            break;
+        }
+    hipError_t e;
+    {
+        TimerScope tsc(timer, st, 1, -1);
+        e = pt::launch_zero(counter, 1, st);
+        if (e == hipSuccess) e = pt::launch_raygen_multi(dtab, njobs, blocks, ts, st);
+    }
+    if (e != hipSuccess) return e;
+    pt::TraceArgs ta{};
+    ta.n = rays;
+    ta.work = counter;
+    ta.ovf = (int32_t*)(bt->arena + bt->ovf_off);
+    ta.by_pixel = 1;
+    ta.refill = bt->group.refill ? bt->group.refill : kDefaultRefill;
+    ta.waves_per_cu = bt->group.waves_per_cu;
+    {
+        TimerScope tsc(timer, st, 0, -1);
+        e = pt::launch_trace_multi(dtab, njobs, ta, st);
+    }
+    if (e != hipSuccess) return e;
+    TimerScope tsc(timer, st, 2, -1);
+    return pt::launch_shade_multi(dtab, njobs, blocks, ts, reuse, st);
+}
+
+pt_status pt_batch_step(pt_batch bt, void* stream, int* active) {
+    if (!bt) return fail(PT_EINVAL, "null batch");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int> ids, bs, ss;
+    for (int i = 0; i < bt->max_jobs; ++i) {
+        BatchJob& J = bt->jobs[i];
+        if (J.used && !J.finished) {
+            ids.push_back(i);
+            bs.push_back(J.b);
+            ss.push_back(J.s);
+        }
+    }
+    if (active) *active = (int)ids.size();
+    if (ids.empty()) return PT_OK;
+    const int slot = (int)(bt->steps % kBatchRing);
+    if (bt->ring_used[slot]) {
+        hipError_t e = hipEventSynchronize(bt->ring_ev[slot]);   // the table slot is free again
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    }
+    std::vector<pt::StepJob>& tab = bt->host_tables[slot];
+    uint32_t blocks = 0, rays = 0;
+    bool reuse = false;
+    const int n = batch_fill_table(bt, ids, tab, bs, ss, &blocks, &rays, &reuse);
+    pt::StepJob* dtab = (pt::StepJob*)(bt->arena + bt->table_off + (size_t)slot * bt->table_stride);
+    hipError_t e = hipMemcpyAsync(dtab, tab.data(), (size_t)n * sizeof(pt::StepJob), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (launch table)");
+    uint32_t* counter = (uint32_t*)(bt->arena + bt->counter_off) + slot;
+    e = batch_launch_step(bt, dtab, n, blocks, rays, reuse, counter, nullptr, st);
+    if (e != hipSuccess) return hip_fail(e, "launch (batch step)");
+    e = hipEventRecord(bt->ring_ev[slot], st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    bt->ring_used[slot] = true;
+    ++bt->steps;
+    for (int id : ids) {
+        BatchJob& J = bt->jobs[id];
+        if (++J.b > J.f.B) {
+            J.b = 0;
+            if (++J.s == J.f.spp) {
+                J.finished = true;
+                e = hipEventRecord(J.done_ev, st);
+                if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+            }
+        }
+    }
+    return PT_OK;
+}
+
+pt_status pt_batch_poll(pt_batch bt, uint32_t id, int* done) {
+    if (!bt || !done || id >= (uint32_t)bt->max_jobs || !bt->jobs[id].used) return fail(PT_EINVAL, "bad job id");
+    BatchJob& J = bt->jobs[id];
+    *done = 0;
+    if (!J.finished) return PT_OK;
+    hipError_t e = hipEventQuery(J.done_ev);
+    if (e == hipSuccess) *done = 1;
+    else if (e != hipErrorNotReady) return hip_fail(e, "hipEventQuery");
+    return PT_OK;
+}
+
+pt_status pt_batch_release(pt_batch bt, uint32_t id) {
+    if (!bt || id >= (uint32_t)bt->max_jobs || !bt->jobs[id].used) return fail(PT_EINVAL, "bad job id");
+    int done = 0;
+    pt_status st = pt_batch_poll(bt, id, &done);
+    if (st != PT_OK) return st;
+    if (!done) return fail(PT_EBUSY, "job %u has not finished", id);
+    BatchJob& J = bt->jobs[id];
+    pool_free(bt, J.off, J.bytes);
+    J.used = false;
+    J.finished = false;
+    batch_drop_graph(bt);
+    return PT_OK;
+}
+
+pt_status pt_batch_run(pt_batch bt, int use_graph, pt_timer timer, void* stream) {
+    if (!bt) return fail(PT_EINVAL, "null batch");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int> ids;
+    for (int i = 0; i < bt->max_jobs; ++i)
+        if (bt->jobs[i].used) ids.push_back(i);
+    if (ids.empty()) return PT_OK;
+    // wait for steps still in flight that use the launch-table ring
+    for (int i = 0; i < kBatchRing; ++i)
+        if (bt->ring_used[i]) {
+            hipError_t e = hipEventSynchronize(bt->ring_ev[i]);
+            if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        }
+    // the static schedule: step k traces bounce (k mod (B+1)) of sample k / (B+1) of each job
+    // that has that many steps
+    std::vector<uint32_t> key;
+    for (int id : ids) {
+        key.push_back((uint32_t)id);
+        key.push_back((uint32_t)(bt->jobs[id].off >> 8));
+    }
+    int nsteps = 0;
+    for (int id : ids) nsteps = std::max(nsteps, bt->jobs[id].f.spp * (bt->jobs[id].f.B + 1));
+    const bool rebuild = key != bt->graph_key || !bt->sched_bytes;
+    std::vector<std::vector<pt::StepJob>> tabs(nsteps);
+    std::vector<uint32_t> tblocks(nsteps), trays(nsteps);
+    std::vector<char> treuse(nsteps);
+    for (int k = 0; k < nsteps; ++k) {
+        std::vector<int> sid, bs, ss;
+        for (int id : ids) {
+            const BatchJob& J = bt->jobs[id];
+            if (k < J.f.spp * (J.f.B + 1)) {
+                sid.push_back(id);
+                bs.push_back(k % (J.f.B + 1));
+                ss.push_back(k / (J.f.B + 1));
+            }
+        }
+        bool r = false;
+        batch_fill_table(bt, sid, tabs[k], bs, ss, &tblocks[k], &trays[k], &r);
+        treuse[k] = r;
+    }
+    if (rebuild) {
+        batch_drop_graph(bt);
+        size_t need = 0;
+        for (int k = 0; k < nsteps; ++k) need += align256(tabs[k].size() * sizeof(pt::StepJob));
+        need += align256((size_t)nsteps * 4);
+        size_t off = 0;
+        if (!pool_alloc(bt, need, &off)) return fail(PT_ENOMEM, "arena has no room for the schedule (%zu bytes)", need);
+        bt->sched_off = off;
+        bt->sched_bytes = need;
+        size_t o = off;
+        for (int k = 0; k < nsteps; ++k) {
+            hipError_t e = hipMemcpyAsync(bt->arena + o, tabs[k].data(), tabs[k].size() * sizeof(pt::StepJob),
+                                          hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (schedule)");
+            o += align256(tabs[k].size() * sizeof(pt::StepJob));
+        }
+        hipError_t e = hipStreamSynchronize(st);   // host tables go out of scope
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        bt->graph_key = key;
+    }
+    auto enqueue = [&](pt_timer tm) -> hipError_t {
+        size_t o = bt->sched_off;
+        uint32_t* counters = (uint32_t*)(bt->arena + bt->sched_off + bt->sched_bytes - align256((size_t)nsteps * 4));
+        for (int k = 0; k < nsteps; ++k) {
+            const pt::StepJob* dtab = (const pt::StepJob*)(bt->arena + o);
+            hipError_t e = batch_launch_step(bt, dtab, (int)tabs[k].size(), tblocks[k], trays[k], treuse[k] != 0,
+                                             counters + k, tm, st);
+            if (e != hipSuccess) return e;
+            o += align256(tabs[k].size() * sizeof(pt::StepJob));
+        }
+        return hipSuccess;
+    };
+    hipError_t e;
+    if (use_graph) {
+        if (!bt->gexec) {
+            // capture on the batch's own stream: the caller's stream may be the null stream
+            hipStream_t user = st;
+            st = bt->gstream;
+            e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+            hipError_t le = enqueue(nullptr);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(st, &g);
+            st = user;
+            if (le != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(le, "launch (batch capture)");
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            bt->graph = g;
+            e = hipGraphInstantiate(&bt->gexec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                bt->graph = nullptr;
+                bt->gexec = nullptr;
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+        }
+        // order the replay after the caller's earlier work and the caller's later work after it
+        e = hipEventRecord(bt->gev_in, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(bt->gstream, bt->gev_in, 0);
+        if (e == hipSuccess) e = hipGraphLaunch(bt->gexec, bt->gstream);
+        if (e == hipSuccess) e = hipEventRecord(bt->gev_out, bt->gstream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, bt->gev_out, 0);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    } else {
+        e = enqueue(timer);
+        if (e != hipSuccess) return hip_fail(e, "launch (batch run)");
+    }
+    for (int id : ids) {
+        BatchJob& J = bt->jobs[id];
+        J.finished = true;
+        J.s = J.f.spp;
+        J.b = 0;
+        e = hipEventRecord(J.done_ev, st);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    return PT_OK;
+}
+
+pt_status pt_batch_free(pt_batch bt) {
+    if (!bt) return PT_OK;
+    for (int i = 0; i < kBatchRing; ++i)
+        if (bt->ring_ev[i]) {
+            if (bt->ring_used[i]) (void)hipEventSynchronize(bt->ring_ev[i]);
+            (void)hipEventDestroy(bt->ring_ev[i]);
+        }
+    for (auto& j : bt->jobs)
+        if (j.done_ev) {
+            if (j.finished) (void)hipEventSynchronize(j.done_ev);
+            (void)hipEventDestroy(j.done_ev);
+        }
+    if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
+    if (bt->gstream) {
+        (void)hipStreamSynchronize(bt->gstream);
+        (void)hipStreamDestroy(bt->gstream);
+    }
+    if (bt->gev_in) (void)hipEventDestroy(bt->gev_in);
+    if (bt->gev_out) (void)hipEventDestroy(bt->gev_out);
+    delete bt;
     return PT_OK;
 }
 

@@ -51,10 +51,41 @@ struct TraceArgs {
     int32_t* ovf;              // [kStackOvf][grid threads]
     int by_pixel;
     int refill;                // a wave fetches new rays once this many lanes are idle (1..64)
+    int waves_per_cu;          // persistent grid size, 0 = as many as fit
 };
 
-int trace_grid_blocks();   // persistent grid size (workgroups): a multiple of 8, <= kMaxTraceBlocks
+// One job of a merged launch (batched rendering): the shade, raygen and trace launches of a
+// step cover every job in flight; a workgroup (shade, raygen) or a ray (trace) finds its job
+// by binary search over block_start / ray_start (the table is sorted by both).
+struct StepJob {
+    DevScene sc;
+    Frame f;
+    int b, s;                  // bounce traced and shaded in this step, sample index
+    int do_raygen;             // the step starts sample s (raygen writes q_out_raygen)
+    int pad;
+    float4* q_out_raygen;      // queue the primary rays go to (= q_in)
+    const float4* q_in;        // rays traced this step (and read back by shade)
+    float4* q_out;             // next rays
+    float4* state;
+    int32_t* hit_prim;         // [B+1][spp][h][w]
+    float* hit_t;
+    int32_t* trace_prim;       // hit_prim + plane of (b, s)
+    float* trace_t;
+    float* radiance;
+    uint32_t block_start;      // first workgroup of the job in the merged raygen/shade grid
+    uint32_t ray_start;        // first ray of the job in the merged trace index space
+    uint32_t nrays;
+    uint32_t pad2;
+};
+
+int trace_grid_blocks(int waves_per_cu = 0);   // persistent grid (workgroups): a multiple of 8, <= kMaxTraceBlocks
 hipError_t launch_trace(const DevScene& sc, const TraceArgs& a, bool stats, hipStream_t st);
+// merged launches over njobs jobs (table in device memory); total_rays = sum of nrays,
+// total_blocks = sum of the jobs' workgroups; all jobs share f.TS and the grouping mode
+hipError_t launch_trace_multi(const StepJob* jobs, int njobs, const TraceArgs& a, hipStream_t st);
+hipError_t launch_raygen_multi(const StepJob* jobs, int njobs, uint32_t total_blocks, int TS, hipStream_t st);
+hipError_t launch_shade_multi(const StepJob* jobs, int njobs, uint32_t total_blocks, int TS, bool reuse,
+                              hipStream_t st);
 hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t st);
 hipError_t launch_raygen(const Frame& f, int s, float4* q, float4* state, float4* rays_out, hipStream_t st);
 hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const float4* q_in, float4* q_out,

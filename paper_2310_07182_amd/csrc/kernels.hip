@@ -256,8 +256,9 @@ constexpr int32_t kDone = INT32_MIN;   // = kEmpty: never a node or leaf code
 // reached is tested, so the result is the exact (t, prim id) minimum.
 constexpr int32_t kNoLeaf = 0;   // never a leaf code (leaf codes are negative)
 
-template <bool STATS>
-__global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a, uint32_t gthreads) {
+template <bool STATS, bool MULTI>
+__global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a, uint32_t gthreads,
+                                                       const StepJob* jobs, int njobs) {
     __shared__ int32_t stk[kStackLds][kTraceBlock];
     const int lane = threadIdx.x;
     const uint32_t gtid = blockIdx.x * kTraceBlock + lane;
@@ -273,6 +274,11 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
     int32_t excl = -1, best_p = INT32_MAX, node = kDone, leaf = kNoLeaf;
     float best_t = INFINITY, tcull = INFINITY;
     int sp = 0, novf = 0;
+    // scene and output of the lane's ray: kernel arguments for one job, per lane for a merged launch
+    const float4* nodes = sc.nodes;
+    const float4* btris = sc.btris;
+    int32_t* oprim = a.out_prim;
+    float* ot = a.out_t;
     for (;;) {
         // ---- refill idle lanes with the next rays of the queue
         const unsigned long long idle = __ballot(!have);
@@ -285,7 +291,23 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
             if (!have) {
                 const uint32_t i = base + (uint32_t)__popcll(idle & lt);
                 if (i < n) {
-                    const float4 r0 = a.rays[2 * (size_t)i], r1 = a.rays[2 * (size_t)i + 1];
+                    const float4* rays = a.rays;
+                    uint32_t li = i;
+                    if constexpr (MULTI) {
+                        int lo = 0, hi = njobs - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (jobs[mid].ray_start <= i) lo = mid; else hi = mid - 1;
+                        }
+                        const StepJob& J = jobs[lo];
+                        li = i - J.ray_start;
+                        rays = J.q_in;
+                        nodes = J.sc.nodes;
+                        btris = J.sc.btris;
+                        oprim = J.trace_prim;
+                        ot = J.trace_t;
+                    }
+                    const float4 r0 = rays[2 * (size_t)li], r1 = rays[2 * (size_t)li + 1];
                     const uint32_t pix = __float_as_uint(r1.w);
                     if (!a.by_pixel || pix != kNoRay) {
                         o = xyz(r0);
@@ -300,7 +322,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
                         novf = 0;
                         node = 0;
                         leaf = kNoLeaf;
-                        oi = a.by_pixel ? pix : i;
+                        oi = a.by_pixel ? pix : li;
                         have = true;
                     }
                 }
@@ -314,7 +336,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
         for (;;) {
             // ---- inner nodes; a leaf that is reached is postponed while the slot is free
             while (node >= 0) {
-                const float4* nd = sc.nodes + 4 * (size_t)node;
+                const float4* nd = nodes + 4 * (size_t)node;
                 const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
                 if (STATS) ++nv;
                 const int32_t c0 = __float_as_int(n3.x), c1 = __float_as_int(n3.y);
@@ -380,7 +402,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
                 const uint32_t code = ~(uint32_t)leaf;
                 const uint32_t first = code >> 3, cnt = (code & 7u) + 1u;
                 for (uint32_t k = 0; k < cnt; ++k) {
-                    const float4* tp = sc.btris + 3 * (size_t)(first + k);
+                    const float4* tp = btris + 3 * (size_t)(first + k);
                     const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
                     const int32_t pid = __float_as_int(p0.w);
                     if (STATS) ++nt;
@@ -394,8 +416,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
                 leaf = kNoLeaf;
             }
             if (node == kDone) {
-                a.out_prim[oi] = best_p == INT32_MAX ? -1 : best_p;
-                a.out_t[oi] = best_t;
+                oprim[oi] = best_p == INT32_MAX ? -1 : best_p;
+                ot[oi] = best_t;
                 ++traced;
                 have = false;
                 break;
@@ -437,10 +459,11 @@ __device__ __forceinline__ SlotPix slot_pixel(const Frame& f, uint32_t block, in
     return r;
 }
 
-__global__ __launch_bounds__(1024) void k_raygen(Frame f, int s, float4* q, float4* state, float4* rays_out) {
+__device__ __forceinline__ void raygen_body(const Frame& f, int s, uint32_t blk, float4* q, float4* state,
+                                            float4* rays_out) {
     const int l = threadIdx.x;
-    const uint32_t p = blockIdx.x * (uint32_t)f.TS + (uint32_t)l;
-    const SlotPix sp = slot_pixel(f, blockIdx.x, l);
+    const uint32_t p = blk * (uint32_t)f.TS + (uint32_t)l;
+    const SlotPix sp = slot_pixel(f, blk, l);
     float4 r0 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1)), r1 = make_float4(0.f, 0.f, 0.f, __uint_as_float(kNoRay));
     float4 s0 = make_float4(1.f, 1.f, 1.f, __uint_as_float(0u)), s1 = make_float4(0.f, 0.f, 0.f, __uint_as_float(p));
     if (sp.inside) {
@@ -469,13 +492,34 @@ __global__ __launch_bounds__(1024) void k_raygen(Frame f, int s, float4* q, floa
     state[2 * (size_t)p + 1] = s1;
 }
 
+__global__ __launch_bounds__(1024) void k_raygen(Frame f, int s, float4* q, float4* state, float4* rays_out) {
+    raygen_body(f, s, blockIdx.x, q, state, rays_out);
+}
+
+// workgroup -> job of a merged launch (the table is sorted by block_start)
+__device__ __forceinline__ int job_of_block(const StepJob* jobs, int njobs, uint32_t blk) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].block_start <= blk) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(1024) void k_raygen_multi(const StepJob* jobs, int njobs) {
+    const int j = job_of_block(jobs, njobs, blockIdx.x);
+    const StepJob& J = jobs[j];
+    if (!J.do_raygen) return;
+    raygen_body(J.f, J.s, blockIdx.x - J.block_start, J.q_out_raygen, J.state, nullptr);
+}
+
 // ------------------------------------------------------------------ shade + next direction
 // One workgroup = one super tile (whole reuse tiles), one thread per slot.
-__global__ __launch_bounds__(1024) void k_shade(DevScene sc, Frame f, int b, int s, const float4* __restrict__ q_in,
-                                                float4* __restrict__ q_out, float4* state, int32_t* hit_prim,
-                                                float* hit_t, float* radiance, float4* rays_out) {
+__device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, int b, int s, uint32_t blk,
+                                           const float4* __restrict__ q_in, float4* __restrict__ q_out,
+                                           float4* state, int32_t* hit_prim, float* hit_t, float* radiance,
+                                           float4* rays_out, float* lds) {
     // group exchange in LDS, TS entries each: own tangent exit, tree sums, info bits, min active slot
-    extern __shared__ float lds[];
     const int TS = f.TS;
     float* sq0 = lds;
     float* sq1 = lds + TS;
@@ -486,8 +530,8 @@ __global__ __launch_bounds__(1024) void k_shade(DevScene sc, Frame f, int b, int
     int* sinfo = (int*)(lds + 6 * TS);
     int* srep = (int*)(lds + 7 * TS);
     const int l = threadIdx.x;
-    const uint32_t p = blockIdx.x * (uint32_t)f.TS + (uint32_t)l;
-    const SlotPix spx = slot_pixel(f, blockIdx.x, l);
+    const uint32_t p = blk * (uint32_t)f.TS + (uint32_t)l;
+    const SlotPix spx = slot_pixel(f, blk, l);
     const uint32_t pix = spx.inside ? (uint32_t)spx.y * (uint32_t)f.w + (uint32_t)spx.x : 0u;
     float4 s0 = state[2 * (size_t)p], s1 = state[2 * (size_t)p + 1];
     float T[3] = {s0.x, s0.y, s0.z}, L[3] = {s1.x, s1.y, s1.z};
@@ -602,7 +646,7 @@ __global__ __launch_bounds__(1024) void k_shade(DevScene sc, Frame f, int b, int
         const V3 avgq = unit3(mk3(ss0[root], ss1[root], ss2[root]));
         use = take_rep ? repq : (take_avg ? avgq : use);
         use_ok = (take_rep || take_avg) ? true : use_ok;
-        newpos = blockIdx.x * (uint32_t)TS + (uint32_t)e;
+        newpos = blk * (uint32_t)TS + (uint32_t)e;
     }
     if (b < f.B) {
         float4 o0 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1)), o1 = make_float4(0.f, 0.f, 0.f, __uint_as_float(kNoRay));
@@ -638,6 +682,21 @@ __global__ __launch_bounds__(1024) void k_shade(DevScene sc, Frame f, int b, int
     }
     state[2 * (size_t)p] = make_float4(T[0], T[1], T[2], __uint_as_float(alive ? 1u : 0u));
     state[2 * (size_t)p + 1] = make_float4(L[0], L[1], L[2], __uint_as_float(newpos));
+}
+
+__global__ __launch_bounds__(1024) void k_shade(DevScene sc, Frame f, int b, int s, const float4* __restrict__ q_in,
+                                                float4* __restrict__ q_out, float4* state, int32_t* hit_prim,
+                                                float* hit_t, float* radiance, float4* rays_out) {
+    extern __shared__ float lds[];
+    shade_body(sc, f, b, s, blockIdx.x, q_in, q_out, state, hit_prim, hit_t, radiance, rays_out, lds);
+}
+
+__global__ __launch_bounds__(1024) void k_shade_multi(const StepJob* jobs, int njobs) {
+    extern __shared__ float lds[];
+    const int j = job_of_block(jobs, njobs, blockIdx.x);
+    const StepJob& J = jobs[j];
+    shade_body(J.sc, J.f, J.b, J.s, blockIdx.x - J.block_start, J.q_in, J.q_out, J.state, J.hit_prim, J.hit_t,
+               J.radiance, nullptr, lds);
 }
 
 // ------------------------------------------------------------------ two-point key, gather
@@ -849,35 +908,67 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* k
 }
 
 int g_trace_blocks[64] = {0};
+int g_cus[64] = {0};
 
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-int trace_grid_blocks() {
+int trace_grid_blocks(int waves_per_cu) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
     if (g_trace_blocks[dev] == 0) {
         int cus = 0, per = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace<false>, kTraceBlock, 0) != hipSuccess || per <= 0)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace<false, false>, kTraceBlock, 0) != hipSuccess ||
+            per <= 0)
             per = 8;
         int g = cus * per;
         if (g > kMaxTraceBlocks) g = kMaxTraceBlocks;
         g &= ~7;   // a multiple of the 8 XCDs
         if (g < 8) g = 8;
         g_trace_blocks[dev] = g;
+        g_cus[dev] = cus;
     }
-    return g_trace_blocks[dev];
+    int g = g_trace_blocks[dev];
+    if (waves_per_cu > 0) {
+        const int want = (g_cus[dev] * waves_per_cu) & ~7;
+        if (want >= 8 && want < g) g = want;
+    }
+    return g;
 }
 
 hipError_t launch_trace(const DevScene& sc, const TraceArgs& a, bool stats, hipStream_t st) {
-    const int g = trace_grid_blocks();
+    const int g = trace_grid_blocks(a.waves_per_cu);
     const uint32_t gthreads = (uint32_t)g * kTraceBlock;
     if (a.refill < 1 || a.refill > 64) return hipErrorInvalidValue;
+    const StepJob* none = nullptr;
     if (stats)
-        hipLaunchKernelGGL(k_trace<true>, dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads);
+        hipLaunchKernelGGL((k_trace<true, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
     else
-        hipLaunchKernelGGL(k_trace<false>, dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads);
+        hipLaunchKernelGGL((k_trace<false, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_multi(const StepJob* jobs, int njobs, const TraceArgs& a, hipStream_t st) {
+    const int g = trace_grid_blocks(a.waves_per_cu);
+    const uint32_t gthreads = (uint32_t)g * kTraceBlock;
+    if (a.refill < 1 || a.refill > 64 || njobs < 1) return hipErrorInvalidValue;
+    DevScene none{};
+    hipLaunchKernelGGL((k_trace<false, true>), dim3(g), dim3(kTraceBlock), 0, st, none, a, gthreads, jobs, njobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_raygen_multi(const StepJob* jobs, int njobs, uint32_t total_blocks, int TS, hipStream_t st) {
+    if (total_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_raygen_multi, dim3(total_blocks), dim3(TS), 0, st, jobs, njobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_shade_multi(const StepJob* jobs, int njobs, uint32_t total_blocks, int TS, bool reuse,
+                              hipStream_t st) {
+    if (total_blocks == 0) return hipSuccess;
+    const size_t lds = reuse ? (size_t)TS * 8 * sizeof(float) : 0;
+    hipLaunchKernelGGL(k_shade_multi, dim3(total_blocks), dim3(TS), lds, st, jobs, njobs);
     return hipGetLastError();
 }
 
