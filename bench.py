@@ -40,6 +40,31 @@ OPS_PER_NODE, OPS_PER_TRI = 58, 74
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_trace_indoor_1080p.md")
+KERNEL_SOURCES = ("paper_2310_07182_amd/csrc/kernels.hip", "paper_2310_07182_amd/csrc/kernels.h",
+                  "paper_2310_07182_amd/build.py")
+
+
+def measured_traffic(mode, config):
+    """Bytes per secondary traversal launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when it covers another workload or the kernel sources changed since."""
+    import hashlib
+    if config != "indoor" or not os.path.exists(PROFILE_SUMMARY):
+        return None
+    digest = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            digest.update(f.read())
+    with open(PROFILE_SUMMARY) as f:
+        for line in f:
+            if line.startswith("traffic_bytes_per_launch "):
+                fields = dict(kv.split("=", 1) for kv in line.split()[1:])
+                if fields.get("source_sha256") != digest.hexdigest() or mode not in fields:
+                    return None
+                return float(fields[mode])
+    return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -149,9 +174,6 @@ def main():
     ap.add_argument("--modes", default="reuse,incoherent,sorted")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--traffic", type=float, default=None,
-                    help="HBM bytes per traversal launch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE "
-                         "for this kernel version (reported in the roofline object)")
     ap.add_argument("--profile", action="store_true",
                     help="short fixed sequence for rocprofv3: per mode one warm-up and two frames, "
                          "then a 1 GiB device copy that calibrates the HBM byte counters")
@@ -223,7 +245,7 @@ def main():
                       "tris_per_ray": round(v["tris_per_ray"], 2)} for m, v in results.items()},
         "p99_frame_ms": round(head["frame_ms_p99"], 4),
         "roofline": {"bound": "alu", "achieved": round(achieved_ops, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                     "unit": "TFLOP/s", "frac": round(achieved_ops / VALU_PEAK_TOPS, 4), "traffic": args.traffic,
+                     "unit": "TFLOP/s", "frac": round(achieved_ops / VALU_PEAK_TOPS, 4), "traffic": measured_traffic(head["mode"], args.config),
                      "kernel": "k_trace (closest-hit traversal), secondary bounces",
                      "op": "32-bit VALU lane operation (compare/min/max/select counted like add/mul)",
                      "ops_per_ray": round(head["ops_per_ray"], 1),
