@@ -165,6 +165,125 @@ def cpu_baseline(scene, cfg, budget_s=15.0, seed=2310071821):
                 seconds=dt)
 
 
+MIX_SCENES = ("tiny", "indoor", "landscape", "mid")
+
+
+def load_scenes(api, scenes, names):
+    out = {}
+    for n in names:
+        t0 = time.perf_counter()
+        sd = getattr(scenes, n)()
+        t1 = time.perf_counter()
+        out[n] = api.Scene(sd, device="cuda:0")
+        log(f"[bench] scene {n}: {sd['tris'].shape[0]} triangles, generated {t1 - t0:.1f} s, "
+            f"BVH + upload {time.perf_counter() - t1:.1f} s, {out[n].arena.numel() / 1e9:.2f} GB on the device")
+    return out
+
+
+def _median_ms(run, reps):
+    import torch
+    st = torch.cuda.current_stream()
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        run()
+        b.record(st)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    return float(np.median(times)), [round(t, 3) for t in times]
+
+
+def bench_batched(api, serve, autotune, scs, args):
+    """Batched workload: 64 jobs over the resident scenes, mixed resolution and spp,
+    4 bounces; per-job pt_render calls vs one batch (merged launches, captured graph)
+    with the default and the autotuned launch parameters."""
+    import torch
+    out = {}
+    for mode in args.modes.split(","):
+        if mode == "sorted":
+            continue                                   # batches trace reuse and incoherent jobs
+        reqs = serve.make_requests(args.jobs, None, list(scs), mode, seed=2310071823)
+        rend = [api.Renderer(scs[r.scene], api.RenderConfig(r.w, r.h, r.spp, r.bounces, mode, (8, 8), 8))
+                for r in reqs]
+
+        def per_job():
+            for rr, r in zip(rend, reqs):
+                rr.render(r.seed)
+        per_job()
+        torch.cuda.synchronize()
+        per_ms, per_all = _median_ms(per_job, args.reps)
+        rays = int(sum(int((rr.hit_prim[1:] != -2).sum()) for rr in rend))
+        del rend
+        torch.cuda.empty_cache()
+        need = api.Batch.base_bytes(len(reqs)) + sum(
+            api.batch_job_bytes(r.w, r.h, r.spp, r.bounces, mode, (16, 16), 32) for r in reqs)
+        need = int(need * 1.05) + (64 << 20)           # room for any tuned group's super tiles
+
+        def batch_ms(p, graph=True):
+            (tile, k) = p["group"]
+            b = api.Batch(len(reqs), need, tile=tile, k=k, refill=p["refill"], waves_per_cu=p["waves_per_cu"])
+            outs = [api.JobOutputs(r.w, r.h, r.spp, r.bounces, "cuda:0") for r in reqs]
+            for r, o in zip(reqs, outs):
+                assert b.submit(b.job_struct(scs[r.scene], r.w, r.h, r.spp, r.bounces, mode, r.seed, o)) is not None
+            b.run(use_graph=graph)
+            torch.cuda.synchronize()
+            res = _median_ms(lambda: b.run(use_graph=graph), args.reps)
+            del b, outs
+            return res
+
+        default = dict(autotune.DEFAULT)
+        d_ms, d_all = batch_ms(default)
+        e_ms, _ = batch_ms(default, graph=False)
+        t0 = time.perf_counter()
+        best, _, tlog = autotune.coordinate_descent(lambda p: batch_ms(p)[0], autotune.search_space(mode), default)
+        tune_s = time.perf_counter() - t0
+        b_ms, b_all = batch_ms(best)
+        out[mode] = dict(jobs=len(reqs), secondary_rays=rays,
+                         per_job_ms=round(per_ms, 3), per_job_mrays_s=round(rays / per_ms / 1e3, 1),
+                         batch_graph_ms=round(d_ms, 3), batch_graph_mrays_s=round(rays / d_ms / 1e3, 1),
+                         batch_stepped_no_graph_ms=round(e_ms, 3),
+                         tuned=dict(group=list(best["group"]), waves_per_cu=best["waves_per_cu"],
+                                    refill=best["refill"]),
+                         tuned_ms=round(b_ms, 3), tuned_mrays_s=round(rays / b_ms / 1e3, 1),
+                         speedup_vs_per_job=round(per_ms / b_ms, 3), tuning_s=round(tune_s, 1),
+                         tuning_log=[[str(p["group"]), p["waves_per_cu"], p["refill"], round(c, 3)] for p, c in tlog],
+                         runs_ms=dict(per_job=per_all, batch=d_all, tuned=b_all))
+        log(f"[batched] {mode}: {json.dumps(out[mode])}")
+    return out
+
+
+def bench_serve(api, serve, scs, args):
+    """Serving workload: Poisson arrivals of mixed requests, admission by the HBM budget,
+    continuous batching; latency = finish - arrival."""
+    import torch
+    res = {}
+    max_jobs = args.max_jobs
+    big = max(api.batch_job_bytes(w, h, max(serve.SPPS), 4, "reuse") for w, h in serve.RESOLUTIONS)
+    scene_bytes = sum(int(s.arena.numel()) for s in scs.values())
+    budget = int(args.budget_gb * 1e9)
+    arena = min(max_jobs * big + api.Batch.base_bytes(max_jobs), (budget - scene_bytes) // 2)
+    for mode in args.modes.split(","):
+        if mode == "sorted":
+            continue
+        backend = serve.BatchBackend(scs, max_jobs, arena)
+        # warm the allocator and the kernels with a short burst
+        serve.serve(serve.make_requests(16, None, list(scs), mode, seed=7), backend, budget)
+        torch.cuda.synchronize()
+        for rate in [float(x) for x in args.rates.split(",")]:
+            reqs = serve.make_requests(args.requests, rate, list(scs), mode, seed=2310071824 + int(rate))
+            log(f"[serve] {mode} rate {rate}/s: {len(reqs)} requests, warm-up {args.serve_warmup}")
+            st = serve.serve(reqs, backend, budget)
+            torch.cuda.synchronize()
+            summ = st.summary(warmup=args.serve_warmup)
+            res[f"{mode}@{rate:g}"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
+            log(f"[serve] {mode} rate {rate}/s: {json.dumps(res[f'{mode}@{rate:g}'])}")
+        del backend
+        torch.cuda.empty_cache()
+    return res, dict(budget_gb=args.budget_gb, scene_gb=round(scene_bytes / 1e9, 3), arena_gb=round(arena / 1e9, 3),
+                     max_jobs=max_jobs)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +296,18 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short fixed sequence for rocprofv3: per mode one warm-up and two frames, "
                          "then a 1 GiB device copy that calibrates the HBM byte counters")
+    ap.add_argument("--batched", action="store_true",
+                    help="batched workload: 64 mixed jobs, per-job launches vs merged graph launches, autotuned")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving workload: Poisson arrivals, HBM-budget admission, continuous batching")
+    ap.add_argument("--scenes", default=",".join(MIX_SCENES), help="resident scenes of --batched / --serve")
+    ap.add_argument("--jobs", type=int, default=64)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--rates", default="20,50,100")
+    ap.add_argument("--requests", type=int, default=600)
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--max-jobs", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {args.gpus}); "
@@ -185,6 +316,20 @@ def main():
     import torch
     from paper_2310_07182_amd import api, scenes
 
+    if args.batched or args.serve:
+        from paper_2310_07182_amd import autotune, serve
+        scs = load_scenes(api, scenes, args.scenes.split(","))
+        line = {"metric": "batched and served secondary Mrays/s, p50/p99 request latency", "n_gpus": 1,
+                "data": "synthetic (seeded procedural scenes)", "dtype": "f32",
+                "config": {"workload": f"mixed jobs over resident scenes {args.scenes}: resolutions "
+                                       f"{[f'{w}x{h}' for w, h in serve.RESOLUTIONS]}, spp {list(serve.SPPS)}, "
+                                       "4 bounces, tile 8x8 / K=8 unless tuned"}}
+        if args.batched:
+            line["batched"] = bench_batched(api, serve, autotune, scs, args)
+        if args.serve:
+            line["serving"], line["serving_setup"] = bench_serve(api, serve, scs, args)
+        print(json.dumps(line), flush=True)
+        return
     cfg = dict(scenes.CONFIGS[args.config])
     t0 = time.perf_counter()
     scene = cfg["scene"]()

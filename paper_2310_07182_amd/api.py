@@ -259,6 +259,17 @@ class JobOutputs:
         return sum(t.numel() * t.element_size() for t in (self.radiance, self.hit_prim, self.hit_t))
 
 
+def batch_job_bytes(w, h, spp, bounces, mode, tile=(8, 8), k=8, refill=0, waves_per_cu=0) -> int:
+    """Arena bytes one job of this shape takes in a batch (pt_batch_job_bytes)."""
+    j = capi.Job()
+    j.w, j.h, j.spp, j.bounces = int(w), int(h), int(spp), int(bounces)
+    j.mode = capi.MODES[mode]
+    n = int(lib().pt_batch_job_bytes(C.byref(j), group_struct(tile, k, 0xFFFF, refill, waves_per_cu)))
+    if n == 0:
+        raise capi.PtError(capi.PT_EINVAL, "invalid job shape")
+    return n
+
+
 class Batch:
     """Jobs in flight over device-resident scenes; merged launches per step (pt_batch_*)."""
 

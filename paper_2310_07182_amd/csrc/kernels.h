@@ -38,7 +38,8 @@ constexpr uint32_t kNoRay = 0xFFFFFFFFu;
 constexpr int kTraceBlock = 64;    // one wave per workgroup
 constexpr int kStackLds = 16;      // LDS stack entries per lane
 constexpr int kStackOvf = kMaxDepth - kStackLds + 16; // global overflow entries per lane
-constexpr int kMaxTraceBlocks = 256 * 24;  // cap of the persistent grid (bounds the overflow area)
+constexpr int kMaxTraceBlocks = 256 * 32;  // cap of the persistent grid (bounds the overflow area)
+constexpr int kDefaultWavesPerCu = 24;     // persistent grid when the caller leaves it to the library
 
 struct TraceArgs {
     const float4* rays;
@@ -51,7 +52,7 @@ struct TraceArgs {
     int32_t* ovf;              // [kStackOvf][grid threads]
     int by_pixel;
     int refill;                // a wave fetches new rays once this many lanes are idle (1..64)
-    int waves_per_cu;          // persistent grid size, 0 = as many as fit
+    int waves_per_cu;          // persistent grid size, 0 = kDefaultWavesPerCu
 };
 
 // One job of a merged launch (batched rendering): the shade, raygen and trace launches of a

@@ -930,10 +930,8 @@ int trace_grid_blocks(int waves_per_cu) {
         g_cus[dev] = cus;
     }
     int g = g_trace_blocks[dev];
-    if (waves_per_cu > 0) {
-        const int want = (g_cus[dev] * waves_per_cu) & ~7;
-        if (want >= 8 && want < g) g = want;
-    }
+    const int want = (g_cus[dev] * (waves_per_cu > 0 ? waves_per_cu : kDefaultWavesPerCu)) & ~7;
+    if (want >= 8 && want < g) g = want;
     return g;
 }
 
