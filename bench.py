@@ -129,7 +129,7 @@ def bench_mode(api, sc, cfg, mode, steps, warmup, seed0):
                 ops_per_launch=float(ops_per_launch), ms_by_kind=kinds)
 
 
-def cpu_baseline(scene, cfg, budget_s=15.0, seed=2310071821):
+def cpu_baseline(scene, cfg, name, budget_s=15.0, seed=2310071821):
     """The oracle, single-threaded, on a bounded sample of the same frame: a
     band of reuse tiles (reuse mode), timed on this host."""
     import oracle
@@ -160,7 +160,7 @@ def cpu_baseline(scene, cfg, budget_s=15.0, seed=2310071821):
     dt = time.perf_counter() - t0
     sec = float(r["rays_per_bounce"][1:].sum())
     return dict(value=sec / dt / 1e6, unit="secondary Mrays/s", cores=1, kind="oracle",
-                sample=f"{n} of {ntx * nty} {tile[0]}x{tile[1]} reuse tiles of the {w}x{h} indoor frame "
+                sample=f"{n} of {ntx * nty} {tile[0]}x{tile[1]} reuse tiles of the {w}x{h} {name} frame "
                        f"(B={B}), single thread, {dt:.1f} s; BVH build {build_s:.1f} s excluded",
                 seconds=dt)
 
@@ -363,7 +363,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle, bounded sample)")
-        cpu = cpu_baseline(scene, cfg, args.cpu_budget)
+        cpu = cpu_baseline(scene, cfg, args.config, args.cpu_budget)
         log(f"[bench] cpu baseline: {cpu}")
     achieved_ops = head["ops_per_launch"] / (head["avg_trace_launch_ms"] * 1e-3) / 1e12
     achieved_gbs = head["bytes_per_launch"] / (head["avg_trace_launch_ms"] * 1e-3) / 1e9

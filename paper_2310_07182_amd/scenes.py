@@ -343,6 +343,28 @@ def _value_noise(x, y, salt):
     return (n00 * (1 - sx) + n10 * sx) * (1 - sy) + (n01 * (1 - sx) + n11 * sx) * sy
 
 
+def _value_noise_grid(x, y, salt):
+    """_value_noise over the grid x[i] (first axis) by y[j] (second axis): the lattice
+    values are hashed once and gathered, the same arithmetic per point."""
+    ix = np.floor(x)
+    iy = np.floor(y)
+    fx = (x - ix)[:, None]
+    fy = (y - iy)[None, :]
+    ix = ix.astype(np.int64)
+    iy = iy.astype(np.int64)
+    sx = fx * fx * (3 - 2 * fx)
+    sy = fy * fy * (3 - 2 * fy)
+    lx = np.arange(ix.min(), ix.max() + 2, dtype=np.int64)
+    ly = np.arange(iy.min(), iy.max() + 2, dtype=np.int64)
+    G = _hash2(lx[:, None] + 0 * ly[None, :], ly[None, :] + 0 * lx[:, None], salt)
+    gi = ix - lx[0]
+    gj = iy - ly[0]
+    rows0, rows1 = G[gi], G[gi + 1]
+    n00, n01 = rows0[:, gj], rows0[:, gj + 1]
+    n10, n11 = rows1[:, gj], rows1[:, gj + 1]
+    return (n00 * (1 - sx) + n10 * sx) * (1 - sy) + (n01 * (1 - sx) + n11 * sx) * sy
+
+
 def fbm_heightfield(n: int, seed: int, octaves: int = 8, amplitude: float = 300.0,
                     base_period: float = 1024.0) -> np.ndarray:
     """n x n heights (float64), value-noise fBm, lacunarity 2, gain 0.5."""
@@ -352,8 +374,7 @@ def fbm_heightfield(n: int, seed: int, octaves: int = 8, amplitude: float = 300.
     hgt = np.zeros((n, n), dtype=np.float64)
     amp, freq, norm = 1.0, 1.0 / base_period, 0.0
     for o in range(octaves):
-        X, Y = np.meshgrid(xs * freq, xs * freq, indexing="ij")
-        hgt += amp * (_value_noise(X, Y, int(salts[o])) - 0.5)
+        hgt += amp * (_value_noise_grid(xs * freq, xs * freq, int(salts[o])) - 0.5)
         norm += amp
         amp *= 0.5
         freq *= 2.0
