@@ -222,7 +222,8 @@ def bench_batched(api, serve, autotune, scs, args):
 
         def batch_ms(p, graph=True):
             (tile, k) = p["group"]
-            b = api.Batch(len(reqs), need, tile=tile, k=k, refill=p["refill"], waves_per_cu=p["waves_per_cu"])
+            b = api.Batch(len(reqs), need, tile=tile, k=k, refill=p["refill"], waves_per_cu=p["waves_per_cu"],
+                          leaf_gate=p["leaf_gate"])
             outs = [api.JobOutputs(r.w, r.h, r.spp, r.bounces, "cuda:0") for r in reqs]
             for r, o in zip(reqs, outs):
                 assert b.submit(b.job_struct(scs[r.scene], r.w, r.h, r.spp, r.bounces, mode, r.seed, o)) is not None
@@ -244,10 +245,11 @@ def bench_batched(api, serve, autotune, scs, args):
                          batch_graph_ms=round(d_ms, 3), batch_graph_mrays_s=round(rays / d_ms / 1e3, 1),
                          batch_stepped_no_graph_ms=round(e_ms, 3),
                          tuned=dict(group=list(best["group"]), waves_per_cu=best["waves_per_cu"],
-                                    refill=best["refill"]),
+                                    refill=best["refill"], leaf_gate=best["leaf_gate"]),
                          tuned_ms=round(b_ms, 3), tuned_mrays_s=round(rays / b_ms / 1e3, 1),
                          speedup_vs_per_job=round(per_ms / b_ms, 3), tuning_s=round(tune_s, 1),
-                         tuning_log=[[str(p["group"]), p["waves_per_cu"], p["refill"], round(c, 3)] for p, c in tlog],
+                         tuning_log=[[str(p["group"]), p["waves_per_cu"], p["refill"], p["leaf_gate"], round(c, 3)]
+                                     for p, c in tlog],
                          runs_ms=dict(per_job=per_all, batch=d_all, tuned=b_all))
         log(f"[batched] {mode}: {json.dumps(out[mode])}")
     return out

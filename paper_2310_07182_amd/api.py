@@ -31,13 +31,14 @@ def camera_struct(cam: dict) -> capi.Camera:
     return c
 
 
-def group_struct(tile=(8, 8), k=8, reuse_max_bounce=0xFFFF, refill=0, waves_per_cu=0) -> capi.Group:
+def group_struct(tile=(8, 8), k=8, reuse_max_bounce=0xFFFF, refill=0, waves_per_cu=0, leaf_gate=0) -> capi.Group:
     g = capi.Group()
     g.tile_w, g.tile_h = int(tile[0]), int(tile[1])
     g.k = int(k)
     g.reuse_max_bounce = int(min(reuse_max_bounce, 0xFFFF))
     g.refill = int(refill)
     g.waves_per_cu = int(waves_per_cu)
+    g.leaf_gate = int(leaf_gate)
     return g
 
 
@@ -142,6 +143,7 @@ class RenderConfig:
     reuse_max_bounce: int | None = None
     refill: int = 0
     waves_per_cu: int = 0
+    leaf_gate: int = 0
 
 
 class Renderer:
@@ -154,7 +156,7 @@ class Renderer:
         dev = scene.device
         B = cfg.bounces
         rmax = B if cfg.reuse_max_bounce is None else cfg.reuse_max_bounce
-        self.group = group_struct(cfg.tile, cfg.k, rmax, cfg.refill, cfg.waves_per_cu)
+        self.group = group_struct(cfg.tile, cfg.k, rmax, cfg.refill, cfg.waves_per_cu, cfg.leaf_gate)
         self.mode = capi.MODES[cfg.mode]
         ws = lib().pt_render_workspace_bytes(cfg.w, cfg.h, cfg.spp, B, self.mode, self.group)
         if ws == 0:
@@ -198,8 +200,8 @@ class Renderer:
 
 
 def render(scene: Scene, w, h, spp=1, bounces=2, mode="incoherent", tile=(8, 8), k=8,
-           reuse_max_bounce=None, seed=1, camera=None, stats=False, rays=False, refill=0) -> dict:
-    r = Renderer(scene, RenderConfig(w, h, spp, bounces, mode, tuple(tile), k, reuse_max_bounce, refill),
+           reuse_max_bounce=None, seed=1, camera=None, stats=False, rays=False, refill=0, leaf_gate=0) -> dict:
+    r = Renderer(scene, RenderConfig(w, h, spp, bounces, mode, tuple(tile), k, reuse_max_bounce, refill, 0, leaf_gate),
                  stats=stats, rays=rays)
     r.render(seed, camera)
     return r.results()
@@ -259,12 +261,12 @@ class JobOutputs:
         return sum(t.numel() * t.element_size() for t in (self.radiance, self.hit_prim, self.hit_t))
 
 
-def batch_job_bytes(w, h, spp, bounces, mode, tile=(8, 8), k=8, refill=0, waves_per_cu=0) -> int:
+def batch_job_bytes(w, h, spp, bounces, mode, tile=(8, 8), k=8, refill=0, waves_per_cu=0, leaf_gate=0) -> int:
     """Arena bytes one job of this shape takes in a batch (pt_batch_job_bytes)."""
     j = capi.Job()
     j.w, j.h, j.spp, j.bounces = int(w), int(h), int(spp), int(bounces)
     j.mode = capi.MODES[mode]
-    n = int(lib().pt_batch_job_bytes(C.byref(j), group_struct(tile, k, 0xFFFF, refill, waves_per_cu)))
+    n = int(lib().pt_batch_job_bytes(C.byref(j), group_struct(tile, k, 0xFFFF, refill, waves_per_cu, leaf_gate)))
     if n == 0:
         raise capi.PtError(capi.PT_EINVAL, "invalid job shape")
     return n
@@ -274,9 +276,9 @@ class Batch:
     """Jobs in flight over device-resident scenes; merged launches per step (pt_batch_*)."""
 
     def __init__(self, max_jobs: int, arena_bytes: int, tile=(8, 8), k=8, reuse_max_bounce=0xFFFF, refill=0,
-                 waves_per_cu=0, device="cuda:0"):
+                 waves_per_cu=0, leaf_gate=0, device="cuda:0"):
         self.device = _require_cuda(device)
-        self.group = group_struct(tile, k, reuse_max_bounce, refill, waves_per_cu)
+        self.group = group_struct(tile, k, reuse_max_bounce, refill, waves_per_cu, leaf_gate)
         base = lib().pt_batch_base_bytes(int(max_jobs))
         if base == 0:
             raise capi.PtError(capi.PT_EINVAL, "bad max_jobs")

@@ -7,7 +7,9 @@ Tuned, by measuring on the device:
     on 8x8 tiles), so the bound keeps one distinct direction per eight pixels at least;
   * waves per CU of the persistent traversal grid;
   * the refill threshold of the traversal: the number of idle lanes at which a wave
-    takes new rays from the ray queue (the queue tile one refill fetches).
+    takes new rays from the ray queue (the queue tile one refill fetches);
+  * the leaf gate: how few lanes may still be looking for a leaf when a wave stops
+    walking inner nodes and tests the leaves its lanes hold.
 
 The search is coordinate descent: one parameter at a time, over its candidate list,
 keeping the best value before moving to the next.  The objective is the measured
@@ -17,7 +19,8 @@ from __future__ import annotations
 
 GROUPS = (((4, 4), 2), ((8, 8), 2), ((8, 8), 4), ((8, 8), 8), ((16, 8), 16), ((16, 16), 32))
 WAVES_PER_CU = (16, 24, 32)
-REFILLS = (16, 32, 48)
+REFILLS = (32, 40, 48, 56)
+LEAF_GATES = (4, 6, 8, 12, 16)
 MAX_GROUP_FRACTION = 8      # K <= W*H / 8
 
 
@@ -50,16 +53,17 @@ def coordinate_descent(evaluate, dims, start):
     return best, best_cost, log
 
 
-def search_space(mode, groups=GROUPS, waves=WAVES_PER_CU, refills=REFILLS):
+def search_space(mode, groups=GROUPS, waves=WAVES_PER_CU, refills=REFILLS, leaf_gates=LEAF_GATES):
     dims = []
     if mode == "reuse":
         dims.append(("group", tuple(g for g in groups if group_allowed(*g))))
     dims.append(("waves_per_cu", tuple(waves)))
     dims.append(("refill", tuple(refills)))
+    dims.append(("leaf_gate", tuple(leaf_gates)))
     return dims
 
 
-DEFAULT = dict(group=((8, 8), 8), waves_per_cu=24, refill=32)
+DEFAULT = dict(group=((8, 8), 8), waves_per_cu=24, refill=48, leaf_gate=8)
 
 
 def _median_ms(run, reps):
@@ -83,7 +87,8 @@ def tune_render(scene, w, h, spp, bounces, mode, reps=3, seed=1, **space):
 
     def evaluate(p):
         (tile, k) = p["group"]
-        cfg = api.RenderConfig(w, h, spp, bounces, mode, tile, k, None, p["refill"], p["waves_per_cu"])
+        cfg = api.RenderConfig(w, h, spp, bounces, mode, tile, k, None, p["refill"], p["waves_per_cu"],
+                               p["leaf_gate"])
         r = api.Renderer(scene, cfg)
         r.render(seed)                                   # warm-up
         return _median_ms(lambda: r.render(seed), reps)
@@ -100,7 +105,8 @@ def tune_batch(scenes, requests, arena_bytes, max_jobs=None, reps=2, **space):
 
     def evaluate(p):
         (tile, k) = p["group"]
-        b = api.Batch(max_jobs, arena_bytes, tile=tile, k=k, refill=p["refill"], waves_per_cu=p["waves_per_cu"])
+        b = api.Batch(max_jobs, arena_bytes, tile=tile, k=k, refill=p["refill"], waves_per_cu=p["waves_per_cu"],
+                      leaf_gate=p["leaf_gate"])
         for r, o in zip(requests, outs):
             if b.submit(b.job_struct(scenes[r.scene], r.w, r.h, r.spp, r.bounces, r.mode, r.seed, o)) is None:
                 raise RuntimeError("batch arena too small for the tuning set")

@@ -93,7 +93,7 @@ pt_status hip_fail(hipError_t e, const char* what) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-constexpr int kDefaultRefill = 32;
+constexpr int kDefaultRefill = 48;
 
 bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
@@ -117,6 +117,7 @@ pt_status check_group(pt_group g, int bounces) {
     if (wh > 1024) return fail(PT_EINVAL, "tile_w * tile_h must be <= 1024 (got %d)", wh);
     if ((int)g.k > wh) return fail(PT_EINVAL, "k (%d) must divide tile_w * tile_h (%d)", g.k, wh);
     if (g.refill > 64) return fail(PT_EINVAL, "refill must be in [0, 64] (got %d)", g.refill);
+    if (g.leaf_gate > 64) return fail(PT_EINVAL, "leaf_gate must be in [0, 64] (got %d)", g.leaf_gate);
     return PT_OK;
 }
 
@@ -491,6 +492,7 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
             ta.by_pixel = 1;
             ta.refill = g.refill ? g.refill : kDefaultRefill;
             ta.waves_per_cu = g.waves_per_cu;
+            ta.leaf_gate = (g.leaf_gate ? g.leaf_gate : pt::kDefaultLeafGate) - 1;
             {
                 TimerScope ts(out->timer, st, 0, b);
                 e = pt::launch_trace(scene->dev, ta, out->stats != nullptr, st);
@@ -533,6 +535,7 @@ pt_status pt_trace(pt_scene scene, const float* rays, uint32_t n, int refill, in
     ta.ovf = (int32_t*)((char*)workspace + 256);
     ta.by_pixel = 0;
     ta.refill = refill ? refill : kDefaultRefill;
+    ta.leaf_gate = pt::kDefaultLeafGate - 1;
     hipError_t e = pt::launch_zero(ta.work, 1, st);
     if (e != hipSuccess) return hip_fail(e, "launch (zero)");
     e = pt::launch_trace(scene->dev, ta, false, st);
@@ -833,6 +836,7 @@ static hipError_t batch_launch_step(pt_batch bt, const pt::StepJob* dtab, int nj
     ta.by_pixel = 1;
     ta.refill = bt->group.refill ? bt->group.refill : kDefaultRefill;
     ta.waves_per_cu = bt->group.waves_per_cu;
+    ta.leaf_gate = (bt->group.leaf_gate ? bt->group.leaf_gate : pt::kDefaultLeafGate) - 1;
     {
         TimerScope tsc(timer, st, 0, -1);
         e = pt::launch_trace_multi(dtab, njobs, ta, st);

@@ -40,6 +40,7 @@ constexpr int kStackLds = 16;      // LDS stack entries per lane
 constexpr int kStackOvf = kMaxDepth - kStackLds + 16; // global overflow entries per lane
 constexpr int kMaxTraceBlocks = 256 * 32;  // cap of the persistent grid (bounds the overflow area)
 constexpr int kDefaultWavesPerCu = 24;     // persistent grid when the caller leaves it to the library
+constexpr int kDefaultLeafGate = 8;        // pt_group.leaf_gate when the caller leaves it to the library
 
 struct TraceArgs {
     const float4* rays;
@@ -53,6 +54,7 @@ struct TraceArgs {
     int by_pixel;
     int refill;                // a wave fetches new rays once this many lanes are idle (1..64)
     int waves_per_cu;          // persistent grid size, 0 = kDefaultWavesPerCu
+    int leaf_gate;             // the inner-node phase ends when at most this many lanes lack a leaf
 };
 
 // One job of a merged launch (batched rendering): the shade, raygen and trace launches of a

@@ -243,23 +243,28 @@ __device__ __forceinline__ float slab(float lx, float hx, float ly, float hy, fl
 
 constexpr int32_t kDone = INT32_MIN;   // = kEmpty: never a node or leaf code
 
-// Closest-hit traversal, one ray per lane, in the structure of Aila & Laine
-// ("Understanding the efficiency of ray traversal on GPUs", HPG 2009):
-//  * while-while: a lane walks inner nodes until every active lane of the wave
-//    holds a leaf (a lane that reaches a leaf early postpones it and keeps walking
-//    inner nodes), then the wave tests leaves together, so the inner-node and
-//    triangle code do not alternate inside one divergent loop;
-//  * persistent lanes with refill: a lane whose ray is finished takes a new ray
-//    from the queue once enough lanes are idle, so a wave is not held by its
-//    slowest ray.
-// Culling only ever prunes (conservative box test), and every leaf that is
-// reached is tested, so the result is the exact (t, prim id) minimum.
+// Closest-hit traversal, one ray per lane, after Aila & Laine ("Understanding the
+// efficiency of ray traversal on GPUs", HPG 2009), shaped for 64-wide waves:
+//  * inner-node phase: lanes walk inner nodes; a lane that reaches a leaf postpones
+//    it and keeps walking (speculative traversal) until it reaches a second one.
+//    The phase ends once at most `leaf_gate` lanes are still without a leaf: waiting
+//    for all 64 lanes leaves most of them parked.
+//  * leaf phase, wave-wide: the triangles of every held leaf are listed as (lane,
+//    triangle) pairs and spread over all 64 lanes, idle ones included; each result
+//    returns to the lane that owns the ray by cross-lane shuffles, where the (t,
+//    prim id) minimum is kept.  A lane tests its pairs with the owner's ray.
+//  * persistent lanes with refill: a lane whose ray is finished takes a new ray from
+//    the queue once `refill` lanes are idle, so a wave is not held by its slowest ray.
+// Culling only ever prunes (conservative box test), and every leaf that is reached
+// is tested, so the result is the exact (t, prim id) minimum.  All loops below are
+// wave-uniform: every lane reaches every shuffle and barrier.
 constexpr int32_t kNoLeaf = 0;   // never a leaf code (leaf codes are negative)
 
 template <bool STATS, bool MULTI>
 __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a, uint32_t gthreads,
                                                        const StepJob* jobs, int njobs) {
     __shared__ int32_t stk[kStackLds][kTraceBlock];
+    __shared__ uint8_t pairs[kTraceBlock * kMaxLeaf];   // lane | (triangle in leaf) << 6
     const int lane = threadIdx.x;
     const uint32_t gtid = blockIdx.x * kTraceBlock + lane;
     const uint32_t n = a.n;
@@ -332,10 +337,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
             if (exhausted) break;
             continue;
         }
-        if (!have) continue;
+        // ---- inner nodes; a leaf that is reached is postponed while the slot is free
         for (;;) {
-            // ---- inner nodes; a leaf that is reached is postponed while the slot is free
-            while (node >= 0) {
+            if (have && node >= 0) {
                 const float4* nd = nodes + 4 * (size_t)node;
                 const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
                 if (STATS) ++nv;
@@ -353,18 +357,20 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
                         // the BVH depth bound keeps the stack within kStackLds + kStackOvf
                         // entries; the check keeps every access in bounds regardless
                         if (novf + kStackLds / 2 > kStackOvf) {
-                            node = kDone;
+                            node = kDone;   // give the ray up (the pop below finds the stack empty)
                             leaf = kNoLeaf;
-                            break;
+                            sp = 0;
+                            novf = 0;
+                        } else {
+                            // spill the lower half of the LDS stack to this lane's overflow column
+                            for (int e = 0; e < kStackLds / 2; ++e)
+                                a.ovf[(size_t)(novf + e) * gthreads + gtid] = stk[e][lane];
+                            for (int e = 0; e < kStackLds / 2; ++e) stk[e][lane] = stk[e + kStackLds / 2][lane];
+                            novf += kStackLds / 2;
+                            sp = kStackLds / 2;
                         }
-                        // spill the lower half of the LDS stack to this lane's overflow column
-                        for (int e = 0; e < kStackLds / 2; ++e)
-                            a.ovf[(size_t)(novf + e) * gthreads + gtid] = stk[e][lane];
-                        for (int e = 0; e < kStackLds / 2; ++e) stk[e][lane] = stk[e + kStackLds / 2][lane];
-                        novf += kStackLds / 2;
-                        sp = kStackLds / 2;
                     }
-                    stk[sp++][lane] = far;
+                    if (node != kDone) stk[sp++][lane] = far;
                 } else if (h0) {
                     node = c0;
                 } else if (h1) {
@@ -383,47 +389,94 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
                     }
                     node = sp > 0 ? stk[--sp][lane] : kDone;
                 }
-                // every active lane holds a leaf: test them together
-                if (__ballot(leaf == kNoLeaf) == 0) break;
             }
-            // ---- leaves: the postponed one, then the next node while it is a leaf
-            for (;;) {
-                if (leaf == kNoLeaf) {
-                    if (node >= 0 || node == kDone) break;
-                    leaf = node;
-                    if (sp == 0 && novf > 0) {
-                        const int m = novf < kStackLds / 2 ? novf : kStackLds / 2;
-                        for (int e = 0; e < m; ++e) stk[e][lane] = a.ovf[(size_t)(novf - m + e) * gthreads + gtid];
-                        novf -= m;
-                        sp = m;
-                    }
-                    node = sp > 0 ? stk[--sp][lane] : kDone;
+            // few lanes are still looking for their first leaf: test the leaves now
+            if ((int)__popcll(__ballot(have && node >= 0 && leaf == kNoLeaf)) <= a.leaf_gate) break;
+        }
+        // ---- leaves, wave-wide: the postponed one, then the next node while it is a leaf
+        for (;;) {
+            if (have && leaf == kNoLeaf && node < 0 && node != kDone) {
+                leaf = node;
+                if (sp == 0 && novf > 0) {
+                    const int m = novf < kStackLds / 2 ? novf : kStackLds / 2;
+                    for (int e = 0; e < m; ++e) stk[e][lane] = a.ovf[(size_t)(novf - m + e) * gthreads + gtid];
+                    novf -= m;
+                    sp = m;
                 }
-                const uint32_t code = ~(uint32_t)leaf;
-                const uint32_t first = code >> 3, cnt = (code & 7u) + 1u;
-                for (uint32_t k = 0; k < cnt; ++k) {
-                    const float4* tp = btris + 3 * (size_t)(first + k);
+                node = sp > 0 ? stk[--sp][lane] : kDone;
+            }
+            const bool hold = have && leaf != kNoLeaf;
+            if (__ballot(hold) == 0) break;
+            const uint32_t code = ~(uint32_t)leaf;
+            const uint32_t first = code >> 3;
+            const uint32_t cnt = hold ? (code & 7u) + 1u : 0u;
+            // exclusive prefix sum of the triangle counts (at most 4: three bits) over the wave
+            const unsigned long long q0 = __ballot(cnt & 1u), q1 = __ballot(cnt & 2u), q2 = __ballot(cnt & 4u);
+            const uint32_t off = (uint32_t)(__popcll(q0 & lt) + 2 * __popcll(q1 & lt) + 4 * __popcll(q2 & lt));
+            const uint32_t total = (uint32_t)(__popcll(q0) + 2 * __popcll(q1) + 4 * __popcll(q2));
+            for (uint32_t j = 0; j < cnt; ++j) pairs[off + j] = (uint8_t)((uint32_t)lane | (j << 6));
+            __syncthreads();
+            const int perm = rp.kx | (rp.ky << 2) | (rp.kz << 4);
+            for (uint32_t base = 0; base < total; base += kTraceBlock) {
+                const uint32_t p = base + (uint32_t)lane;
+                const bool valid = p < total;
+                const uint32_t e = valid ? (uint32_t)pairs[p] : 0u;
+                const int src = (int)(e & 63u);
+                // the owner's ray, leaf and triangle array
+                RayPre q;
+                q.ox = __shfl(rp.ox, src);
+                q.oy = __shfl(rp.oy, src);
+                q.oz = __shfl(rp.oz, src);
+                q.sx = __shfl(rp.sx, src);
+                q.sy = __shfl(rp.sy, src);
+                q.sz = __shfl(rp.sz, src);
+                const int qperm = __shfl(perm, src);
+                q.kx = qperm & 3;
+                q.ky = (qperm >> 2) & 3;
+                q.kz = (qperm >> 4) & 3;
+                const int32_t qexcl = __shfl(excl, src);
+                const uint32_t qtri = __shfl(first, src) + (e >> 6);
+                const float4* qtris = btris;
+                if constexpr (MULTI) {
+                    const uint64_t bp = (uint64_t)(uintptr_t)btris;
+                    const uint32_t lo = __shfl((uint32_t)bp, src), hi = __shfl((uint32_t)(bp >> 32), src);
+                    qtris = (const float4*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+                }
+                float t = INFINITY;
+                int32_t pid = INT32_MAX;
+                if (valid) {
+                    const float4* tp = qtris + 3 * (size_t)qtri;
                     const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
-                    const int32_t pid = __float_as_int(p0.w);
+                    const int32_t id = __float_as_int(p0.w);
                     if (STATS) ++nt;
-                    float t;
-                    if (pid != excl && tri_test(rp, p0, p1, p2, t) && (t < best_t || (t == best_t && pid < best_p))) {
-                        best_t = t;
-                        best_p = pid;
-                        tcull = t * kCullScale;
+                    float th;
+                    if (tri_test(q, p0, p1, p2, th) && id != qexcl) {
+                        t = th;
+                        pid = id;
                     }
                 }
-                leaf = kNoLeaf;
+                // each owner takes the results of its pairs that fell into this block of 64
+#pragma unroll
+                for (int jj = 0; jj < kMaxLeaf; ++jj) {
+                    const int s = (int)off + jj - (int)base;
+                    const int sl = s < 0 ? 0 : (s > kTraceBlock - 1 ? kTraceBlock - 1 : s);
+                    const float tt = __shfl(t, sl);
+                    const int32_t pp = __shfl(pid, sl);
+                    if (jj < (int)cnt && s >= 0 && s < kTraceBlock && (tt < best_t || (tt == best_t && pp < best_p))) {
+                        best_t = tt;
+                        best_p = pp;
+                        tcull = tt * kCullScale;
+                    }
+                }
             }
-            if (node == kDone) {
-                oprim[oi] = best_p == INT32_MAX ? -1 : best_p;
-                ot[oi] = best_t;
-                ++traced;
-                have = false;
-                break;
-            }
-            // too few lanes still busy: leave to refill the idle ones
-            if (!exhausted && __popcll(__ballot(true)) <= 64 - a.refill) break;
+            __syncthreads();   // the pair list is rewritten by the next round
+            leaf = kNoLeaf;
+        }
+        if (have && node == kDone) {
+            oprim[oi] = best_p == INT32_MAX ? -1 : best_p;
+            ot[oi] = best_t;
+            ++traced;
+            have = false;
         }
     }
     // per-workgroup count of traced rays (no atomics on a shared counter)

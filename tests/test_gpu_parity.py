@@ -40,9 +40,10 @@ def both(api, orc, name):
     return _cache[name]
 
 
-def gpu_render(api, sc, w, h, spp, B, mode, tile, k, seed, rmax=None, camera=None, refill=0):
-    _say(f"[gpu] render {w}x{h} spp={spp} B={B} mode={mode} tile={tile} k={k} seed={seed} rmax={rmax} refill={refill}")
-    r = api.render(sc, w, h, spp, B, mode, tile, k, rmax, seed, camera, refill=refill)
+def gpu_render(api, sc, w, h, spp, B, mode, tile, k, seed, rmax=None, camera=None, refill=0, leaf_gate=0):
+    _say(f"[gpu] render {w}x{h} spp={spp} B={B} mode={mode} tile={tile} k={k} seed={seed} rmax={rmax} refill={refill} "
+         f"leaf_gate={leaf_gate}")
+    r = api.render(sc, w, h, spp, B, mode, tile, k, rmax, seed, camera, refill=refill, leaf_gate=leaf_gate)
     import torch
     torch.cuda.synchronize()
     return r
@@ -120,6 +121,15 @@ def test_render_parity_refill(api, orc, torch_dev, mode, refill):
     s, sc, osc = both(api, orc, "mixed_small")
     g = gpu_render(api, sc, 83, 61, 1, 3, mode, (8, 8), 8, 41, refill=refill)
     o = osc.render(83, 61, 1, 3, mode=mode, tile=(8, 8), k=8, seed=41)
+    compare_render(g, o, (8, 8), mode)
+
+
+@pytest.mark.parametrize("mode,leaf_gate,refill", [("incoherent", 1, 0), ("reuse", 2, 0), ("reuse", 33, 16),
+                                                   ("sorted", 64, 0), ("incoherent", 64, 64), ("reuse", 8, 1)])
+def test_render_parity_leaf_gate(api, orc, torch_dev, mode, leaf_gate, refill):
+    s, sc, osc = both(api, orc, "mixed_small")
+    g = gpu_render(api, sc, 83, 61, 1, 3, mode, (8, 8), 8, 43, refill=refill, leaf_gate=leaf_gate)
+    o = osc.render(83, 61, 1, 3, mode=mode, tile=(8, 8), k=8, seed=43)
     compare_render(g, o, (8, 8), mode)
 
 
