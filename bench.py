@@ -162,7 +162,60 @@ def cpu_baseline(scene, cfg, name, budget_s=15.0, seed=2310071821):
     return dict(value=sec / dt / 1e6, unit="secondary Mrays/s", cores=1, kind="oracle",
                 sample=f"{n} of {ntx * nty} {tile[0]}x{tile[1]} reuse tiles of the {w}x{h} {name} frame "
                        f"(B={B}), single thread, {dt:.1f} s; BVH build {build_s:.1f} s excluded",
-                seconds=dt)
+                seconds=dt, tiles_per_s=n / dt)
+
+
+def cpu_worker(args):
+    """Child process of the all-cores baseline: the oracle renders tile band `--cpu-part`
+    of `--cpu-parts` (tiles t with t mod parts == part) `--cpu-reps` times from the agreed
+    start time and prints its timing.  Never touches the GPU."""
+    import oracle
+    from paper_2310_07182_amd import scenes
+    cfg = scenes.CONFIGS[args.config]
+    osc = oracle.OracleScene(cfg["scene"]())
+    w, h, B, tile, k = cfg["w"], cfg["h"], cfg["bounces"], tuple(cfg["tile"]), cfg["k"]
+    ntx, nty = (w + tile[0] - 1) // tile[0], (h + tile[1] - 1) // tile[1]
+    mask = (np.arange(ntx * nty) % args.cpu_parts == args.cpu_part).astype(np.uint8)
+    while time.time() < args.cpu_start:
+        time.sleep(0.005)
+    t0 = time.time()
+    rays = 0
+    for rep in range(args.cpu_reps):
+        r = osc.render(w, h, 1, B, mode="reuse", tile=tile, k=k, seed=2310071900 + rep, tile_mask=mask)
+        rays += int(r["rays_per_bounce"][1:].sum())
+    print(json.dumps(dict(t0=t0, t1=time.time(), rays=rays, tiles=int(mask.sum()) * args.cpu_reps)), flush=True)
+
+
+def cpu_baseline_all_cores(cfg, name, single, budget_s=10.0):
+    """The same oracle as independent processes, one per host core, over interleaved tile
+    bands of the frame (no reuse group spans two processes); value = all secondary rays
+    traced / wall time from the first start to the last finish."""
+    import subprocess
+    cores = len(os.sched_getaffinity(0))
+    w, h, tile = cfg["w"], cfg["h"], tuple(cfg["tile"])
+    ntiles = ((w + tile[0] - 1) // tile[0]) * ((h + tile[1] - 1) // tile[1])
+    band = ntiles / cores
+    reps = max(1, int(round(budget_s * single["tiles_per_s"] / band)))
+    start = time.time() + 20.0                         # scene generation and BVH build first
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", "--config", name,
+                               "--cpu-part", str(i), "--cpu-parts", str(cores), "--cpu-reps", str(reps),
+                               "--cpu-start", repr(start)], stdout=subprocess.PIPE, text=True)
+             for i in range(cores)]
+    res = []
+    for p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle worker failed with {p.returncode}")
+        res.append(json.loads(out.strip().splitlines()[-1]))
+    t0, t1 = min(r["t0"] for r in res), max(r["t1"] for r in res)
+    rays = sum(r["rays"] for r in res)
+    late = max(r["t0"] for r in res) - start
+    return dict(value=rays / (t1 - t0) / 1e6, unit="secondary Mrays/s", cores=cores, kind="oracle",
+                sample=f"{cores} oracle processes, one per host core, each rendering an interleaved band of "
+                       f"{int(band)} of the {ntiles} {tile[0]}x{tile[1]} reuse tiles of the {w}x{h} {name} frame "
+                       f"{reps} times (different seeds); {t1 - t0:.1f} s wall from first start to last finish "
+                       f"(latest start {late:+.1f} s after the agreed time); BVH builds excluded",
+                single_core_value=single["value"], single_core_sample=single["sample"])
 
 
 MIX_SCENES = ("tiny", "indoor", "landscape", "mid")
@@ -310,7 +363,15 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--max-jobs", type=int, default=64)
+    ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-part", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-parts", type=int, default=1, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-reps", type=int, default=1, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-start", type=float, default=0.0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker:
+        cpu_worker(args)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {args.gpus}); "
               "run with --gpus 1", file=sys.stderr)
@@ -365,8 +426,11 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle, bounded sample)")
-        cpu = cpu_baseline(scene, cfg, args.config, args.cpu_budget)
-        log(f"[bench] cpu baseline: {cpu}")
+        single = cpu_baseline(scene, cfg, args.config, args.cpu_budget)
+        log(f"[bench] cpu baseline, one core: {single}")
+        log("[bench] cpu baseline on every host core")
+        cpu = cpu_baseline_all_cores(cfg, args.config, single)
+        log(f"[bench] cpu baseline, all cores: {cpu}")
     achieved_ops = head["ops_per_launch"] / (head["avg_trace_launch_ms"] * 1e-3) / 1e12
     achieved_gbs = head["bytes_per_launch"] / (head["avg_trace_launch_ms"] * 1e-3) / 1e9
     line = {
@@ -398,7 +462,8 @@ def main():
                      "ops_per_ray": round(head["ops_per_ray"], 1),
                      "algorithmic_bytes_per_ray": round(head["bytes_per_ray"], 1),
                      "algorithmic_GBps": round(achieved_gbs, 1), "hbm_peak_GBps": HBM_PEAK_GBS},
-        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample",
+                                                                       "single_core_value", "single_core_sample")},
     }
     print(json.dumps(line), flush=True)
 
