@@ -219,6 +219,22 @@ def cpu_baseline_all_cores(cfg, name, single, budget_s=10.0):
 
 
 MIX_SCENES = ("tiny", "indoor", "landscape", "mid")
+MALL_BYTES = 256 << 20          # MI355X Infinity Cache
+
+
+def measure_ceilings(api):
+    """Read bandwidth and dependent-load latency of the level holding a 4 GiB (HBM),
+    128 MiB (MALL) and 2 MiB (L2 of each XCD) buffer, with the library's probe kernels."""
+    import torch
+    buf = torch.empty(4 << 30, dtype=torch.uint8, device="cuda:0")
+    out = {}
+    for level, nbytes, passes, steps in (("hbm", 4 << 30, 3, 20000), ("mall", 128 << 20, 60, 50000),
+                                         ("l2", 2 << 20, 4000, 100000)):
+        r = api.probe_memory(nbytes, passes, steps, buf)
+        out[level] = {"bytes": nbytes, "read_GBps": round(r["read_gbps"], 1), "dependent_load_ns": round(r["chase_ns"], 1)}
+    del buf
+    torch.cuda.empty_cache()
+    return out
 
 
 def load_scenes(api, scenes, names):
@@ -423,6 +439,10 @@ def main():
         results[mode] = bench_mode(api, sc, cfg, mode, args.steps, args.warmup, 2310071821 + 100000 * i)
         log(f"[bench] {mode}: {json.dumps(results[mode])}")
     head = results.get("reuse") or next(iter(results.values()))
+    log("[bench] memory ceilings")
+    ceil = measure_ceilings(api)
+    log(f"[bench] ceilings: {ceil}")
+    level = "mall" if sc.arena.numel() <= MALL_BYTES else "hbm"
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle, bounded sample)")
@@ -461,7 +481,10 @@ def main():
                      "op": "32-bit VALU lane operation (compare/min/max/select counted like add/mul)",
                      "ops_per_ray": round(head["ops_per_ray"], 1),
                      "algorithmic_bytes_per_ray": round(head["bytes_per_ray"], 1),
-                     "algorithmic_GBps": round(achieved_gbs, 1), "hbm_peak_GBps": HBM_PEAK_GBS},
+                     "algorithmic_GBps": round(achieved_gbs, 1), "hbm_peak_GBps": HBM_PEAK_GBS,
+                     "working_set_level": level, "measured_ceiling_GBps": ceil[level]["read_GBps"],
+                     "algorithmic_frac_of_measured_ceiling": round(achieved_gbs / ceil[level]["read_GBps"], 4)},
+        "ceilings": ceil,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample",
                                                                        "single_core_value", "single_core_sample")},
     }

@@ -242,6 +242,21 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor):
     return keys, vals
 
 
+def probe_memory(nbytes: int, passes: int, chase_steps: int, buf: "torch.Tensor | None" = None,
+                 device="cuda:0") -> dict:
+    """Read bandwidth (GB/s) and dependent-load latency (ns) of the memory level that
+    holds a buffer of nbytes (pt_probe_memory); buf: optional scratch of >= nbytes."""
+    dev = _require_cuda(device)
+    with torch.cuda.device(dev):
+        if buf is None:
+            buf = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        assert buf.numel() >= nbytes
+        g, ns = C.c_float(), C.c_float()
+        check(lib().pt_probe_memory(buf.data_ptr(), int(nbytes), int(passes), int(chase_steps), C.byref(g),
+                                    C.byref(ns), _stream_handle(dev)))
+    return dict(bytes=int(nbytes), read_gbps=g.value, chase_ns=ns.value)
+
+
 def device_info():
     cu, ma, mi = C.c_int32(), C.c_int32(), C.c_int32()
     check(lib().pt_device_info(C.byref(cu), C.byref(ma), C.byref(mi)))

@@ -9,7 +9,7 @@ LIB = os.path.join(HERE, "libpt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "capi.hip", "bvh_build.cpp"]
+SOURCES = ["kernels.hip", "probe.hip", "capi.hip", "bvh_build.cpp"]
 
 # -ffp-contract=off: the ray chain is binary32 without FMA contraction (host and device).
 # -packed-fp32-ops off: no packed FP32 instructions are generated.

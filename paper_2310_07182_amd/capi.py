@@ -64,6 +64,7 @@ class Job(C.Structure):
 # name -> (restype, argtypes); the full list of exported entry points
 _vp, _sz, _u32, _i32, _st = C.c_void_p, C.c_size_t, C.c_uint32, C.c_int, C.c_int32
 PROTOTYPES = {
+    "pt_probe_memory": (_st, [_vp, _sz, C.c_int32, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float), _vp]),
     "pt_scene_create": (_st, [C.POINTER(SceneDesc), C.POINTER(_vp)]),
     "pt_scene_device_bytes": (_sz, [_vp]),
     "pt_scene_upload": (_st, [_vp, _vp, _sz, _vp]),

@@ -236,6 +236,44 @@ struct TimerScope {
 
 extern "C" {
 
+pt_status pt_probe_memory(void* buf, size_t bytes, int passes, int chase_steps, float* read_gbps, float* chase_ns,
+                          void* stream) {
+    if (!buf || !read_gbps || !chase_ns) return fail(PT_EINVAL, "null argument");
+    if (((uintptr_t)buf & 255) != 0) return fail(PT_EINVAL, "buffer must be 256-byte aligned");
+    if (bytes < (64u << 10)) return fail(PT_EINVAL, "buffer must hold at least 64 KiB (got %zu)", bytes);
+    if (passes < 1 || passes > (1 << 24) || chase_steps < 1 || chase_steps > (1 << 24))
+        return fail(PT_EINVAL, "passes and chase_steps must be in [1, 2^24]");
+    hipStream_t st = (hipStream_t)stream;
+    size_t lines = bytes / 128;
+    if (lines > (1ull << 31)) lines = 1ull << 31;
+    uint32_t nlines = 1;
+    while ((size_t)nlines * 2 <= lines) nlines *= 2;
+    uint32_t* words = (uint32_t*)buf;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto& x : ev)
+                if (x) (void)hipEventDestroy(x);
+            return fail(PT_EDEVICE, "hipEventCreate failed");
+        }
+    hipError_t e = pt::launch_probe_fill(words, nlines, st);
+    if (e == hipSuccess) e = pt::launch_probe_read(buf, bytes, 1, words + 1, st);   // warm the level
+    if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+    if (e == hipSuccess) e = pt::launch_probe_read(buf, bytes, passes, words + 1, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+    if (e == hipSuccess) e = pt::launch_probe_chase(words, nlines, chase_steps, words + 2, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[2], st);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
+    float ms_read = 0.f, ms_chase = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms_read, ev[0], ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms_chase, ev[1], ev[2]);
+    for (auto& x : ev) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(e, "memory probe");
+    *read_gbps = (float)((double)(bytes / 16) * 16.0 * passes / (ms_read * 1e-3) / 1e9);
+    *chase_ns = (float)(ms_chase * 1e6 / chase_steps);
+    return PT_OK;
+}
+
 const char* pt_last_error(void) { return g_err.c_str(); }
 
 pt_status pt_device_info(int* compute_units, int* arch_major, int* arch_minor) {

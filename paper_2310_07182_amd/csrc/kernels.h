@@ -89,6 +89,10 @@ hipError_t launch_trace_multi(const StepJob* jobs, int njobs, const TraceArgs& a
 hipError_t launch_raygen_multi(const StepJob* jobs, int njobs, uint32_t total_blocks, int TS, hipStream_t st);
 hipError_t launch_shade_multi(const StepJob* jobs, int njobs, uint32_t total_blocks, int TS, bool reuse,
                               hipStream_t st);
+// memory-level probe (probe.hip)
+hipError_t launch_probe_fill(uint32_t* buf, uint32_t nlines, hipStream_t st);
+hipError_t launch_probe_read(const void* buf, size_t bytes, int passes, uint32_t* sink, hipStream_t st);
+hipError_t launch_probe_chase(const uint32_t* buf, uint32_t nlines, int steps, uint32_t* sink, hipStream_t st);
 hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t st);
 hipError_t launch_raygen(const Frame& f, int s, float4* q, float4* state, float4* rays_out, hipStream_t st);
 hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const float4* q_in, float4* q_out,

@@ -188,3 +188,22 @@ def test_render_rejects_before_touching_device(L):
     assert st == capi.PT_EINVAL
     assert L.pt_render(None, C.byref(cam), 8, 8, 1, 1, 0, _group(4, 4, 2), 1, None, 0, C.byref(out), None) == capi.PT_EINVAL
     L.pt_scene_free(h)
+
+
+def test_group_leaf_gate_checked(L):
+    g = _group(8, 8, 8)
+    g.leaf_gate = 65
+    j = capi.Job()
+    j.w, j.h, j.spp, j.bounces, j.mode = 64, 64, 1, 2, capi.MODES["reuse"]
+    assert L.pt_batch_job_bytes(C.byref(j), g) == 0
+    g.leaf_gate = 64
+    assert L.pt_batch_job_bytes(C.byref(j), g) > 0
+
+
+def test_probe_rejects_before_touching_device(L):
+    g, ns = C.c_float(), C.c_float()
+    assert L.pt_probe_memory(None, 1 << 20, 1, 1, C.byref(g), C.byref(ns), None) == capi.PT_EINVAL
+    assert L.pt_probe_memory(C.c_void_p(256), 1024, 1, 1, C.byref(g), C.byref(ns), None) == capi.PT_EINVAL
+    assert L.pt_probe_memory(C.c_void_p(257), 1 << 20, 1, 1, C.byref(g), C.byref(ns), None) == capi.PT_EINVAL
+    assert L.pt_probe_memory(C.c_void_p(256), 1 << 20, 0, 1, C.byref(g), C.byref(ns), None) == capi.PT_EINVAL
+    assert L.pt_probe_memory(C.c_void_p(256), 1 << 20, 1, 1 << 25, C.byref(g), C.byref(ns), None) == capi.PT_EINVAL
