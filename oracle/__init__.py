@@ -12,7 +12,7 @@ import numpy as np
 
 from .build import LIB, build
 
-MODE = {"incoherent": 0, "sorted": 1, "reuse": 2}
+MODE = {"incoherent": 0, "sorted": 1, "reuse": 2, "sorted_origin": 3, "sorted_reis": 4, "sorted_aila": 5}
 
 F_ACTIVE = 1 << 0
 F_CLASS_SH = 1
@@ -67,6 +67,8 @@ def lib():
         L.orc_shuffle.argtypes = [i32, C.c_uint64, C.c_uint64, vp]
         L.orc_ray_key.restype = u32
         L.orc_ray_key.argtypes = [vp, vp, vp, vp]
+        L.orc_ray_key_kind.restype = u32
+        L.orc_ray_key_kind.argtypes = [C.c_int, vp, vp, vp, vp]
         L.orc_camera_ray.argtypes = [vp, i32, i32, i32, i32, f, f, vp, vp]
         _lib = L
     return _lib
@@ -219,9 +221,12 @@ def shuffle(wh, x0, x1):
     return s
 
 
-def ray_key(lo, hi, o, d):
+def ray_key(lo, hi, o, d, kind="sorted"):
+    """Reordering key of one ray; kind = one of the sorted modes ("sorted" = TwoPoint)."""
     a = [np.ascontiguousarray(v, dtype=np.float32) for v in (lo, hi, o, d)]
-    return int(lib().orc_ray_key(*[_p(v) for v in a]))
+    if kind == "sorted":
+        return int(lib().orc_ray_key(*[_p(v) for v in a]))
+    return int(lib().orc_ray_key_kind(MODE[kind], *[_p(v) for v in a]))
 
 
 def camera_ray(cam: dict, w, h, x, y, u0, u1):

@@ -678,34 +678,76 @@ void orc_shuffle(int wh, uint64_t x0, uint64_t x1, uint32_t* slot)
 }
 
 /* ------------------------------------------------------------------------
- * Sorted baseline key: two-point Morton code (origin and the point at a fixed
- * length of 0.25 times the largest scene extent, Section 4), 5 bits per
- * coordinate, interleaved most significant bit first in the order
- * ox, oy, oz, ex, ey, ez.  Pin: bit-by-bit rebuild in the test suite.
+ * Keys of the reordering baselines (Section 4 names the methods; Section 2.1
+ * says what each encodes).  A coordinate x in [lo, lo + ext] is quantized to
+ * nb bits as floor(((x - lo) / ext) * 2^nb), clamped to [0, 2^nb - 1] (NaN and
+ * values below lo give 0); a direction component d in [-1, 1] is quantized the
+ * same way with lo = -1, ext = 2.  Bits are interleaved most significant first.
+ *   TwoPoint: origin and the point at a fixed length of 0.25 times the largest
+ *     scene extent, 5 bits per coordinate, order ox oy oz ex ey ez (30 bits).
+ *   Origin: origin only, 10 bits per coordinate, order ox oy oz (30 bits).
+ *   Reis: origin in the high bits (6 bits per coordinate, interleaved), then the
+ *     direction (4 bits per component, interleaved): 18 + 12 bits.
+ *   Aila: origin and direction bits interleaved, 5 bits per value, order
+ *     ox oy oz dx dy dz (30 bits).
+ * Pin: bit-by-bit rebuild of every kind in the test suite.
  * ---------------------------------------------------------------------- */
-static uint32_t quant5(float x, float lo, float ext)
+static uint32_t quant(float x, float lo, float ext, int nb)
 {
     if (!(ext > 0.0f)) return 0;
-    float f = ((x - lo) / ext) * 32.0f;
+    const float top = (float)(1u << nb);
+    float f = ((x - lo) / ext) * top;
     if (!(f > 0.0f)) return 0;    /* also maps NaN to 0 */
-    if (f >= 31.0f) return 31;
+    if (f >= top - 1.0f) return (1u << nb) - 1u;
     return (uint32_t)f;
+}
+
+/* interleave the low nb bits of n values, most significant bit first */
+static uint32_t interleave(const uint32_t* q, int n, int nb)
+{
+    uint32_t key = 0;
+    for (int bit = nb - 1; bit >= 0; --bit)
+        for (int c = 0; c < n; ++c) key = (key << 1) | ((q[c] >> bit) & 1u);
+    return key;
+}
+
+uint32_t orc_ray_key_kind(int kind, const float lo[3], const float hi[3], const float o[3], const float d[3])
+{
+    float ext[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+    uint32_t q[6];
+    switch (kind) {
+    case ORC_MODE_SORTED_ORIGIN:
+        for (int a = 0; a < 3; ++a) q[a] = quant(o[a], lo[a], ext[a], 10);
+        return interleave(q, 3, 10);
+    case ORC_MODE_SORTED_REIS: {
+        uint32_t qd[3];
+        for (int a = 0; a < 3; ++a) { q[a] = quant(o[a], lo[a], ext[a], 6); qd[a] = quant(d[a], -1.0f, 2.0f, 4); }
+        return (interleave(q, 3, 6) << 12) | interleave(qd, 3, 4);
+    }
+    case ORC_MODE_SORTED_AILA:
+        for (int a = 0; a < 3; ++a) { q[a] = quant(o[a], lo[a], ext[a], 5); q[3 + a] = quant(d[a], -1.0f, 2.0f, 5); }
+        return interleave(q, 6, 5);
+    default: {   /* TwoPoint */
+        float mx = ext[0];
+        if (ext[1] > mx) mx = ext[1];
+        if (ext[2] > mx) mx = ext[2];
+        float L = 0.25f * mx;
+        float e[3] = {o[0] + L * d[0], o[1] + L * d[1], o[2] + L * d[2]};
+        for (int a = 0; a < 3; ++a) { q[a] = quant(o[a], lo[a], ext[a], 5); q[3 + a] = quant(e[a], lo[a], ext[a], 5); }
+        return interleave(q, 6, 5);
+    }
+    }
 }
 
 uint32_t orc_ray_key(const float lo[3], const float hi[3], const float o[3], const float d[3])
 {
-    float ext[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
-    float mx = ext[0];
-    if (ext[1] > mx) mx = ext[1];
-    if (ext[2] > mx) mx = ext[2];
-    float L = 0.25f * mx;
-    float e[3] = {o[0] + L * d[0], o[1] + L * d[1], o[2] + L * d[2]};
-    uint32_t q[6];
-    for (int a = 0; a < 3; ++a) { q[a] = quant5(o[a], lo[a], ext[a]); q[3 + a] = quant5(e[a], lo[a], ext[a]); }
-    uint32_t key = 0;
-    for (int bit = 4; bit >= 0; --bit)
-        for (int c = 0; c < 6; ++c) key = (key << 1) | ((q[c] >> bit) & 1u);
-    return key;
+    return orc_ray_key_kind(ORC_MODE_SORTED, lo, hi, o, d);
+}
+
+static int is_sorted_mode(int mode)
+{
+    return mode == ORC_MODE_SORTED || mode == ORC_MODE_SORTED_ORIGIN || mode == ORC_MODE_SORTED_REIS ||
+           mode == ORC_MODE_SORTED_AILA;
 }
 
 /* ------------------------------------------------------------------------
@@ -763,7 +805,7 @@ int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp,
 {
     if (w <= 0 || h <= 0 || spp <= 0 || B < 0 || W <= 0 || H <= 0 || K <= 0) return -1;
     if ((W & (W - 1)) || (H & (H - 1)) || (K & (K - 1)) || K > W * H || W * H > 65536) return -1;
-    if (mode < 0 || mode > 2) return -1;
+    if (mode < 0 || mode > 5) return -1;
     const int WH = W * H;
     const int ntx = (w + W - 1) / W, nty = (h + H - 1) / H;
     const size_t npix = (size_t)w * (size_t)h;
@@ -829,11 +871,11 @@ int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp,
             size_t nl = 0;
             for (size_t i = 0; i < npix; ++i)
                 if (P[i].alive) list[nl++] = (uint32_t)i;
-            if (mode == ORC_MODE_SORTED && b >= 1) {
+            if (is_sorted_mode(mode) && b >= 1) {
                 for (size_t j = 0; j < nl; ++j) {
                     opath* p = &P[list[j]];
                     float o[3] = {p->o.x, p->o.y, p->o.z}, d[3] = {p->d.x, p->d.y, p->d.z};
-                    ki[j].key = orc_ray_key(s->lo, s->hi, o, d);
+                    ki[j].key = orc_ray_key_kind(mode, s->lo, s->hi, o, d);
                     ki[j].idx = list[j];
                 }
                 qsort(ki, nl, sizeof(keyidx), cmp_keyidx);
@@ -981,7 +1023,7 @@ int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp,
                 p->excl = p->prim;
                 if (out->dbg_keys) {
                     float o[3] = {p->o.x, p->o.y, p->o.z}, d[3] = {nd.x, nd.y, nd.z};
-                    out->dbg_keys[at] = orc_ray_key(s->lo, s->hi, o, d);
+                    out->dbg_keys[at] = orc_ray_key_kind(is_sorted_mode(mode) ? mode : ORC_MODE_SORTED, s->lo, s->hi, o, d);
                 }
             }
         }

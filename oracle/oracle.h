@@ -51,7 +51,8 @@ typedef struct {
     uint64_t* rays_per_bounce;/* [B+1] */
 } orc_outputs;
 
-enum { ORC_MODE_INCOHERENT = 0, ORC_MODE_SORTED = 1, ORC_MODE_REUSE = 2 };
+enum { ORC_MODE_INCOHERENT = 0, ORC_MODE_SORTED = 1, ORC_MODE_REUSE = 2, ORC_MODE_SORTED_ORIGIN = 3,
+       ORC_MODE_SORTED_REIS = 4, ORC_MODE_SORTED_AILA = 5 };
 
 /* debug flag bits for the ray generated at hit b (ray index b+1) */
 #define ORC_F_ACTIVE   (1 << 0)     /* the path scatters at this hit */
@@ -87,6 +88,8 @@ int orc_sample_ggx(const float wi[3], float alpha, const float f0[3], float u2, 
 void orc_offset_origin(const float p[3], const float n[3], float out[3]);
 void orc_shuffle(int wh, uint64_t x0, uint64_t x1, uint32_t* slot);
 uint32_t orc_ray_key(const float lo[3], const float hi[3], const float o[3], const float d[3]);
+/* key of one of the sorted modes (ORC_MODE_SORTED = TwoPoint, _ORIGIN, _REIS, _AILA) */
+uint32_t orc_ray_key_kind(int kind, const float lo[3], const float hi[3], const float o[3], const float d[3]);
 void orc_camera_ray(const orc_camera* cam, int w, int h, int x, int y, float u0, float u1,
                     float o[3], float d[3]);
 

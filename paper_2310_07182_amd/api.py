@@ -221,12 +221,15 @@ def trace(scene: Scene, rays: torch.Tensor, refill: int = 0):
     return prim, t
 
 
-def ray_keys(scene: Scene, rays: torch.Tensor) -> torch.Tensor:
+def ray_keys(scene: Scene, rays: torch.Tensor, mode: str = "sorted") -> torch.Tensor:
+    """Reordering keys of a sorted mode ("sorted" = TwoPoint, "sorted_origin", "sorted_reis",
+    "sorted_aila"); int32 tensor holding the uint32 keys."""
     assert rays.dtype == torch.float32 and rays.is_contiguous() and rays.shape[-1] == 8
     dev = scene.device
     keys = torch.empty(rays.shape[0], dtype=torch.int32, device=dev)
     with torch.cuda.device(dev):
-        check(lib().pt_ray_keys(scene.handle, rays.data_ptr(), rays.shape[0], keys.data_ptr(), _stream_handle(dev)))
+        check(lib().pt_ray_keys(scene.handle, rays.data_ptr(), rays.shape[0], capi.MODES[mode], keys.data_ptr(),
+                                _stream_handle(dev)))
     return keys
 
 

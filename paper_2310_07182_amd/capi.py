@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpt.so")
 
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_EUNSUPPORTED, PT_EBUSY = 0, -1, -2, -3, -4, -5
-MODES = {"incoherent": 0, "sorted": 1, "reuse": 2}
+MODES = {"incoherent": 0, "sorted": 1, "reuse": 2, "sorted_origin": 3, "sorted_reis": 4, "sorted_aila": 5}
 TIMER_KINDS = {0: "trace", 1: "raygen", 2: "shade", 3: "key", 4: "sort", 5: "gather", 6: "other"}
 
 
@@ -76,7 +76,7 @@ PROTOTYPES = {
                         C.POINTER(Outputs), _vp]),
     "pt_trace_workspace_bytes": (_sz, []),
     "pt_trace": (_st, [_vp, _vp, _u32, _i32, _vp, _vp, _vp, _sz, _vp]),
-    "pt_ray_keys": (_st, [_vp, _vp, _u32, _vp, _vp]),
+    "pt_ray_keys": (_st, [_vp, _vp, _u32, C.c_int, _vp, _vp]),
     "pt_sort_workspace_bytes": (_sz, [_u32]),
     "pt_sort_pairs": (_st, [_vp, _vp, _u32, _vp, _sz, _vp]),
     "pt_timer_create": (_st, [_i32, C.POINTER(_vp)]),

@@ -93,6 +93,11 @@ pt_status hip_fail(hipError_t e, const char* what) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+bool is_sorted_mode(int mode) {
+    return mode == PT_MODE_SORTED || mode == PT_MODE_SORTED_ORIGIN || mode == PT_MODE_SORTED_REIS ||
+           mode == PT_MODE_SORTED_AILA;
+}
+
 constexpr int kDefaultRefill = 48;
 
 bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
@@ -199,7 +204,7 @@ Layout layout(const Frame& f) {
     o = align256(o + launches * 4);
     L.partial = o;
     o = align256(o + launches * pt::kMaxTraceBlocks * 4);
-    if (f.mode == PT_MODE_SORTED) {
+    if (is_sorted_mode(f.mode)) {
         L.keys = o;
         o = align256(o + (size_t)f.nslots * 4);
         L.vals = o;
@@ -454,7 +459,7 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
     if (w <= 0 || h <= 0 || spp <= 0) return fail(PT_EINVAL, "w, h, spp must be >= 1 (got %d, %d, %d)", w, h, spp);
     if (B < 0 || B > 64) return fail(PT_EINVAL, "bounces must be in [0, 64] (got %d)", B);
     if ((long long)w * (long long)h > (1ll << 30)) return fail(PT_EINVAL, "image too large");
-    if (mode != PT_MODE_INCOHERENT && mode != PT_MODE_SORTED && mode != PT_MODE_REUSE)
+    if (mode != PT_MODE_INCOHERENT && mode != PT_MODE_REUSE && !is_sorted_mode(mode))
         return fail(PT_EINVAL, "unknown mode %d", (int)mode);
     pt_status cs = check_group(g, B);
     if (cs != PT_OK) return cs;
@@ -466,7 +471,8 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
     if (dev != scene->device) return fail(PT_EINVAL, "scene was uploaded on device %d, current device is %d", scene->device, dev);
 
     Frame f = make_frame(w, h, spp, B, mode, g, seed);
-    if (mode == PT_MODE_SORTED && f.nslots > (1u << 27)) return fail(PT_EINVAL, "sorted mode supports at most 2^27 rays per bounce");
+    if (is_sorted_mode(mode) && f.nslots > (1u << 27))
+        return fail(PT_EINVAL, "sorted modes support at most 2^27 rays per bounce");
     const Layout L = layout(f);
     if (ws_bytes < L.total) return fail(PT_ENOMEM, "workspace too small: %zu < %zu", ws_bytes, L.total);
     set_camera(f, cam, w, h);
@@ -497,13 +503,13 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
             const size_t li = (size_t)b * spp + s;
             const float4* tq = q[b & 1];
             const uint32_t n = f.nslots;
-            if (mode == PT_MODE_SORTED && b >= 1) {
+            if (is_sorted_mode(mode) && b >= 1) {
                 uint32_t* keys = (uint32_t*)(ws + L.keys);
                 uint32_t* vals = (uint32_t*)(ws + L.vals);
                 float4* qs = (float4*)(ws + L.qs);
                 {
                     TimerScope ts(out->timer, st, 3, b);
-                    e = pt::launch_keys(scene->dev, q[b & 1], f.nslots, keys, vals, st);
+                    e = pt::launch_keys(scene->dev, q[b & 1], f.nslots, keys, vals, (int)mode, st);
                 }
                 if (e != hipSuccess) return hip_fail(e, "launch (keys)");
                 {
@@ -581,11 +587,12 @@ pt_status pt_trace(pt_scene scene, const float* rays, uint32_t n, int refill, in
     return PT_OK;
 }
 
-pt_status pt_ray_keys(pt_scene scene, const float* rays, uint32_t n, uint32_t* keys, void* stream) {
+pt_status pt_ray_keys(pt_scene scene, const float* rays, uint32_t n, pt_mode mode, uint32_t* keys, void* stream) {
     if (!scene || (n > 0 && (!rays || !keys))) return fail(PT_EINVAL, "null argument");
     if (!scene->uploaded) return fail(PT_EINVAL, "scene not uploaded");
+    if (!is_sorted_mode(mode)) return fail(PT_EINVAL, "mode %d is not a sorted mode", (int)mode);
     if (n == 0) return PT_OK;
-    hipError_t e = pt::launch_keys(scene->dev, (const float4*)rays, n, keys, nullptr, (hipStream_t)stream);
+    hipError_t e = pt::launch_keys(scene->dev, (const float4*)rays, n, keys, nullptr, (int)mode, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launch (keys)");
     return PT_OK;
 }

@@ -98,7 +98,7 @@ hipError_t launch_raygen(const Frame& f, int s, float4* q, float4* state, float4
 hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const float4* q_in, float4* q_out,
                         float4* state, int32_t* hit_prim, float* hit_t, float* radiance, float4* rays_out,
                         hipStream_t st);
-hipError_t launch_keys(const DevScene& sc, const float4* q, uint32_t n, uint32_t* keys, uint32_t* vals,
+hipError_t launch_keys(const DevScene& sc, const float4* q, uint32_t n, uint32_t* keys, uint32_t* vals, int kind,
                        hipStream_t st);
 // ray_count[i] = sum of partial[i * stride + j] for j < parts, i < launches
 hipError_t launch_count_finalize(const uint32_t* partial, int stride, int parts, int launches, uint32_t* ray_count,

@@ -753,16 +753,19 @@ __global__ __launch_bounds__(1024) void k_shade_multi(const StepJob* jobs, int n
 }
 
 // ------------------------------------------------------------------ two-point key, gather
-__device__ __forceinline__ uint32_t q5(float x, float lo, float ext) {
+// nb-bit quantization of x over [lo, lo + ext]: floor(((x - lo) / ext) * 2^nb), clamped
+__device__ __forceinline__ uint32_t qbits(float x, float lo, float ext, int nb) {
     if (!(ext > 0.0f)) return 0u;
-    const float f = ((x - lo) / ext) * 32.0f;
+    const float top = (float)(1u << nb);
+    const float f = ((x - lo) / ext) * top;
     if (!(f > 0.0f)) return 0u;
-    if (f >= 31.0f) return 31u;
+    if (f >= top - 1.0f) return (1u << nb) - 1u;
     return (uint32_t)f;
 }
 
+// 30-bit reordering keys of the sorted modes (bits interleaved most significant first)
 __global__ __launch_bounds__(256) void k_keys(DevScene sc, const float4* q, uint32_t n, uint32_t* keys,
-                                              uint32_t* vals) {
+                                              uint32_t* vals, int kind) {
     const uint32_t j = blockIdx.x * 256u + threadIdx.x;
     if (j < n) {
         const float4 r0 = q[2 * (size_t)j], r1 = q[2 * (size_t)j + 1];
@@ -770,18 +773,50 @@ __global__ __launch_bounds__(256) void k_keys(DevScene sc, const float4* q, uint
         uint32_t key = 0xFFFFFFFFu;
         if (live) {
             const float ex = sc.hi[0] - sc.lo[0], ey = sc.hi[1] - sc.lo[1], ez = sc.hi[2] - sc.lo[2];
-            float mx = ex;
-            if (ey > mx) mx = ey;
-            if (ez > mx) mx = ez;
-            const float len = 0.25f * mx;
-            const uint32_t qc[6] = {q5(r0.x, sc.lo[0], ex), q5(r0.y, sc.lo[1], ey), q5(r0.z, sc.lo[2], ez),
-                                    q5(r0.x + len * r1.x, sc.lo[0], ex), q5(r0.y + len * r1.y, sc.lo[1], ey),
-                                    q5(r0.z + len * r1.z, sc.lo[2], ez)};
             key = 0;
+            if (kind == PT_MODE_SORTED_ORIGIN) {
+                const uint32_t qc[3] = {qbits(r0.x, sc.lo[0], ex, 10), qbits(r0.y, sc.lo[1], ey, 10),
+                                        qbits(r0.z, sc.lo[2], ez, 10)};
 #pragma unroll
-            for (int bit = 4; bit >= 0; --bit)
+                for (int bit = 9; bit >= 0; --bit)
 #pragma unroll
-                for (int c = 0; c < 6; ++c) key = (key << 1) | ((qc[c] >> bit) & 1u);
+                    for (int c = 0; c < 3; ++c) key = (key << 1) | ((qc[c] >> bit) & 1u);
+            } else if (kind == PT_MODE_SORTED_REIS) {
+                const uint32_t qo[3] = {qbits(r0.x, sc.lo[0], ex, 6), qbits(r0.y, sc.lo[1], ey, 6),
+                                        qbits(r0.z, sc.lo[2], ez, 6)};
+                const uint32_t qd[3] = {qbits(r1.x, -1.0f, 2.0f, 4), qbits(r1.y, -1.0f, 2.0f, 4),
+                                        qbits(r1.z, -1.0f, 2.0f, 4)};
+#pragma unroll
+                for (int bit = 5; bit >= 0; --bit)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) key = (key << 1) | ((qo[c] >> bit) & 1u);
+#pragma unroll
+                for (int bit = 3; bit >= 0; --bit)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) key = (key << 1) | ((qd[c] >> bit) & 1u);
+            } else {
+                uint32_t qc[6];
+                if (kind == PT_MODE_SORTED_AILA) {
+                    qc[3] = qbits(r1.x, -1.0f, 2.0f, 5);
+                    qc[4] = qbits(r1.y, -1.0f, 2.0f, 5);
+                    qc[5] = qbits(r1.z, -1.0f, 2.0f, 5);
+                } else {   // TwoPoint: the point at a fixed length of 0.25 x the largest extent
+                    float mx = ex;
+                    if (ey > mx) mx = ey;
+                    if (ez > mx) mx = ez;
+                    const float len = 0.25f * mx;
+                    qc[3] = qbits(r0.x + len * r1.x, sc.lo[0], ex, 5);
+                    qc[4] = qbits(r0.y + len * r1.y, sc.lo[1], ey, 5);
+                    qc[5] = qbits(r0.z + len * r1.z, sc.lo[2], ez, 5);
+                }
+                qc[0] = qbits(r0.x, sc.lo[0], ex, 5);
+                qc[1] = qbits(r0.y, sc.lo[1], ey, 5);
+                qc[2] = qbits(r0.z, sc.lo[2], ez, 5);
+#pragma unroll
+                for (int bit = 4; bit >= 0; --bit)
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) key = (key << 1) | ((qc[c] >> bit) & 1u);
+            }
         }
         keys[j] = key;
         if (vals) vals[j] = j;
@@ -1045,10 +1080,10 @@ hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const 
     return hipGetLastError();
 }
 
-hipError_t launch_keys(const DevScene& sc, const float4* q, uint32_t n, uint32_t* keys, uint32_t* vals,
+hipError_t launch_keys(const DevScene& sc, const float4* q, uint32_t n, uint32_t* keys, uint32_t* vals, int kind,
                        hipStream_t st) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_keys, dim3((n + 255) / 256), dim3(256), 0, st, sc, q, n, keys, vals);
+    hipLaunchKernelGGL(k_keys, dim3((n + 255) / 256), dim3(256), 0, st, sc, q, n, keys, vals, kind);
     return hipGetLastError();
 }
 

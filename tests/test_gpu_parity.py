@@ -172,7 +172,8 @@ def test_bounces_zero_and_empty_scene(api, orc, torch_dev):
 
 
 # ------------------------------------------------------------------ sorted-mode kernels alone
-def test_ray_keys_parity(api, orc, torch_dev):
+@pytest.mark.parametrize("kind", ["sorted", "sorted_origin", "sorted_reis", "sorted_aila"])
+def test_ray_keys_parity(api, orc, torch_dev, kind):
     s, sc, osc = both(api, orc, "mixed_small")
     lo, hi = osc.bounds()
     rng = np.random.default_rng(4)
@@ -180,11 +181,22 @@ def test_ray_keys_parity(api, orc, torch_dev):
     o = rng.uniform(lo - 1.0, hi + 1.0, (n, 3)).astype(np.float32)
     d = rng.normal(size=(n, 3))
     d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    d[0] = (1.0, -1.0, 0.0)
     rays = orc.pack_rays(o, d)
-    _say(f"[gpu] keys n={n}")
-    keys = api.ray_keys(sc, torch_dev.from_numpy(rays).cuda()).cpu().numpy().view(np.uint32)
-    ref = np.array([orc.ray_key(lo, hi, o[i], d[i]) for i in range(n)], np.uint32)
+    rays[5, 7] = np.uint32(0xFFFFFFFF).view(np.float32)        # a dead ray
+    _say(f"[gpu] keys {kind} n={n}")
+    keys = api.ray_keys(sc, torch_dev.from_numpy(rays).cuda(), kind).cpu().numpy().view(np.uint32)
+    ref = np.array([orc.ray_key(lo, hi, o[i], d[i], kind) for i in range(n)], np.uint32)
+    ref[5] = 0xFFFFFFFF
     assert np.array_equal(keys, ref)
+
+
+@pytest.mark.parametrize("mode", ["sorted_origin", "sorted_reis", "sorted_aila"])
+def test_render_parity_other_sorted_modes(api, orc, torch_dev, mode):
+    s, sc, osc = both(api, orc, "mixed_small")
+    g = gpu_render(api, sc, 101, 67, 2, 4, mode, (8, 8), 8, 77)
+    o = osc.render(101, 67, 2, 4, mode=mode, tile=(8, 8), k=8, seed=77)
+    compare_render(g, o, (8, 8), mode)
 
 
 @pytest.mark.parametrize("n", [1, 17, 2048, 2049, 100003, 2100000])

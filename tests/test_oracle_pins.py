@@ -310,6 +310,64 @@ def test_ray_key_matches_bitwise_rebuild(orc):
         assert key < 2 ** 30
 
 
+def _q(x, lo, ext, nb):
+    # floor(((x - lo) / ext) * 2^nb) in float32, clamped to [0, 2^nb - 1]
+    f = (np.float32(x) - np.float32(lo)) / np.float32(ext) * np.float32(2 ** nb)
+    return int(min(2 ** nb - 1, max(0, np.floor(f))))
+
+
+def _bits_of(qs, nb):
+    return "".join(str((qq >> b) & 1) for b in range(nb - 1, -1, -1) for qq in qs)
+
+
+@pytest.mark.parametrize("kind", ["sorted_origin", "sorted_reis", "sorted_aila"])
+def test_other_keys_match_bitwise_rebuild(orc, kind):
+    lo = np.array([-3.0, 0.0, 1.0], np.float32)
+    hi = np.array([17.0, 8.0, 41.0], np.float32)
+    ext = hi - lo
+    rng = np.random.default_rng(5)
+    for i in range(400):
+        o = rng.uniform(lo - 0.5, hi + 0.5).astype(np.float32)   # also outside the box: clamped
+        d = rng.normal(size=3)
+        d = (d / np.linalg.norm(d)).astype(np.float32)
+        if i == 0:
+            d = np.array([1.0, -1.0, 0.0], np.float32)           # components at the ends of [-1, 1]
+        key = orc.ray_key(lo, hi, o, d, kind)
+        if kind == "sorted_origin":
+            want = _bits_of([_q(o[a], lo[a], ext[a], 10) for a in range(3)], 10)
+        elif kind == "sorted_reis":
+            want = (_bits_of([_q(o[a], lo[a], ext[a], 6) for a in range(3)], 6)
+                    + _bits_of([_q(d[a], -1.0, 2.0, 4) for a in range(3)], 4))
+        else:
+            want = _bits_of([_q(o[a], lo[a], ext[a], 5) for a in range(3)] + [_q(d[a], -1.0, 2.0, 5) for a in range(3)], 5)
+        assert key == int(want, 2), (kind, o, d)
+        assert key < 2 ** 30
+
+
+@pytest.mark.parametrize("kind", ["sorted_origin", "sorted_reis", "sorted_aila"])
+def test_other_sorted_modes_equal_incoherent(orc, kind):
+    # reordering changes only the order in which rays are traced
+    s = scenes.mixed_small()
+    sc = orc.OracleScene(s)
+    a = sc.render(40, 28, 1, 3, mode="incoherent", seed=3)
+    b = sc.render(40, 28, 1, 3, mode=kind, seed=3, debug=True)
+    for key in ("radiance", "hit_prim", "hit_t"):
+        assert np.array_equal(_bits(a[key]), _bits(b[key]))
+    # the debug keys are the mode's own
+    r = b["rays"]
+    lo, hi = sc.bounds()
+    checked = 0
+    for bb in (1, 2, 3):
+        for y in range(0, 28, 3):
+            for x in range(0, 40, 3):
+                if b["hit_prim"][bb, 0, y, x] == -2:
+                    continue
+                o, d = r[bb, 0, y, x, :3], r[bb, 0, y, x, 4:7]
+                assert b["dbg_keys"][bb - 1, 0, y, x] == orc.ray_key(lo, hi, o, d, kind)
+                checked += 1
+    assert checked > 100
+
+
 # ---------------------------------------------------------------- whole-path properties
 @pytest.mark.parametrize("mode,k", [("incoherent", 1), ("sorted", 1), ("reuse", 1), ("reuse", 4), ("reuse", 16)])
 def test_furnace_closed_form(orc, mode, k):
