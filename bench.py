@@ -355,6 +355,84 @@ def bench_serve(api, serve, scs, args):
                      max_jobs=max_jobs)
 
 
+TABLE3_TILES = ((8, 8), (16, 8), (16, 16), (32, 8))
+TABLE3_KS = (8, 16, 32, 64)
+
+
+def _ldr(x):
+    # display transform for PSNR: clamp to [0, 1], gamma 1/2.2
+    return x.clamp(0.0, 1.0).pow(1.0 / 2.2)
+
+
+def bench_quality(api, sc, cfg, args):
+    """Image quality and the tile/group sweep (the protocols of the paper's Table 2 and
+    Table 3): PSNR after `--quality-frames` frames (1 spp each, a new seed per frame, so
+    the interleaved grouping changes every frame) against an incoherent reference of
+    `--quality-ref` frames; secondary trace speed of every (W,H) x K with K <= W*H."""
+    import torch
+    w, h, B = cfg["w"], cfg["h"], cfg["bounces"]
+
+    def average(mode, tile, k, frames, seed0):
+        r = api.Renderer(sc, api.RenderConfig(w, h, 1, B, mode, tile, k))
+        acc = torch.zeros((h, w, 3), dtype=torch.float64, device="cuda:0")
+        for i in range(frames):
+            r.render(seed0 + i)
+            acc += r.radiance.double()
+        torch.cuda.synchronize()
+        return acc / frames
+
+    def trace_speed(mode, tile, k):
+        timer = api.Timer(4096)
+        r = api.Renderer(sc, api.RenderConfig(w, h, 1, B, mode, tile, k), timer=timer)
+        for i in range(3):
+            r.render(11 + i)
+        torch.cuda.synchronize()
+        timer.reset()
+        for i in range(10):
+            r.render(100 + i)
+        torch.cuda.synchronize()
+        ms, kind, bounce = timer.read()
+        rays = r.ray_count.cpu().numpy().reshape(-1).astype(np.float64)
+        sec = (kind == 0) & (bounce >= 1)
+        return rays[1:].sum() / (ms[sec].sum() / 10 * 1e-3) / 1e6
+
+    t0 = time.perf_counter()
+    ref = _ldr(average("incoherent", (8, 8), 8, args.quality_ref, 7_000_000))
+    log(f"[quality] reference: {args.quality_ref} frames in {time.perf_counter() - t0:.1f} s")
+
+    def psnr(img):
+        mse = float(((_ldr(img) - ref) ** 2).mean())
+        return 10.0 * np.log10(1.0 / mse) if mse > 0 else float("inf")
+
+    out = {"reference_frames": args.quality_ref, "frames": args.quality_frames,
+           "display": "clamp to [0,1], gamma 1/2.2, PSNR over all pixels and channels",
+           "incoherent": {"psnr_db": round(psnr(average("incoherent", (8, 8), 8, args.quality_frames, 1)), 3),
+                          "secondary_mrays_s": round(trace_speed("incoherent", (8, 8), 8), 1)}}
+    rows = []
+    for tile in TABLE3_TILES:
+        for k in TABLE3_KS:
+            if k > tile[0] * tile[1]:
+                continue
+            q = psnr(average("reuse", tile, k, args.quality_frames, 1))
+            v = trace_speed("reuse", tile, k)
+            rows.append({"tile": list(tile), "k": k, "psnr_db": round(q, 3), "secondary_mrays_s": round(v, 1),
+                         "speedup_vs_incoherent": round(v / out["incoherent"]["secondary_mrays_s"], 3)})
+            log(f"[quality] reuse {tile} K={k}: {rows[-1]}")
+    out["reuse"] = rows
+    # ablations: direct world-space reuse with one direction per 8x8 tile (Sec. 3.1) and
+    # tangent-space reuse in non-interleaved groups (Sec. 3.3)
+    abl = []
+    for mode, tile, k in (("reuse_world", (8, 8), 64), ("reuse_world", (8, 8), 8), ("reuse_plain", (8, 8), 8),
+                          ("reuse_plain", (8, 8), 64)):
+        q = psnr(average(mode, tile, k, args.quality_frames, 1))
+        v = trace_speed(mode, tile, k)
+        abl.append({"mode": mode, "tile": list(tile), "k": k, "psnr_db": round(q, 3), "secondary_mrays_s": round(v, 1),
+                    "speedup_vs_incoherent": round(v / out["incoherent"]["secondary_mrays_s"], 3)})
+        log(f"[quality] {mode} {tile} K={k}: {abl[-1]}")
+    out["ablations"] = abl
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,6 +457,10 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--max-jobs", type=int, default=64)
+    ap.add_argument("--quality", action="store_true",
+                    help="PSNR against a many-frame reference and the (W,H) x K speed sweep")
+    ap.add_argument("--quality-frames", type=int, default=128)
+    ap.add_argument("--quality-ref", type=int, default=4096)
     ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-part", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-parts", type=int, default=1, help=argparse.SUPPRESS)
@@ -418,6 +500,14 @@ def main():
     build_s = time.perf_counter() - t0
     log(f"[bench] {args.config}: {scene.ntri} triangles, generated in {gen_s:.1f} s, BVH+upload {build_s:.1f} s, "
         f"info {sc.info()}")
+    if args.quality:
+        line = {"metric": "PSNR (dB) after N frames vs a many-frame reference; secondary Mrays/s per (W,H) x K",
+                "n_gpus": 1, "data": "synthetic (seeded procedural scene)", "dtype": "f32",
+                "config": {"workload": f"{args.config}: {cfg['w']}x{cfg['h']}, 1 spp per frame, {cfg['bounces']} bounces, "
+                                       f"{scene.ntri} triangles"},
+                "quality": bench_quality(api, sc, cfg, args)}
+        print(json.dumps(line), flush=True)
+        return
     if args.profile:
         for i, mode in enumerate(args.modes.split(",")):
             r = api.Renderer(sc, api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], mode, tuple(cfg["tile"]),

@@ -12,7 +12,8 @@ import numpy as np
 
 from .build import LIB, build
 
-MODE = {"incoherent": 0, "sorted": 1, "reuse": 2, "sorted_origin": 3, "sorted_reis": 4, "sorted_aila": 5}
+MODE = {"incoherent": 0, "sorted": 1, "reuse": 2, "sorted_origin": 3, "sorted_reis": 4, "sorted_aila": 5,
+        "reuse_plain": 6, "reuse_world": 7}
 
 F_ACTIVE = 1 << 0
 F_CLASS_SH = 1

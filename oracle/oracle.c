@@ -744,6 +744,11 @@ uint32_t orc_ray_key(const float lo[3], const float hi[3], const float o[3], con
     return orc_ray_key_kind(ORC_MODE_SORTED, lo, hi, o, d);
 }
 
+static int is_reuse_mode(int mode)
+{
+    return mode == ORC_MODE_REUSE || mode == ORC_MODE_REUSE_PLAIN || mode == ORC_MODE_REUSE_WORLD;
+}
+
 static int is_sorted_mode(int mode)
 {
     return mode == ORC_MODE_SORTED || mode == ORC_MODE_SORTED_ORIGIN || mode == ORC_MODE_SORTED_REIS ||
@@ -765,6 +770,7 @@ typedef struct {
     v3 origin, n, Tt, Bt, wi;
     v3 own_q; float own_w[3]; int own_ok;
     v3 use_q; float use_w[3]; int use_ok;
+    int use_world; v3 use_dw;   /* direct world-space reuse: the shared world direction */
     int32_t flags;
 } opath;
 
@@ -805,7 +811,7 @@ int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp,
 {
     if (w <= 0 || h <= 0 || spp <= 0 || B < 0 || W <= 0 || H <= 0 || K <= 0) return -1;
     if ((W & (W - 1)) || (H & (H - 1)) || (K & (K - 1)) || K > W * H || W * H > 65536) return -1;
-    if (mode < 0 || mode > 5) return -1;
+    if (mode < 0 || mode > 7) return -1;
     const int WH = W * H;
     const int ntx = (w + W - 1) / W, nty = (h + H - 1) / H;
     const size_t npix = (size_t)w * (size_t)h;
@@ -931,20 +937,29 @@ int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp,
                 own_sample(m, p, u01(r[2]), u01(r[3]));
                 p->use_q = p->own_q;
                 p->use_ok = p->own_ok;
+                p->use_world = 0;
                 for (int c = 0; c < 3; ++c) p->use_w[c] = p->own_w[c];
                 p->flags = ORC_F_ACTIVE | ((int32_t)m->kind << ORC_F_CLASS_SH);
             }
 
-            /* ---- generate: direction reuse inside interleaved groups ---- */
-            if (b < B && mode == ORC_MODE_REUSE && b + 1 <= reuse_max_bounce) {
+            /* ---- generate: direction reuse inside interleaved groups ----
+             * REUSE: tangent-space rules of Section 3.2 in groups interleaved by the
+             * per-tile shuffle of Section 3.3.  REUSE_PLAIN: the same rules in groups of
+             * K consecutive screen-order pixels (no shuffle: the ablation of Section 3.3).
+             * REUSE_WORLD: direct reuse of Section 3.1 -- the active member with the
+             * smallest slot samples its own direction and every other Lambert member
+             * takes it unchanged in world space, weighted by its own albedo; the path of
+             * a member below whose surface that direction points ends; glossy and
+             * specular members sample their own. */
+            if (b < B && is_reuse_mode(mode) && b + 1 <= reuse_max_bounce) {
                 for (int ty = 0; ty < nty; ++ty)
                     for (int tx = 0; tx < ntx; ++tx) {
                         int tile = ty * ntx + tx;
                         if (tile_mask && !tile_mask[tile]) continue;
                         uint64_t r[4];
                         draw(seed, (uint64_t)tile, smp, b, 1, r);
-                        uint32_t a, c;
-                        shuffle_params(WH, r[0], r[1], &a, &c);
+                        uint32_t a = 1, c = 0;
+                        if (mode != ORC_MODE_REUSE_PLAIN) shuffle_params(WH, r[0], r[1], &a, &c);
                         for (int sl = 0; sl < WH; ++sl) member[sl] = 0;
                         for (int iy = 0; iy < H; ++iy)
                             for (int ix = 0; ix < W; ++ix) {
@@ -955,7 +970,31 @@ int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp,
                                 member[sl] = (uint32_t)((size_t)y * w + x) + 1u;
                                 P[(size_t)y * w + x].flags |= (int32_t)(sl << ORC_F_SLOT_SH);
                             }
-                        for (int g = 0; g < WH / K; ++g) {
+                        for (int g = 0; g < WH / K && mode == ORC_MODE_REUSE_WORLD; ++g) {
+                            int rep = -1;
+                            for (int j = 0; j < K && rep < 0; ++j) {
+                                uint32_t mm = member[g * K + j];
+                                if (mm && P[mm - 1].active) rep = (int)(mm - 1);
+                            }
+                            if (rep < 0) continue;
+                            opath* pr = &P[rep];
+                            pr->flags |= ORC_F_REP;
+                            if (!pr->own_ok) continue;
+                            v3 wdir = to_world(pr->own_q, pr->Tt, pr->Bt, pr->n);
+                            for (int j = 0; j < K; ++j) {
+                                uint32_t mm = member[g * K + j];
+                                if (!mm || (int)(mm - 1) == rep) continue;
+                                opath* p = &P[mm - 1];
+                                if (!p->active || p->kind != 0) continue;
+                                p->use_world = 1;
+                                p->use_dw = wdir;
+                                p->use_ok = vdot(wdir, p->n) > 0.0f;
+                                const orc_material* m = &s->mats[s->tri_mat[p->prim]];
+                                for (int cc = 0; cc < 3; ++cc) p->use_w[cc] = m->albedo[cc];
+                                p->flags |= ORC_F_REUSED;
+                            }
+                        }
+                        for (int g = 0; g < WH / K && mode != ORC_MODE_REUSE_WORLD; ++g) {
                             int nd = 0, ng = 0;
                             int rep = -1;
                             for (int j = 0; j < K; ++j) {
@@ -1014,9 +1053,10 @@ int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp,
                 if (p->use_ok) p->flags |= ORC_F_VALID;
                 size_t at = ((size_t)b * spp + smp) * plane + i;
                 if (out->dbg_flags) out->dbg_flags[at] = p->flags;
-                if (out->dbg_q) { out->dbg_q[at * 3] = p->use_q.x; out->dbg_q[at * 3 + 1] = p->use_q.y; out->dbg_q[at * 3 + 2] = p->use_q.z; }
+                v3 dq = p->use_world ? p->use_dw : p->use_q;   /* world direction for direct reuse */
+                if (out->dbg_q) { out->dbg_q[at * 3] = dq.x; out->dbg_q[at * 3 + 1] = dq.y; out->dbg_q[at * 3 + 2] = dq.z; }
                 if (!p->use_ok) { p->alive = 0; continue; }
-                v3 nd = to_world(p->use_q, p->Tt, p->Bt, p->n);
+                v3 nd = p->use_world ? p->use_dw : to_world(p->use_q, p->Tt, p->Bt, p->n);
                 for (int c = 0; c < 3; ++c) p->T[c] = p->T[c] * p->use_w[c];
                 p->o = p->origin;
                 p->d = nd;

@@ -52,7 +52,7 @@ typedef struct {
 } orc_outputs;
 
 enum { ORC_MODE_INCOHERENT = 0, ORC_MODE_SORTED = 1, ORC_MODE_REUSE = 2, ORC_MODE_SORTED_ORIGIN = 3,
-       ORC_MODE_SORTED_REIS = 4, ORC_MODE_SORTED_AILA = 5 };
+       ORC_MODE_SORTED_REIS = 4, ORC_MODE_SORTED_AILA = 5, ORC_MODE_REUSE_PLAIN = 6, ORC_MODE_REUSE_WORLD = 7 };
 
 /* debug flag bits for the ray generated at hit b (ray index b+1) */
 #define ORC_F_ACTIVE   (1 << 0)     /* the path scatters at this hit */

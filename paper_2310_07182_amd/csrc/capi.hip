@@ -93,6 +93,10 @@ pt_status hip_fail(hipError_t e, const char* what) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+bool is_reuse_mode(int mode) {
+    return mode == PT_MODE_REUSE || mode == PT_MODE_REUSE_PLAIN || mode == PT_MODE_REUSE_WORLD;
+}
+
 bool is_sorted_mode(int mode) {
     return mode == PT_MODE_SORTED || mode == PT_MODE_SORTED_ORIGIN || mode == PT_MODE_SORTED_REIS ||
            mode == PT_MODE_SORTED_AILA;
@@ -459,7 +463,7 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
     if (w <= 0 || h <= 0 || spp <= 0) return fail(PT_EINVAL, "w, h, spp must be >= 1 (got %d, %d, %d)", w, h, spp);
     if (B < 0 || B > 64) return fail(PT_EINVAL, "bounces must be in [0, 64] (got %d)", B);
     if ((long long)w * (long long)h > (1ll << 30)) return fail(PT_EINVAL, "image too large");
-    if (mode != PT_MODE_INCOHERENT && mode != PT_MODE_REUSE && !is_sorted_mode(mode))
+    if (mode != PT_MODE_INCOHERENT && !is_reuse_mode(mode) && !is_sorted_mode(mode))
         return fail(PT_EINVAL, "unknown mode %d", (int)mode);
     pt_status cs = check_group(g, B);
     if (cs != PT_OK) return cs;

@@ -650,16 +650,21 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
     for (int c = 0; c < 3; ++c) w3[c] = kind == 1 ? gw[c] : m.albedo[c];
     V3 use = own;
     bool use_ok = own_ok;
+    bool use_world = false;   // direct reuse: the next direction is given in world space
+    V3 wdir = mk3(0.f, 0.f, 0.f);
     uint32_t newpos = p;
-    const bool reuse = f.mode == PT_MODE_REUSE && b < f.B && b + 1 <= f.reuse_max;
+    const bool world = f.mode == PT_MODE_REUSE_WORLD;
+    const bool reuse = (f.mode == PT_MODE_REUSE || f.mode == PT_MODE_REUSE_PLAIN || world) && b < f.B &&
+                       b + 1 <= f.reuse_max;
     if (reuse) {
-        // interleaved grouping: shuffle screen-order numbers inside the tile
+        // interleaved grouping: shuffle screen-order numbers inside the tile (not in the
+        // plain ablation, whose groups are consecutive screen-order pixels)
         uint32_t slot = 0;
         {
             const uint32_t tile = (uint32_t)(spx.y / f.H) * (uint32_t)f.ntx + (uint32_t)(spx.x / f.W);
             const U64x4 rnd = philox(tile, (uint64_t)s, (uint64_t)b, 1, f.seed);
             uint32_t ma = 1, mc = 0;
-            if (f.WH > 1) {
+            if (f.WH > 1 && f.mode != PT_MODE_REUSE_PLAIN) {
                 ma = 2u * (uint32_t)(rnd.v[0] & (uint64_t)(f.WH / 2 - 1)) + 1u;
                 mc = (uint32_t)(rnd.v[1] & (uint64_t)(f.WH - 1));
             }
@@ -667,9 +672,12 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
         }
         const int e = spx.tin * f.WH + (int)slot;
         const bool gl_exit = active && kind != 0 && own_ok;
-        sq0[e] = own.x;
-        sq1[e] = own.y;
-        sq2[e] = own.z;
+        // direct reuse shares the own exit in world space; x = 2 marks a sample that died
+        const V3 ow = tangent_to_world(own, tt, bt, n);
+        const V3 shared = world ? (own_ok ? ow : mk3(2.0f, 0.0f, 0.0f)) : own;
+        sq0[e] = shared.x;
+        sq1[e] = shared.y;
+        sq2[e] = shared.z;
         ss0[e] = gl_exit ? own.x : 0.0f;
         ss1[e] = gl_exit ? own.y : 0.0f;
         ss2[e] = gl_exit ? own.z : 0.0f;
@@ -692,19 +700,24 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
         const int rslot = srep[root] < f.WH ? srep[root] : 0;
         const int r = spx.tin * f.WH + rslot;
         // diffuse group: every member takes the representative's tangent direction
-        const bool take_rep = active && kind == 0 && !(info & 2);
+        const bool take_rep = !world && active && kind == 0 && !(info & 2);
         // hybrid group: diffuse members take the normalized sum of the glossy/specular exits
-        const bool take_avg = active && kind == 0 && (info & 2) && (info & 4);
+        const bool take_avg = !world && active && kind == 0 && (info & 2) && (info & 4);
         const V3 repq = mk3(sq0[r], sq1[r], sq2[r]);
         const V3 avgq = unit3(mk3(ss0[root], ss1[root], ss2[root]));
         use = take_rep ? repq : (take_avg ? avgq : use);
         use_ok = (take_rep || take_avg) ? true : use_ok;
+        // direct reuse: Lambert members other than the representative take its world
+        // direction; a member below whose surface it points ends its path
+        use_world = world && active && kind == 0 && srep[root] < f.WH && (int)slot != rslot && repq.x <= 1.5f;
+        wdir = repq;
+        use_ok = use_world ? dot3(repq, n) > 0.0f : use_ok;
         newpos = blk * (uint32_t)TS + (uint32_t)e;
     }
     if (b < f.B) {
         float4 o0 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1)), o1 = make_float4(0.f, 0.f, 0.f, __uint_as_float(kNoRay));
         if (active && use_ok) {
-            const V3 nd = tangent_to_world(use, tt, bt, n);
+            const V3 nd = use_world ? wdir : tangent_to_world(use, tt, bt, n);
             for (int c = 0; c < 3; ++c) T[c] = T[c] * w3[c];
             o0 = make_float4(origin.x, origin.y, origin.z, __int_as_float(prim));
             o1 = make_float4(nd.x, nd.y, nd.z, __uint_as_float(pix));
@@ -1074,7 +1087,8 @@ hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const 
                         float4* state, int32_t* hit_prim, float* hit_t, float* radiance, float4* rays_out,
                         hipStream_t st) {
     const unsigned blocks = (unsigned)(f.nslots / (uint32_t)f.TS);
-    const size_t lds = (f.mode == PT_MODE_REUSE) ? (size_t)f.TS * 8 * sizeof(float) : 0;
+    const bool reuse = f.mode == PT_MODE_REUSE || f.mode == PT_MODE_REUSE_PLAIN || f.mode == PT_MODE_REUSE_WORLD;
+    const size_t lds = reuse ? (size_t)f.TS * 8 * sizeof(float) : 0;
     hipLaunchKernelGGL(k_shade, dim3(blocks), dim3(f.TS), lds, st, sc, f, b, s, q_in, q_out, state, hit_prim, hit_t,
                        radiance, rays_out);
     return hipGetLastError();

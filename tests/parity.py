@@ -31,7 +31,7 @@ def compare_render(gpu: dict, orc: dict, tile=(8, 8), mode="incoherent", pixel_m
         newly = mism & tie
         if newly.any():
             ties += int(newly.sum())
-            if mode == "reuse":
+            if mode.startswith("reuse"):
                 W, H = tile
                 for s, y, x in np.argwhere(newly):
                     excluded[s, (y // H) * H:(y // H + 1) * H, (x // W) * W:(x // W + 1) * W] = True

@@ -133,6 +133,22 @@ def test_render_parity_leaf_gate(api, orc, torch_dev, mode, leaf_gate, refill):
     compare_render(g, o, (8, 8), mode)
 
 
+@pytest.mark.parametrize("mode,tile,k,w,h,spp,B", [
+    ("reuse_plain", (8, 8), 8, 101, 67, 1, 4),
+    ("reuse_plain", (4, 4), 2, 64, 48, 2, 3),
+    ("reuse_world", (8, 8), 64, 101, 67, 1, 4),
+    ("reuse_world", (8, 8), 8, 77, 41, 2, 3),
+    ("reuse_world", (16, 16), 256, 64, 64, 1, 2),
+    ("reuse_world", (4, 4), 1, 50, 30, 1, 3),
+])
+def test_render_parity_reuse_ablations(api, orc, torch_dev, mode, tile, k, w, h, spp, B):
+    s, sc, osc = both(api, orc, "mixed_small")
+    g = gpu_render(api, sc, w, h, spp, B, mode, tile, k, 123)
+    o = osc.render(w, h, spp, B, mode=mode, tile=tile, k=k, seed=123)
+    res = compare_render(g, o, tile, mode)
+    _say("  ", res)
+
+
 def test_reuse_max_bounce_one(api, orc, torch_dev):
     s, sc, osc = both(api, orc, "mixed_small")
     g = gpu_render(api, sc, 64, 48, 1, 3, "reuse", (8, 8), 8, 5, rmax=1)

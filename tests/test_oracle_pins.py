@@ -422,17 +422,19 @@ def _pairwise_sum(vecs):
     return v[0]
 
 
-@pytest.mark.parametrize("tile,k", [((4, 4), 4), ((8, 8), 8)])
-def test_reuse_rules_per_category(orc, tile, k):
+@pytest.mark.parametrize("tile,k,mode", [((4, 4), 4, "reuse"), ((8, 8), 8, "reuse"), ((8, 8), 8, "reuse_plain"),
+                                         ((4, 4), 2, "reuse_plain")])
+def test_reuse_rules_per_category(orc, tile, k, mode):
     """Sections 3.2/3.3: diffuse groups share the representative's tangent
     direction, glossy members keep their own, hybrid diffuse members take the
-    normalized sum of the glossy members' exits."""
+    normalized sum of the glossy members' exits; groups are interleaved by the
+    per-tile shuffle, or consecutive screen-order pixels in the plain ablation."""
     s = scenes.mixed_small()
     sc = orc.OracleScene(s)
     W, H = tile
     w, h = 64, 48
     inc = sc.render(w, h, 1, 2, mode="incoherent", tile=tile, k=k, seed=31, debug=True)
-    reu = sc.render(w, h, 1, 2, mode="reuse", tile=tile, k=k, seed=31, debug=True)
+    reu = sc.render(w, h, 1, 2, mode=mode, tile=tile, k=k, seed=31, debug=True)
     # only the first generated ray (bounce 0 -> 1) has identical shading points in both runs
     fi, qi = inc["dbg_flags"][0, 0], inc["dbg_q"][0, 0]
     fr, qr = reu["dbg_flags"][0, 0], reu["dbg_q"][0, 0]
@@ -449,7 +451,10 @@ def test_reuse_rules_per_category(orc, tile, k):
             # screen-order numbering i = row*W + col, shuffled by the tile draw
             # of counter (tile id, sample, bounce, stream 1) (Section 3.3)
             x = orc.philox((ty * (w // W) + tx, 0, 0, 1), (31, 0))
-            assert np.array_equal(slot, orc.shuffle(W * H, int(x[0]), int(x[1])))
+            if mode == "reuse":
+                assert np.array_equal(slot, orc.shuffle(W * H, int(x[0]), int(x[1])))
+            else:
+                assert np.array_equal(slot, np.arange(W * H))
             for g in range(W * H // k):
                 mem = np.where((slot // k) == g)[0]
                 mem = mem[np.argsort(slot[mem])]
@@ -486,6 +491,79 @@ def test_reuse_rules_per_category(orc, tile, k):
                         for m in diff:
                             assert np.array_equal(qu[m].view(np.uint32), qo[m].view(np.uint32))
     assert seen[1] > 0 and seen[3] > 0
+
+
+def test_world_reuse_rules(orc):
+    """Section 3.1 (direct reuse): the active member with the smallest slot samples
+    its own direction; every other Lambert member's next ray takes it unchanged in
+    world space (and ends if it points below the member's surface); glossy and
+    specular members, and members of groups whose representative's sample died,
+    keep their own."""
+    s = scenes.mixed_small()
+    sc = orc.OracleScene(s)
+    W = H = 8
+    k = 64
+    w, h = 64, 48
+    inc = sc.render(w, h, 1, 2, mode="incoherent", tile=(W, H), k=k, seed=33, debug=True)
+    reu = sc.render(w, h, 1, 2, mode="reuse_world", tile=(W, H), k=k, seed=33, debug=True)
+    fi, fr = inc["dbg_flags"][0, 0], reu["dbg_flags"][0, 0]
+    ri, rr = inc["rays"][1, 0], reu["rays"][1, 0]
+    hp = reu["hit_prim"][1, 0]
+    assert np.array_equal(fi & orc.F_ACTIVE, fr & orc.F_ACTIVE)
+    shared = died = 0
+    for ty in range(h // H):
+        for tx in range(w // W):
+            sl = (slice(ty * H, (ty + 1) * H), slice(tx * W, (tx + 1) * W))
+            fl, f0 = fr[sl].ravel(), fi[sl].ravel()
+            di, dr = ri[sl].reshape(-1, 8)[:, 4:7], rr[sl].reshape(-1, 8)[:, 4:7]
+            hpt = hp[sl].ravel()
+            slot = (fl >> orc.F_SLOT_SH) & 0xFFFF
+            x = orc.philox((ty * (w // W) + tx, 0, 0, 1), (33, 0))
+            assert np.array_equal(slot, orc.shuffle(W * H, int(x[0]), int(x[1])))
+            act = np.where((fl & orc.F_ACTIVE) != 0)[0]
+            if len(act) == 0:
+                continue
+            rep = act[np.argmin(slot[act])]
+            assert fl[rep] & orc.F_REP
+            rep_ok = (f0[rep] & orc.F_VALID) != 0
+            for m in act:
+                lam = ((fl[m] >> orc.F_CLASS_SH) & 3) == 0
+                if m == rep or not lam or not rep_ok:
+                    assert not (fl[m] & orc.F_REUSED)
+                    if f0[m] & orc.F_VALID:
+                        assert np.array_equal(dr[m].view(np.uint32), di[m].view(np.uint32))
+                    continue
+                assert fl[m] & orc.F_REUSED
+                if fl[m] & orc.F_VALID:
+                    assert np.array_equal(dr[m].view(np.uint32), di[rep].view(np.uint32))
+                    shared += 1
+                else:
+                    assert hpt[m] == -2
+                    died += 1
+    assert shared > 100 and died > 0
+
+
+@pytest.mark.parametrize("scene_fn,k", [(scenes.mixed_small, 1), (scenes.glossy_only, 8)])
+def test_world_reuse_degenerate_cases_equal_incoherent(orc, scene_fn, k):
+    # one pixel per group, or no Lambert member anywhere: nothing is shared
+    sc = orc.OracleScene(scene_fn())
+    a = sc.render(48, 40, 1, 3, mode="incoherent", tile=(8, 8), k=k, seed=5)
+    b = sc.render(48, 40, 1, 3, mode="reuse_world", tile=(8, 8), k=k, seed=5)
+    for key in ("radiance", "hit_prim", "hit_t"):
+        assert np.array_equal(_bits(a[key]), _bits(b[key]))
+
+
+def test_world_reuse_furnace_weights(orc):
+    # closed all-Lambert box, albedo rho and emission E everywhere: a path alive for n
+    # hits gathers E * sum_{i<n} rho^i; a member whose shared direction points below its
+    # surface ends there, so only the number of hits changes, never the weights
+    rho, E, B = 0.5, 1.0, 3
+    sc = orc.OracleScene(scenes.furnace(rho, E))
+    r = sc.render(32, 32, 1, B, mode="reuse_world", tile=(8, 8), k=64, seed=13)
+    hits = (r["hit_prim"][:, 0] >= 0).sum(axis=0)
+    expect = E * np.array([sum(rho ** i for i in range(n)) for n in range(B + 2)])[hits]
+    assert np.allclose(r["radiance"], expect[..., None], rtol=1e-5)
+    assert (hits < B + 1).any() and (hits == B + 1).any()
 
 
 def test_group_composition_changes_across_samples(orc):
