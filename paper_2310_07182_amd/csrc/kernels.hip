@@ -11,6 +11,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -259,12 +260,16 @@ constexpr int32_t kDone = INT32_MIN;   // = kEmpty: never a node or leaf code
 // is tested, so the result is the exact (t, prim id) minimum.  All loops below are
 // wave-uniform: every lane reaches every shuffle and barrier.
 constexpr int32_t kNoLeaf = 0;   // never a leaf code (leaf codes are negative)
+constexpr int kLeafCountBits = kMaxLeaf < 2 ? 1 : (kMaxLeaf < 4 ? 2 : (kMaxLeaf < 8 ? 3 : 4));
+static_assert(kMaxLeaf >= 1 && kMaxLeaf <= 8, "leaf codes hold counts 1..8");
+static_assert(kTraceBlock == 64, "the pair list stores a lane in 6 bits");
+using PairT = std::conditional_t<(kMaxLeaf <= 4), uint8_t, uint16_t>;   // lane + triangle-in-leaf
 
 template <bool STATS, bool MULTI>
 __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a, uint32_t gthreads,
                                                        const StepJob* jobs, int njobs) {
     __shared__ int32_t stk[kStackLds][kTraceBlock];
-    __shared__ uint8_t pairs[kTraceBlock * kMaxLeaf];   // lane | (triangle in leaf) << 6
+    __shared__ PairT pairs[kTraceBlock * kMaxLeaf];   // lane | (triangle in leaf) << 6
     const int lane = threadIdx.x;
     const uint32_t gtid = blockIdx.x * kTraceBlock + lane;
     const uint32_t n = a.n;
@@ -410,11 +415,15 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
             const uint32_t code = ~(uint32_t)leaf;
             const uint32_t first = code >> 3;
             const uint32_t cnt = hold ? (code & 7u) + 1u : 0u;
-            // exclusive prefix sum of the triangle counts (at most 4: three bits) over the wave
-            const unsigned long long q0 = __ballot(cnt & 1u), q1 = __ballot(cnt & 2u), q2 = __ballot(cnt & 4u);
-            const uint32_t off = (uint32_t)(__popcll(q0 & lt) + 2 * __popcll(q1 & lt) + 4 * __popcll(q2 & lt));
-            const uint32_t total = (uint32_t)(__popcll(q0) + 2 * __popcll(q1) + 4 * __popcll(q2));
-            for (uint32_t j = 0; j < cnt; ++j) pairs[off + j] = (uint8_t)((uint32_t)lane | (j << 6));
+            // exclusive prefix sum of the triangle counts over the wave, one ballot per bit
+            uint32_t off = 0, total = 0;
+#pragma unroll
+            for (int bit = 0; bit < kLeafCountBits; ++bit) {
+                const unsigned long long qb = __ballot((cnt >> bit) & 1u);
+                off += (uint32_t)__popcll(qb & lt) << bit;
+                total += (uint32_t)__popcll(qb) << bit;
+            }
+            for (uint32_t j = 0; j < cnt; ++j) pairs[off + j] = (PairT)((uint32_t)lane | (j << 6));
             __syncthreads();
             const int perm = rp.kx | (rp.ky << 2) | (rp.kz << 4);
             for (uint32_t base = 0; base < total; base += kTraceBlock) {
