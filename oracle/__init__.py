@@ -37,7 +37,8 @@ class _Camera(C.Structure):
 class _Outputs(C.Structure):
     _fields_ = [("radiance", C.c_void_p), ("hit_prim", C.c_void_p), ("hit_t", C.c_void_p),
                 ("hit_t2", C.c_void_p), ("dbg_q", C.c_void_p), ("dbg_flags", C.c_void_p),
-                ("dbg_keys", C.c_void_p), ("rays", C.c_void_p), ("rays_per_bounce", C.c_void_p)]
+                ("dbg_keys", C.c_void_p), ("rays", C.c_void_p), ("rays_per_bounce", C.c_void_p),
+                ("shadow_rays", C.c_void_p)]
 
 
 _lib = None
@@ -57,7 +58,7 @@ def lib():
         L.orc_trace.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp]
         L.orc_trace_brute.argtypes = [vp, vp, u32, vp, vp]
         L.orc_render.restype = i32
-        L.orc_render.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, i32, i32, i32, C.c_uint64, vp, vp]
+        L.orc_render.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, i32, i32, i32, C.c_uint64, vp, i32, vp]
         L.orc_philox4x64_10.argtypes = [vp, vp, vp]
         L.orc_sincos2pi.argtypes = [vp, u32, vp, vp]
         L.orc_onb.argtypes = [vp, vp, vp]
@@ -135,7 +136,7 @@ class OracleScene:
         return prim, t
 
     def render(self, w, h, spp, bounces, mode="incoherent", tile=(8, 8), k=8, reuse_max_bounce=None,
-               seed=1, tile_mask=None, debug=False, camera=None):
+               seed=1, tile_mask=None, debug=False, camera=None, nee=False):
         cam = camera_struct(camera or self.scene["camera"])
         B = int(bounces)
         if reuse_max_bounce is None:
@@ -145,10 +146,12 @@ class OracleScene:
         ht = np.full((B + 1, spp, h, w), np.inf, np.float32)
         ht2 = np.full((B + 1, spp, h, w), np.inf, np.float32)
         rpb = np.zeros(B + 1, np.uint64)
+        srb = np.zeros(B + 1, np.uint64)
         out = _Outputs()
         out.radiance, out.hit_prim, out.hit_t, out.hit_t2 = _p(rad), _p(hp), _p(ht), _p(ht2)
         out.rays_per_bounce = _p(rpb)
-        res = dict(radiance=rad, hit_prim=hp, hit_t=ht, hit_t2=ht2, rays_per_bounce=rpb)
+        out.shadow_rays = _p(srb)
+        res = dict(radiance=rad, hit_prim=hp, hit_t=ht, hit_t2=ht2, rays_per_bounce=rpb, shadow_rays=srb)
         if debug:
             q = np.zeros((max(B, 1), spp, h, w, 3), np.float32)
             fl = np.zeros((max(B, 1), spp, h, w), np.int32)
@@ -163,7 +166,7 @@ class OracleScene:
             nty = (h + tile[1] - 1) // tile[1]
             assert mask.size == ntx * nty
         rc = lib().orc_render(self.h, C.byref(cam), w, h, spp, B, MODE[mode], tile[0], tile[1], k,
-                              int(reuse_max_bounce), C.c_uint64(seed), _p(mask), C.byref(out))
+                              int(reuse_max_bounce), C.c_uint64(seed), _p(mask), int(bool(nee)), C.byref(out))
         if rc != 0:
             raise ValueError(f"orc_render failed with {rc}")
         return res

@@ -241,6 +241,8 @@ struct orc_scene {
     uint32_t nnodes;
     uint32_t* order;      /* leaf slots -> original prim */
     double pad;
+    uint32_t* emit;       /* emissive triangles (any emission channel > 0), original order */
+    uint32_t nemit;
 };
 
 static float* g_cent;  /* build scratch: centroids (the oracle is single-threaded) */
@@ -391,6 +393,12 @@ orc_scene* orc_scene_create(const float* tris, uint32_t ntri, const uint32_t* tr
     memcpy(s->tris, tris, (size_t)ntri * 9 * sizeof(float));
     memcpy(s->tri_mat, tri_mat, (size_t)ntri * sizeof(uint32_t));
     memcpy(s->mats, mats, (size_t)nmat * sizeof(orc_material));
+    s->emit = (uint32_t*)malloc((size_t)ntri * sizeof(uint32_t) + 4);
+    if (!s->emit) { orc_scene_free(s); free(g_cent); free(g_tlo); free(g_thi); g_cent = g_tlo = g_thi = NULL; return NULL; }
+    for (uint32_t i = 0; i < ntri; ++i) {
+        const float* e = mats[tri_mat[i]].emission;
+        if (e[0] > 0.0f || e[1] > 0.0f || e[2] > 0.0f) s->emit[s->nemit++] = i;
+    }
     for (int a = 0; a < 3; ++a) { s->env[a] = env[a]; s->lo[a] = INFINITY; s->hi[a] = -INFINITY; }
     for (uint32_t i = 0; i < ntri; ++i) {
         s->order[i] = i;
@@ -422,7 +430,7 @@ orc_scene* orc_scene_create(const float* tris, uint32_t ntri, const uint32_t* tr
 void orc_scene_free(orc_scene* s)
 {
     if (!s) return;
-    free(s->tris); free(s->tri_mat); free(s->mats); free(s->order); free(s->nodes);
+    free(s->tris); free(s->tri_mat); free(s->mats); free(s->order); free(s->nodes); free(s->emit);
     free(s);
 }
 
@@ -771,6 +779,7 @@ typedef struct {
     v3 own_q; float own_w[3]; int own_ok;
     v3 use_q; float use_w[3]; int use_ok;
     int use_world; v3 use_dw;   /* direct world-space reuse: the shared world direction */
+    int nee_prev;       /* the current ray left a Lambert point where NEE counted direct light */
     int32_t flags;
 } opath;
 
@@ -805,13 +814,59 @@ static void own_sample(const orc_material* m, opath* p, float u2, float u3)
     }
 }
 
+/* ------------------------------------------------------------------------
+ * Next-event estimation at a Lambert scattering point (the paper's future-work
+ * extension, Section 6): one emissive triangle chosen uniformly from the
+ * pixel draw of stream 2 (x0 mod nemit), a uniform point on it from x1, x2
+ * (b0 = 1 - sqrt(u1), b1 = u2 sqrt(u1), b2 = (1 - b0) - b1), and a shadow ray
+ * from the scattering point's offset origin along D = point - origin, blocked by
+ * any triangle other than the scattering one at 0 < t < 1 - 2^-10 (t in units of
+ * D).  Unblocked and with D in the upper hemisphere, it adds
+ * (T * albedo) * (Le * ((cos_s * cos_l) / (|D|^2 |D|^2)) * (nemit / (2 pi))),
+ * cos_s = D.n and cos_l = |D.(e1 x e2)| unnormalized: the area-sampling
+ * estimator f Le cos cos / (r^2 pdf_A) with f = albedo / pi, pdf_A = 1/(nemit A).
+ * Emission that a ray sampled at a Lambert point then hits is not added again.
+ * ---------------------------------------------------------------------- */
+#define ORC_SHADOW_TMAX (1.0f - 0x1p-10f)
+
+static void nee_sample(const orc_scene* s, const opath* p, const orc_material* m, uint64_t seed,
+                       size_t pixel, int smp, int b, float C[3], v3* D, int* ok)
+{
+    *ok = 0;
+    if (s->nemit == 0) return;
+    uint64_t r[4];
+    draw(seed, pixel, smp, b, 2, r);
+    uint32_t e = s->emit[(uint32_t)(r[0] % (uint64_t)s->nemit)];
+    float u1 = u01(r[1]), u2 = u01(r[2]);
+    const float* v = s->tris + (size_t)e * 9;
+    v3 v0 = load3(v), v1 = load3(v + 3), v2 = load3(v + 6);
+    float su = sqrtf(u1);
+    float b0 = 1.0f - su, b1 = u2 * su;
+    float b2 = (1.0f - b0) - b1;
+    v3 q = mk((b0 * v0.x + b1 * v1.x) + b2 * v2.x, (b0 * v0.y + b1 * v1.y) + b2 * v2.y,
+              (b0 * v0.z + b1 * v1.z) + b2 * v2.z);
+    v3 d = vsub(q, p->origin);
+    float cs = vdot(d, p->n);
+    if (!(cs > 0.0f)) return;
+    v3 nl = vcross(vsub(v1, v0), vsub(v2, v0));
+    float cl = fabsf(vdot(d, nl));
+    float d2 = vdot(d, d);
+    float g = (cs * cl) / (d2 * d2);
+    float k = g * ((float)s->nemit * (float)(1.0 / (2.0 * 3.14159265358979323846)));
+    const float* Le = s->mats[s->tri_mat[e]].emission;
+    for (int c = 0; c < 3; ++c) C[c] = (p->T[c] * m->albedo[c]) * (Le[c] * k);
+    *D = d;
+    *ok = 1;
+}
+
 int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp, int B,
                int mode, int W, int H, int K, int reuse_max_bounce, uint64_t seed,
-               const uint8_t* tile_mask, orc_outputs* out)
+               const uint8_t* tile_mask, int nee, orc_outputs* out)
 {
     if (w <= 0 || h <= 0 || spp <= 0 || B < 0 || W <= 0 || H <= 0 || K <= 0) return -1;
     if ((W & (W - 1)) || (H & (H - 1)) || (K & (K - 1)) || K > W * H || W * H > 65536) return -1;
     if (mode < 0 || mode > 7) return -1;
+    if (nee && mode == ORC_MODE_REUSE_WORLD) return -1;   /* a member that dies after NEE is not covered */
     const int WH = W * H;
     const int ntx = (w + W - 1) / W, nty = (h + H - 1) / H;
     const size_t npix = (size_t)w * (size_t)h;
@@ -870,6 +925,7 @@ int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp,
                 camera_ray(&cb, w, h, x, y, u01(r[0]), u01(r[1]), &p->o, &p->d);
                 p->excl = -1;
                 p->alive = 1;
+                p->nee_prev = 0;
                 p->T[0] = p->T[1] = p->T[2] = 1.0f;
             }
         for (int b = 0; b <= B; ++b) {
@@ -918,7 +974,8 @@ int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp,
                     continue;
                 }
                 const orc_material* m = &s->mats[s->tri_mat[p->prim]];
-                for (int c = 0; c < 3; ++c) p->L[c] = p->L[c] + p->T[c] * m->emission[c];
+                if (!(nee && p->nee_prev))
+                    for (int c = 0; c < 3; ++c) p->L[c] = p->L[c] + p->T[c] * m->emission[c];
                 if (b == B || absorbing(m)) { p->alive = 0; continue; }
                 const float* v = s->tris + (size_t)p->prim * 9;
                 v3 v0 = load3(v), v1 = load3(v + 3), v2 = load3(v + 6);
@@ -940,6 +997,19 @@ int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp,
                 p->use_world = 0;
                 for (int c = 0; c < 3; ++c) p->use_w[c] = p->own_w[c];
                 p->flags = ORC_F_ACTIVE | ((int32_t)m->kind << ORC_F_CLASS_SH);
+                if (nee && m->kind == 0) {
+                    float C[3];
+                    v3 D;
+                    int ok;
+                    nee_sample(s, p, m, seed, i, smp, b, C, &D, &ok);
+                    if (ok) {
+                        hit2 sh = trace_one(s, p->origin, D, p->prim, NULL, NULL);
+                        int blocked = sh.p1 != INT32_MAX && sh.t1 < ORC_SHADOW_TMAX;
+                        if (out->shadow_rays) out->shadow_rays[b] += 1;
+                        if (!blocked)
+                            for (int c = 0; c < 3; ++c) p->L[c] = p->L[c] + C[c];
+                    }
+                }
             }
 
             /* ---- generate: direction reuse inside interleaved groups ----
@@ -1058,6 +1128,7 @@ int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp,
                 if (!p->use_ok) { p->alive = 0; continue; }
                 v3 nd = p->use_world ? p->use_dw : to_world(p->use_q, p->Tt, p->Bt, p->n);
                 for (int c = 0; c < 3; ++c) p->T[c] = p->T[c] * p->use_w[c];
+                p->nee_prev = nee && p->kind == 0;
                 p->o = p->origin;
                 p->d = nd;
                 p->excl = p->prim;

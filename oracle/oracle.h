@@ -49,6 +49,7 @@ typedef struct {
     uint32_t* dbg_keys;       /* [B][spp][h][w] two-point key of ray b+1 (sorted mode) */
     float* rays;              /* [B+1][spp][h][w][8] ray traced at bounce b {o, excluded, d, pixel} */
     uint64_t* rays_per_bounce;/* [B+1] */
+    uint64_t* shadow_rays;    /* [B+1] shadow rays traced at hit b (next-event estimation) */
 } orc_outputs;
 
 enum { ORC_MODE_INCOHERENT = 0, ORC_MODE_SORTED = 1, ORC_MODE_REUSE = 2, ORC_MODE_SORTED_ORIGIN = 3,
@@ -74,9 +75,11 @@ void orc_trace(const orc_scene* s, const float* rays, uint32_t n, int32_t* prim,
                float* t2, uint64_t* node_visits, uint64_t* tri_tests);
 void orc_trace_brute(const orc_scene* s, const float* rays, uint32_t n, int32_t* prim, float* t);
 
+/* nee: next-event estimation toward the emissive triangles at Lambert scattering points
+ * (not with ORC_MODE_REUSE_WORLD) */
 int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp, int bounces,
                int mode, int tile_w, int tile_h, int k, int reuse_max_bounce, uint64_t seed,
-               const uint8_t* tile_mask, orc_outputs* out);
+               const uint8_t* tile_mask, int nee, orc_outputs* out);
 
 /* individual steps, exported for the pins */
 void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);

@@ -616,3 +616,68 @@ def test_tile_mask_matches_full_render(orc):
         pix[ty * H:(ty + 1) * H, tx * W:(tx + 1) * W] = True
     assert np.array_equal(full["hit_prim"][:, :, pix], part["hit_prim"][:, :, pix])
     assert np.array_equal(full["radiance"][pix].view(np.uint32), part["radiance"][pix].view(np.uint32))
+
+
+# ---------------------------------------------------------------- next-event estimation
+def _scene(tri_list, mat_ids, mats, env, camera):
+    tris = np.array(tri_list, np.float64).reshape(-1, 3, 3).astype(np.float32)
+    return scenes.Scene(name="custom", tris=tris, tri_mat=np.array(mat_ids, np.uint32),
+                        mats=np.array(mats, dtype=scenes.MATERIAL_DTYPE), env=np.array(env, np.float32), camera=camera)
+
+
+@pytest.mark.parametrize("mode", ["incoherent", "reuse"])
+def test_nee_furnace_mean(orc, mode):
+    # closed box, every face Lambert rho and emissive E: with next-event estimation every
+    # hit's direct light is estimated from the emissive faces (form factors of a closed box
+    # sum to 1), so the mean stays E * sum_{k<=B} rho^k while single paths vary
+    rho, E, B = 0.5, 1.0, 3
+    sc = orc.OracleScene(scenes.furnace(rho, E))
+    r = sc.render(16, 16, 64, B, mode=mode, tile=(4, 4), k=4, seed=17, nee=True)
+    x = r["radiance"][..., 0].astype(np.float64).ravel()
+    expect = E * sum(rho ** i for i in range(B + 1))
+    z = abs(x.mean() - expect) / (x.std(ddof=1) / np.sqrt(x.size))
+    assert z < 4.0, (x.mean(), expect, z)
+    assert x.std() > 1e-3                        # the estimate is stochastic per pixel
+    assert (r["shadow_rays"][:B] > 0).all() and r["shadow_rays"][B] == 0
+
+
+def test_nee_blocked_light_adds_nothing(orc):
+    # floor (Lambert), a light above it hidden behind a large opaque blocker, no environment:
+    # with next-event estimation the floor under the blocker receives nothing (shadow rays
+    # blocked, emission of later hits not counted after a Lambert bounce); without the
+    # blocker every pixel receives direct light
+    mats = [scenes._mat(scenes.LAMBERT, (0.5, 0.5, 0.5)), scenes._mat(scenes.LAMBERT, (0.0, 0.0, 0.0), 0.0, (5.0, 5.0, 5.0)),
+            scenes._mat(scenes.LAMBERT, (0.0, 0.0, 0.0))]
+    floor = scenes.quad((-20, 0, -20), (-20, 0, 20), (20, 0, 20), (20, 0, -20))
+    light = scenes.quad((-1, 2, -1), (1, 2, -1), (1, 2, 1), (-1, 2, 1))
+    block = scenes.quad((-3, 1, -3), (3, 1, -3), (3, 1, 3), (-3, 1, 3))
+    cam = dict(pos=(10.0, 0.5, 0.0), look_at=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0), vfov=0.5)
+    s = _scene(floor + light + block, [0, 0, 1, 1, 2, 2], mats, (0.0, 0.0, 0.0), cam)
+    sc = orc.OracleScene(s)
+    on = sc.render(16, 16, 16, 1, mode="incoherent", seed=3, nee=True)
+    assert (on["hit_prim"][0] >= 0).all() and (on["hit_prim"][0] <= 1).all()     # camera rays hit the floor
+    assert on["shadow_rays"][0] == 16 * 16 * 16
+    assert (on["radiance"] == 0.0).all()
+    # the same without the blocker: every shadow ray reaches the light
+    open_ = orc.OracleScene(_scene(floor + light, [0, 0, 1, 1], mats[:2], (0.0, 0.0, 0.0), cam))
+    lit = open_.render(16, 16, 16, 1, mode="incoherent", seed=3, nee=True)
+    assert (lit["radiance"] > 0.0).all()
+
+
+def test_nee_matches_plain_estimate_in_mean(orc):
+    # mixed materials: Lambert points use next-event estimation, glossy and specular points
+    # count emission where their sampled rays hit it; the expected image is unchanged
+    s = scenes.mixed_small()
+    sc = orc.OracleScene(s)
+    w, h, spp, B = 32, 24, 96, 3
+    a = sc.render(w, h, spp, B, mode="reuse", tile=(8, 8), k=8, seed=41)["radiance"].astype(np.float64)
+    b = sc.render(w, h, spp, B, mode="reuse", tile=(8, 8), k=8, seed=42, nee=True)["radiance"].astype(np.float64)
+    D = (b - a).reshape(h // 4, 4, w // 4, 4, 3).mean(axis=(1, 3)).reshape(-1)
+    z = abs(D.mean()) / (D.std(ddof=1) / np.sqrt(D.size))
+    assert z < 4.0, z
+
+
+def test_nee_not_with_world_reuse(orc):
+    sc = orc.OracleScene(scenes.tiny())
+    with pytest.raises(ValueError):
+        sc.render(8, 8, 1, 2, mode="reuse_world", tile=(4, 4), k=4, seed=1, nee=True)
