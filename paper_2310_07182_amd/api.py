@@ -31,7 +31,8 @@ def camera_struct(cam: dict) -> capi.Camera:
     return c
 
 
-def group_struct(tile=(8, 8), k=8, reuse_max_bounce=0xFFFF, refill=0, waves_per_cu=0, leaf_gate=0) -> capi.Group:
+def group_struct(tile=(8, 8), k=8, reuse_max_bounce=0xFFFF, refill=0, waves_per_cu=0, leaf_gate=0,
+                 nee=False) -> capi.Group:
     g = capi.Group()
     g.tile_w, g.tile_h = int(tile[0]), int(tile[1])
     g.k = int(k)
@@ -39,6 +40,7 @@ def group_struct(tile=(8, 8), k=8, reuse_max_bounce=0xFFFF, refill=0, waves_per_
     g.refill = int(refill)
     g.waves_per_cu = int(waves_per_cu)
     g.leaf_gate = int(leaf_gate)
+    g.nee = int(bool(nee))
     return g
 
 
@@ -82,7 +84,7 @@ class Scene:
         i = capi.SceneInfo()
         check(lib().pt_scene_get_info(self.handle, C.byref(i)))
         return dict(ntri=i.ntri, nnodes=i.nnodes, max_depth=i.max_depth, max_leaf=i.max_leaf,
-                    lo=list(i.lo), hi=list(i.hi), sah_cost=i.sah_cost, device_bytes=i.device_bytes)
+                    lo=list(i.lo), hi=list(i.hi), sah_cost=i.sah_cost, device_bytes=i.device_bytes, nemit=i.nemit)
 
     def export_bvh(self):
         inf = self.info()
@@ -144,6 +146,7 @@ class RenderConfig:
     refill: int = 0
     waves_per_cu: int = 0
     leaf_gate: int = 0
+    nee: bool = False
 
 
 class Renderer:
@@ -156,7 +159,7 @@ class Renderer:
         dev = scene.device
         B = cfg.bounces
         rmax = B if cfg.reuse_max_bounce is None else cfg.reuse_max_bounce
-        self.group = group_struct(cfg.tile, cfg.k, rmax, cfg.refill, cfg.waves_per_cu, cfg.leaf_gate)
+        self.group = group_struct(cfg.tile, cfg.k, rmax, cfg.refill, cfg.waves_per_cu, cfg.leaf_gate, cfg.nee)
         self.mode = capi.MODES[cfg.mode]
         ws = lib().pt_render_workspace_bytes(cfg.w, cfg.h, cfg.spp, B, self.mode, self.group)
         if ws == 0:
@@ -167,6 +170,7 @@ class Renderer:
             self.hit_prim = torch.empty((B + 1, cfg.spp, cfg.h, cfg.w), dtype=torch.int32, device=dev)
             self.hit_t = torch.empty((B + 1, cfg.spp, cfg.h, cfg.w), dtype=torch.float32, device=dev)
             self.ray_count = torch.empty((B + 1, cfg.spp), dtype=torch.int32, device=dev)
+            self.shadow_count = torch.empty((B + 1, cfg.spp), dtype=torch.int32, device=dev) if cfg.nee else None
             self.stats = torch.empty((B + 1, 2), dtype=torch.int64, device=dev) if stats else None
             self.rays = torch.zeros((B + 1, cfg.spp, cfg.h, cfg.w, 8), dtype=torch.float32, device=dev) if rays else None
         self.timer = timer
@@ -178,6 +182,7 @@ class Renderer:
         self.out.stats = self.stats.data_ptr() if stats else None
         self.out.rays = self.rays.data_ptr() if rays else None
         self.out.timer = timer.handle if timer is not None else None
+        self.out.shadow_count = self.shadow_count.data_ptr() if cfg.nee else None
 
     def render(self, seed: int = 1, camera: dict | None = None):
         cfg = self.cfg
@@ -196,13 +201,16 @@ class Renderer:
             r["stats"] = self.stats
         if self.rays is not None:
             r["rays"] = self.rays
+        if self.shadow_count is not None:
+            r["shadow_rays_per_bounce"] = self.shadow_count.sum(dim=1)
         return r
 
 
 def render(scene: Scene, w, h, spp=1, bounces=2, mode="incoherent", tile=(8, 8), k=8,
-           reuse_max_bounce=None, seed=1, camera=None, stats=False, rays=False, refill=0, leaf_gate=0) -> dict:
-    r = Renderer(scene, RenderConfig(w, h, spp, bounces, mode, tuple(tile), k, reuse_max_bounce, refill, 0, leaf_gate),
-                 stats=stats, rays=rays)
+           reuse_max_bounce=None, seed=1, camera=None, stats=False, rays=False, refill=0, leaf_gate=0,
+           nee=False) -> dict:
+    r = Renderer(scene, RenderConfig(w, h, spp, bounces, mode, tuple(tile), k, reuse_max_bounce, refill, 0, leaf_gate,
+                                     nee), stats=stats, rays=rays)
     r.render(seed, camera)
     return r.results()
 

@@ -37,7 +37,7 @@ class Camera(C.Structure):
 class Group(C.Structure):
     _fields_ = [("tile_w", C.c_uint16), ("tile_h", C.c_uint16), ("k", C.c_uint16),
                 ("reuse_max_bounce", C.c_uint16), ("refill", C.c_uint16), ("waves_per_cu", C.c_uint16),
-                ("leaf_gate", C.c_uint16)]
+                ("leaf_gate", C.c_uint16), ("nee", C.c_uint16)]
 
 
 class SceneDesc(C.Structure):
@@ -48,12 +48,13 @@ class SceneDesc(C.Structure):
 class SceneInfo(C.Structure):
     _fields_ = [("ntri", C.c_uint32), ("nnodes", C.c_uint32), ("max_depth", C.c_uint32),
                 ("max_leaf", C.c_uint32), ("lo", C.c_float * 3), ("hi", C.c_float * 3),
-                ("sah_cost", C.c_double), ("device_bytes", C.c_uint64)]
+                ("sah_cost", C.c_double), ("device_bytes", C.c_uint64), ("nemit", C.c_uint32)]
 
 
 class Outputs(C.Structure):
     _fields_ = [("radiance", C.c_void_p), ("hit_prim", C.c_void_p), ("hit_t", C.c_void_p),
-                ("ray_count", C.c_void_p), ("stats", C.c_void_p), ("rays", C.c_void_p), ("timer", C.c_void_p)]
+                ("ray_count", C.c_void_p), ("stats", C.c_void_p), ("rays", C.c_void_p), ("timer", C.c_void_p),
+                ("shadow_count", C.c_void_p)]
 
 
 class Job(C.Structure):

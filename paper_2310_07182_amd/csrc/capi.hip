@@ -24,10 +24,11 @@ struct pt_scene_s {
     std::vector<float4> btris, otris;
     std::vector<uint32_t> tri_mat;
     std::vector<pt_material> mats;
+    std::vector<uint32_t> emit;     // emissive triangles, original order (next-event estimation)
     uint32_t ntri = 0, nmat = 0;
     float env[3] = {0, 0, 0};
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    size_t off_nodes = 0, off_btris = 0, off_otris = 0, off_mat = 0, off_mats = 0, bytes = 0;
+    size_t off_nodes = 0, off_btris = 0, off_otris = 0, off_mat = 0, off_mats = 0, off_emit = 0, bytes = 0;
     bool uploaded = false;
     int device = -1;
     DevScene dev{};
@@ -127,6 +128,7 @@ pt_status check_group(pt_group g, int bounces) {
     if ((int)g.k > wh) return fail(PT_EINVAL, "k (%d) must divide tile_w * tile_h (%d)", g.k, wh);
     if (g.refill > 64) return fail(PT_EINVAL, "refill must be in [0, 64] (got %d)", g.refill);
     if (g.leaf_gate > 64) return fail(PT_EINVAL, "leaf_gate must be in [0, 64] (got %d)", g.leaf_gate);
+    if (g.nee > 1) return fail(PT_EINVAL, "nee must be 0 or 1 (got %d)", g.nee);
     return PT_OK;
 }
 
@@ -166,6 +168,7 @@ Frame make_frame(int w, int h, int spp, int B, pt_mode mode, pt_group g, uint64_
     f.ntx = (w + f.W - 1) / f.W;
     f.nslots = (uint32_t)f.nstx * (uint32_t)f.nsty * (uint32_t)f.TS;
     f.seed = seed;
+    f.nee = g.nee;
     return f;
 }
 
@@ -191,6 +194,7 @@ void set_camera(Frame& f, const pt_camera* cam, int w, int h) {
 
 struct Layout {
     size_t q0, q1, state, work, partial, keys, vals, qs, sortws, ovf, total;
+    size_t shray, shc, sprim, st, swork, spartial;   // next-event estimation
 };
 
 Layout layout(const Frame& f) {
@@ -217,6 +221,20 @@ Layout layout(const Frame& f) {
         o = align256(o + qb);
         L.sortws = o;
         o = align256(o + pt::sort_workspace_bytes(f.nslots));
+    }
+    if (f.nee) {
+        L.shray = o;
+        o = align256(o + qb);
+        L.shc = o;
+        o = align256(o + (size_t)f.nslots * 16);
+        L.sprim = o;
+        o = align256(o + (size_t)f.nslots * 4);
+        L.st = o;
+        o = align256(o + (size_t)f.nslots * 4);
+        L.swork = o;
+        o = align256(o + launches * 4);
+        L.spartial = o;
+        o = align256(o + launches * pt::kMaxTraceBlocks * 4);
     }
     L.ovf = o;
     o = align256(o + (size_t)pt::kMaxTraceBlocks * pt::kTraceBlock * pt::kStackOvf * 4);
@@ -354,6 +372,10 @@ pt_status pt_scene_create(const pt_scene_desc* d, pt_scene* out) {
         }
         s->tri_mat.assign(d->tri_mat, d->tri_mat + n);
         s->mats.assign(d->mats, d->mats + d->nmat);
+        for (uint32_t i = 0; i < n; ++i) {
+            const float* em = s->mats[s->tri_mat[i]].emission;
+            if (em[0] > 0.0f || em[1] > 0.0f || em[2] > 0.0f) s->emit.push_back(i);
+        }
         for (int a = 0; a < 3; ++a) s->env[a] = d->env_radiance[a];
         size_t o = 0;
         s->off_nodes = o;
@@ -366,6 +388,8 @@ pt_status pt_scene_create(const pt_scene_desc* d, pt_scene* out) {
         o = align256(o + s->tri_mat.size() * 4);
         s->off_mats = o;
         o = align256(o + s->mats.size() * sizeof(pt_material));
+        s->off_emit = o;
+        o = align256(o + s->emit.size() * 4);
         s->bytes = o;
     } catch (const std::bad_alloc&) {
         delete s;
@@ -393,6 +417,7 @@ pt_status pt_scene_upload(pt_scene s, void* arena, size_t bytes, void* stream) {
         {s->off_otris, s->otris.data(), s->otris.size() * sizeof(float4)},
         {s->off_mat, s->tri_mat.data(), s->tri_mat.size() * 4},
         {s->off_mats, s->mats.data(), s->mats.size() * sizeof(pt_material)},
+        {s->off_emit, s->emit.data(), s->emit.size() * 4},
     };
     for (const Part& p : parts) {
         if (p.n == 0) continue;
@@ -411,8 +436,10 @@ pt_status pt_scene_upload(pt_scene s, void* arena, size_t bytes, void* stream) {
     d.otris = (const float4*)(base + s->off_otris);
     d.tri_mat = (const uint32_t*)(base + s->off_mat);
     d.mats = (const pt_material*)(base + s->off_mats);
+    d.emit = (const uint32_t*)(base + s->off_emit);
     d.ntri = s->ntri;
     d.nmat = s->nmat;
+    d.nemit = (uint32_t)s->emit.size();
     for (int a = 0; a < 3; ++a) {
         d.env[a] = s->env[a];
         d.lo[a] = s->lo[a];
@@ -435,6 +462,7 @@ pt_status pt_scene_get_info(pt_scene s, pt_scene_info* info) {
     }
     info->sah_cost = s->bvh.sah_cost;
     info->device_bytes = s->bytes;
+    info->nemit = (uint32_t)s->emit.size();
     return PT_OK;
 }
 
@@ -467,6 +495,8 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
         return fail(PT_EINVAL, "unknown mode %d", (int)mode);
     pt_status cs = check_group(g, B);
     if (cs != PT_OK) return cs;
+    if (g.nee && mode == PT_MODE_REUSE_WORLD)
+        return fail(PT_EUNSUPPORTED, "next-event estimation is not combined with direct world-space reuse");
     if (!out->radiance || !out->hit_prim || !out->hit_t) return fail(PT_EINVAL, "radiance, hit_prim and hit_t are required");
     if (!workspace) return fail(PT_EINVAL, "null workspace");
     int dev = 0;
@@ -493,6 +523,8 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
         TimerScope ts(out->timer, st, 6, -1);
         e = pt::launch_zero(work, launches, st);
         if (e == hipSuccess && out->stats) e = pt::launch_zero((uint32_t*)out->stats, (size_t)(B + 1) * 4, st);
+        if (e == hipSuccess && f.nee) e = pt::launch_zero((uint32_t*)(ws + L.swork), launches, st);
+        if (e == hipSuccess && out->shadow_count) e = pt::launch_zero(out->shadow_count, launches, st);
     }
     if (e != hipSuccess) return hip_fail(e, "launch (zero)");
     const int grid = pt::trace_grid_blocks(g.waves_per_cu);
@@ -546,18 +578,55 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
                 e = pt::launch_trace(scene->dev, ta, out->stats != nullptr, st);
             }
             if (e != hipSuccess) return hip_fail(e, "launch (trace)");
+            float4* shray = f.nee ? (float4*)(ws + L.shray) : nullptr;
+            float4* shc = f.nee ? (float4*)(ws + L.shc) : nullptr;
             {
                 TimerScope ts(out->timer, st, 2, b);
                 e = pt::launch_shade(scene->dev, f, b, s, q[b & 1], q[(b + 1) & 1], state, out->hit_prim, out->hit_t,
-                                     out->radiance, (float4*)out->rays, st);
+                                     out->radiance, (float4*)out->rays, shray, shc, st);
             }
             if (e != hipSuccess) return hip_fail(e, "launch (shade)");
+            if (f.nee && b < B) {
+                // shadow rays of the Lambert points of this hit, then their light into the paths
+                int32_t* sprim = (int32_t*)(ws + L.sprim);
+                pt::TraceArgs sa{};
+                sa.rays = shray;
+                sa.n = n;
+                sa.work = (uint32_t*)(ws + L.swork) + li;
+                sa.out_prim = sprim;
+                sa.out_t = (float*)(ws + L.st);
+                sa.partial = out->shadow_count ? (uint32_t*)(ws + L.spartial) + li * pt::kMaxTraceBlocks : nullptr;
+                sa.ovf = ovf;
+                sa.by_pixel = 0;
+                sa.shadow = 1;
+                sa.skip_empty = 1;
+                sa.refill = g.refill ? g.refill : kDefaultRefill;
+                sa.waves_per_cu = g.waves_per_cu;
+                sa.leaf_gate = (g.leaf_gate ? g.leaf_gate : pt::kDefaultLeafGate) - 1;
+                {
+                    TimerScope ts(out->timer, st, 7, b);
+                    e = pt::launch_trace(scene->dev, sa, false, st);
+                }
+                if (e != hipSuccess) return hip_fail(e, "launch (shadow trace)");
+                {
+                    TimerScope ts(out->timer, st, 8, b);
+                    e = pt::launch_nee_accumulate(shray, shc, sprim, f.nslots, state, st);
+                }
+                if (e != hipSuccess) return hip_fail(e, "launch (shadow accumulate)");
+            }
         }
     }
     if (out->ray_count) {
         TimerScope ts(out->timer, st, 6, -1);
         e = pt::launch_count_finalize(partial, pt::kMaxTraceBlocks, grid, (int)launches, out->ray_count, st);
         if (e != hipSuccess) return hip_fail(e, "launch (count)");
+    }
+    if (out->shadow_count && f.nee && B > 0) {
+        // launches of bounces 0..B-1 hold shadow rays: the first B * spp entries
+        TimerScope ts(out->timer, st, 6, -1);
+        e = pt::launch_count_finalize((uint32_t*)(ws + L.spartial), pt::kMaxTraceBlocks, grid, B * spp,
+                                      out->shadow_count, st);
+        if (e != hipSuccess) return hip_fail(e, "launch (shadow count)");
     }
     return PT_OK;
 }
@@ -731,6 +800,7 @@ pt_status pt_batch_create(int max_jobs, pt_group group, void* arena, size_t byte
     if (max_jobs <= 0 || max_jobs > 65536) return fail(PT_EINVAL, "max_jobs must be in [1, 65536]");
     pt_status cs = check_group(group, 0);
     if (cs != PT_OK) return cs;
+    if (group.nee) return fail(PT_EUNSUPPORTED, "batches do not run next-event estimation");
     if (((uintptr_t)arena & 255) != 0) return fail(PT_EINVAL, "arena must be 256-byte aligned");
     const size_t base = pt_batch_base_bytes(max_jobs);
     if (bytes < base) return fail(PT_ENOMEM, "arena too small: %zu < %zu", bytes, base);

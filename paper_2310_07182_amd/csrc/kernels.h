@@ -16,7 +16,8 @@ struct DevScene {
     const float4* otris;     // [ntri][3]    original order
     const uint32_t* tri_mat; // [ntri]
     const pt_material* mats; // [nmat]
-    uint32_t ntri, nmat;
+    const uint32_t* emit;    // [nemit] emissive triangles, original order
+    uint32_t ntri, nmat, nemit;
     float env[3];
     float lo[3], hi[3];
 };
@@ -31,10 +32,13 @@ struct Frame {
     uint64_t seed;
     float cpos[3], cfwd[3], cright[3], cup[3];
     float th, thx;
+    int nee;                  // next-event estimation at Lambert points
 };
 
 // Ray queue record: {ox, oy, oz, excluded prim} {dx, dy, dz, pixel}; pixel = kNoRay: no ray.
 constexpr uint32_t kNoRay = 0xFFFFFFFFu;
+// shadow rays run along D = light point - origin; a hit at t >= kShadowTmax is the light itself
+constexpr float kShadowTmax = 1.0f - 0x1p-10f;
 constexpr int kTraceBlock = 64;    // one wave per workgroup
 constexpr int kStackLds = 16;      // LDS stack entries per lane
 constexpr int kStackOvf = kMaxDepth - kStackLds + 16; // global overflow entries per lane
@@ -55,6 +59,8 @@ struct TraceArgs {
     int refill;                // a wave fetches new rays once this many lanes are idle (1..64)
     int waves_per_cu;          // persistent grid size, 0 = kDefaultWavesPerCu
     int leaf_gate;             // the inner-node phase ends when at most this many lanes lack a leaf
+    int shadow;                // shadow rays: blocked iff a triangle lies at 0 < t < kShadowTmax (units of d)
+    int skip_empty;            // rays whose pixel word is kNoRay are skipped (not traced, no output)
 };
 
 // One job of a merged launch (batched rendering): the shade, raygen and trace launches of a
@@ -97,7 +103,11 @@ hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t st);
 hipError_t launch_raygen(const Frame& f, int s, float4* q, float4* state, float4* rays_out, hipStream_t st);
 hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const float4* q_in, float4* q_out,
                         float4* state, int32_t* hit_prim, float* hit_t, float* radiance, float4* rays_out,
-                        hipStream_t st);
+                        float4* shadow_rays, float4* shadow_light, hipStream_t st);
+// next-event estimation: adds shadow_light[p].rgb to the radiance of path p when its shadow
+// ray exists (pixel word != kNoRay) and shadow_prim[p] == -1 (nothing in between)
+hipError_t launch_nee_accumulate(const float4* shadow_rays, const float4* shadow_light, const int32_t* shadow_prim,
+                                 uint32_t n, float4* state, hipStream_t st);
 hipError_t launch_keys(const DevScene& sc, const float4* q, uint32_t n, uint32_t* keys, uint32_t* vals, int kind,
                        hipStream_t st);
 // ray_count[i] = sum of partial[i * stride + j] for j < parts, i < launches

@@ -319,15 +319,17 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
                     }
                     const float4 r0 = rays[2 * (size_t)li], r1 = rays[2 * (size_t)li + 1];
                     const uint32_t pix = __float_as_uint(r1.w);
-                    if (!a.by_pixel || pix != kNoRay) {
+                    if (!(a.by_pixel || a.skip_empty) || pix != kNoRay) {
                         o = xyz(r0);
                         const V3 d = xyz(r1);
                         excl = __float_as_int(r0.w);
                         inv = mk3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
                         rp = prepare(o, d);
-                        best_t = INFINITY;
-                        tcull = INFINITY;
-                        best_p = INT32_MAX;
+                        // a shadow ray only asks whether anything lies before the light point:
+                        // hits are kept from t < kShadowTmax on, and INT32_MIN never loses a tie
+                        best_t = a.shadow ? kShadowTmax : INFINITY;
+                        tcull = a.shadow ? kShadowTmax * kCullScale : INFINITY;
+                        best_p = a.shadow ? INT32_MIN : INT32_MAX;
                         sp = 0;
                         novf = 0;
                         node = 0;
@@ -482,7 +484,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
             leaf = kNoLeaf;
         }
         if (have && node == kDone) {
-            oprim[oi] = best_p == INT32_MAX ? -1 : best_p;
+            oprim[oi] = (best_p == INT32_MAX || best_p == INT32_MIN) ? -1 : best_p;
             ot[oi] = best_t;
             ++traced;
             have = false;
@@ -580,7 +582,7 @@ __global__ __launch_bounds__(1024) void k_raygen_multi(const StepJob* jobs, int 
 __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, int b, int s, uint32_t blk,
                                            const float4* __restrict__ q_in, float4* __restrict__ q_out,
                                            float4* state, int32_t* hit_prim, float* hit_t, float* radiance,
-                                           float4* rays_out, float* lds) {
+                                           float4* rays_out, float4* shadow_rays, float4* shadow_light, float* lds) {
     // group exchange in LDS, TS entries each: own tangent exit, tree sums, info bits, min active slot
     const int TS = f.TS;
     float* sq0 = lds;
@@ -598,6 +600,7 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
     float4 s0 = state[2 * (size_t)p], s1 = state[2 * (size_t)p + 1];
     float T[3] = {s0.x, s0.y, s0.z}, L[3] = {s1.x, s1.y, s1.z};
     const bool alive_in = (__float_as_uint(s0.w) & 1u) != 0;
+    const bool nee_prev = (__float_as_uint(s0.w) & 2u) != 0;   // the ray left a Lambert point with NEE
     bool alive = alive_in;
     const uint32_t qpos = __float_as_uint(s1.w);
     const size_t plane = (size_t)f.w * (size_t)f.h;
@@ -630,9 +633,11 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
         tv1 = tp[1];
         tv2 = tp[2];
     }
+    // emission that next-event estimation already counted at the previous Lambert point is skipped
+    const bool add_le = alive_in && !(hit && nee_prev);
     for (int c = 0; c < 3; ++c) {
         const float le = hit ? m.emission[c] : sc.env[c];
-        L[c] = alive_in ? L[c] + T[c] * le : L[c];
+        L[c] = add_le ? L[c] + T[c] * le : L[c];
     }
     const bool absorb = m.albedo[0] == 0.0f && m.albedo[1] == 0.0f && m.albedo[2] == 0.0f;
     const bool active = hit && b < f.B && !absorb;
@@ -657,6 +662,41 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
     const bool own_ok = active && (kind == 0 ? true : (kind == 1 ? g_ok : mir.z > 0.0f));
     float w3[3];
     for (int c = 0; c < 3; ++c) w3[c] = kind == 1 ? gw[c] : m.albedo[c];
+    // next-event estimation: one emissive triangle and a point on it, a shadow ray from the
+    // offset origin along D = point - origin; the light is added once the ray is unblocked
+    float4 sh0 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1)), sh1 = make_float4(0.f, 0.f, 0.f, __uint_as_float(kNoRay));
+    float4 shl = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (shadow_rays && f.nee && active && kind == 0 && sc.nemit > 0) {
+        const U64x4 rl = philox(pix, (uint64_t)s, (uint64_t)b, 2, f.seed);
+        const uint32_t e = sc.emit[(uint32_t)(rl.v[0] % (uint64_t)sc.nemit)];
+        const float u1 = unit01(rl.v[1]), uu2 = unit01(rl.v[2]);
+        const float4* lp = sc.otris + 3 * (size_t)e;
+        const V3 l0 = xyz(lp[0]), l1 = xyz(lp[1]), l2 = xyz(lp[2]);
+        const float su = sqrtf(u1);
+        const float b0 = 1.0f - su, b1 = uu2 * su;
+        const float b2 = (1.0f - b0) - b1;
+        const V3 lq = mk3((b0 * l0.x + b1 * l1.x) + b2 * l2.x, (b0 * l0.y + b1 * l1.y) + b2 * l2.y,
+                          (b0 * l0.z + b1 * l1.z) + b2 * l2.z);
+        const V3 D = sub3(lq, origin);
+        const float cs = dot3(D, n);
+        if (cs > 0.0f) {
+            const V3 nl = cross3(sub3(l1, l0), sub3(l2, l0));
+            const float cl = fabsf(dot3(D, nl));
+            const float d2 = dot3(D, D);
+            const float g = (cs * cl) / (d2 * d2);
+            const float k = g * ((float)sc.nemit * (float)(1.0 / (2.0 * 3.14159265358979323846)));
+            const pt_material& ml = sc.mats[sc.tri_mat[e]];
+            shl = make_float4((T[0] * m.albedo[0]) * (ml.emission[0] * k), (T[1] * m.albedo[1]) * (ml.emission[1] * k),
+                              (T[2] * m.albedo[2]) * (ml.emission[2] * k), 0.0f);
+            sh0 = make_float4(origin.x, origin.y, origin.z, __int_as_float(prim));
+            sh1 = make_float4(D.x, D.y, D.z, __uint_as_float(pix));
+        }
+    }
+    if (shadow_rays) {
+        shadow_rays[2 * (size_t)p] = sh0;
+        shadow_rays[2 * (size_t)p + 1] = sh1;
+        shadow_light[p] = shl;
+    }
     V3 use = own;
     bool use_ok = own_ok;
     bool use_world = false;   // direct reuse: the next direction is given in world space
@@ -755,15 +795,33 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
             hit_t[at] = INFINITY;
         }
     }
-    state[2 * (size_t)p] = make_float4(T[0], T[1], T[2], __uint_as_float(alive ? 1u : 0u));
+    // the next hit's emission is skipped when this point estimated its direct light
+    const bool nee_next = alive && f.nee && kind == 0;
+    state[2 * (size_t)p] = make_float4(T[0], T[1], T[2], __uint_as_float((alive ? 1u : 0u) | (nee_next ? 2u : 0u)));
     state[2 * (size_t)p + 1] = make_float4(L[0], L[1], L[2], __uint_as_float(newpos));
 }
 
 __global__ __launch_bounds__(1024) void k_shade(DevScene sc, Frame f, int b, int s, const float4* __restrict__ q_in,
                                                 float4* __restrict__ q_out, float4* state, int32_t* hit_prim,
-                                                float* hit_t, float* radiance, float4* rays_out) {
+                                                float* hit_t, float* radiance, float4* rays_out, float4* shadow_rays,
+                                                float4* shadow_light) {
     extern __shared__ float lds[];
-    shade_body(sc, f, b, s, blockIdx.x, q_in, q_out, state, hit_prim, hit_t, radiance, rays_out, lds);
+    shade_body(sc, f, b, s, blockIdx.x, q_in, q_out, state, hit_prim, hit_t, radiance, rays_out, shadow_rays,
+               shadow_light, lds);
+}
+
+// adds the light of unblocked shadow rays to their paths (one thread per path slot)
+__global__ __launch_bounds__(256) void k_nee_accumulate(const float4* shadow_rays, const float4* shadow_light,
+                                                        const int32_t* shadow_prim, uint32_t n, float4* state) {
+    const uint32_t p = blockIdx.x * 256u + threadIdx.x;
+    if (p >= n) return;
+    if (__float_as_uint(shadow_rays[2 * (size_t)p + 1].w) == kNoRay || shadow_prim[p] != -1) return;
+    const float4 c = shadow_light[p];
+    float4 s1 = state[2 * (size_t)p + 1];
+    s1.x = s1.x + c.x;
+    s1.y = s1.y + c.y;
+    s1.z = s1.z + c.z;
+    state[2 * (size_t)p + 1] = s1;
 }
 
 __global__ __launch_bounds__(1024) void k_shade_multi(const StepJob* jobs, int njobs) {
@@ -771,7 +829,7 @@ __global__ __launch_bounds__(1024) void k_shade_multi(const StepJob* jobs, int n
     const int j = job_of_block(jobs, njobs, blockIdx.x);
     const StepJob& J = jobs[j];
     shade_body(J.sc, J.f, J.b, J.s, blockIdx.x - J.block_start, J.q_in, J.q_out, J.state, J.hit_prim, J.hit_t,
-               J.radiance, nullptr, lds);
+               J.radiance, nullptr, nullptr, nullptr, lds);
 }
 
 // ------------------------------------------------------------------ two-point key, gather
@@ -1094,12 +1152,20 @@ hipError_t launch_raygen(const Frame& f, int s, float4* q, float4* state, float4
 
 hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const float4* q_in, float4* q_out,
                         float4* state, int32_t* hit_prim, float* hit_t, float* radiance, float4* rays_out,
-                        hipStream_t st) {
+                        float4* shadow_rays, float4* shadow_light, hipStream_t st) {
     const unsigned blocks = (unsigned)(f.nslots / (uint32_t)f.TS);
     const bool reuse = f.mode == PT_MODE_REUSE || f.mode == PT_MODE_REUSE_PLAIN || f.mode == PT_MODE_REUSE_WORLD;
     const size_t lds = reuse ? (size_t)f.TS * 8 * sizeof(float) : 0;
     hipLaunchKernelGGL(k_shade, dim3(blocks), dim3(f.TS), lds, st, sc, f, b, s, q_in, q_out, state, hit_prim, hit_t,
-                       radiance, rays_out);
+                       radiance, rays_out, shadow_rays, shadow_light);
+    return hipGetLastError();
+}
+
+hipError_t launch_nee_accumulate(const float4* shadow_rays, const float4* shadow_light, const int32_t* shadow_prim,
+                                 uint32_t n, float4* state, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_nee_accumulate, dim3((n + 255) / 256), dim3(256), 0, st, shadow_rays, shadow_light,
+                       shadow_prim, n, state);
     return hipGetLastError();
 }
 

@@ -207,3 +207,28 @@ def test_probe_rejects_before_touching_device(L):
     assert L.pt_probe_memory(C.c_void_p(257), 1 << 20, 1, 1, C.byref(g), C.byref(ns), None) == capi.PT_EINVAL
     assert L.pt_probe_memory(C.c_void_p(256), 1 << 20, 0, 1, C.byref(g), C.byref(ns), None) == capi.PT_EINVAL
     assert L.pt_probe_memory(C.c_void_p(256), 1 << 20, 1, 1 << 25, C.byref(g), C.byref(ns), None) == capi.PT_EINVAL
+
+
+def test_nee_checks(L):
+    g = _group(8, 8, 8)
+    g.nee = 2
+    j = capi.Job()
+    j.w, j.h, j.spp, j.bounces, j.mode = 64, 64, 1, 2, capi.MODES["reuse"]
+    assert L.pt_batch_job_bytes(C.byref(j), g) == 0
+    g.nee = 1
+    assert L.pt_render_workspace_bytes(64, 64, 1, 2, capi.MODES["reuse"], g) > \
+        L.pt_render_workspace_bytes(64, 64, 1, 2, capi.MODES["reuse"], _group(8, 8, 8))
+    # batches refuse next-event estimation before touching the device
+    h = C.c_void_p()
+    assert L.pt_batch_create(4, g, C.c_void_p(1 << 20), 1 << 30, C.byref(h)) == capi.PT_EUNSUPPORTED
+
+
+def test_scene_counts_emitters(L):
+    s = scenes.mixed_small()
+    st, h, keep = _create(L, s)
+    assert st == capi.PT_OK
+    info = capi.SceneInfo()
+    assert L.pt_scene_get_info(h, C.byref(info)) == capi.PT_OK
+    em = s["mats"]["emission"].max(axis=1) > 0
+    assert info.nemit == int(em[s["tri_mat"]].sum()) > 0
+    L.pt_scene_free(h)

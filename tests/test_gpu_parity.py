@@ -149,6 +149,27 @@ def test_render_parity_reuse_ablations(api, orc, torch_dev, mode, tile, k, w, h,
     _say("  ", res)
 
 
+@pytest.mark.parametrize("name,mode,tile,k,w,h,spp,B", [
+    ("mixed_small", "incoherent", (8, 8), 8, 101, 67, 1, 4),
+    ("mixed_small", "reuse", (8, 8), 8, 101, 67, 2, 4),
+    ("mixed_small", "sorted", (8, 8), 8, 77, 41, 1, 3),
+    ("mixed_small", "reuse_plain", (4, 4), 2, 64, 48, 1, 3),
+    ("furnace", "reuse", (4, 4), 4, 32, 32, 2, 3),
+    ("tiny", "incoherent", (8, 8), 8, 40, 30, 1, 2),
+])
+def test_render_parity_nee(api, orc, torch_dev, name, mode, tile, k, w, h, spp, B):
+    s, sc, osc = both(api, orc, name)
+    _say(f"[gpu] nee render {name} {w}x{h} spp={spp} B={B} mode={mode}")
+    g = api.render(sc, w, h, spp, B, mode, tile, k, None, 321, nee=True)
+    torch_dev.cuda.synchronize()
+    o = osc.render(w, h, spp, B, mode=mode, tile=tile, k=k, seed=321, nee=True)
+    res = compare_render(g, o, tile, mode)
+    _say("  ", res)
+    assert np.array_equal(g["shadow_rays_per_bounce"].cpu().numpy(), o["shadow_rays"].astype(np.int64))
+    if name != "tiny":
+        assert o["shadow_rays"][:B].sum() > 0
+
+
 def test_reuse_max_bounce_one(api, orc, torch_dev):
     s, sc, osc = both(api, orc, "mixed_small")
     g = gpu_render(api, sc, 64, 48, 1, 3, "reuse", (8, 8), 8, 5, rmax=1)
