@@ -69,9 +69,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bench_mode(api, sc, cfg, mode, steps, warmup, seed0):
+def bench_mode(api, sc, cfg, mode, steps, warmup, seed0, nee=False):
     import torch
-    rc = api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], mode, tuple(cfg["tile"]), cfg["k"])
+    rc = api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], mode, tuple(cfg["tile"]), cfg["k"], nee=nee)
     # untimed counting frame: nodes / triangles per ray and rays per bounce
     rs = api.Renderer(sc, rc, stats=True)
     rs.render(seed0)
@@ -118,6 +118,12 @@ def bench_mode(api, sc, cfg, mode, steps, warmup, seed0):
     ops_per_ray = nodes_per_ray * OPS_PER_NODE + tris_per_ray * OPS_PER_TRI
     ops_per_launch = ops_per_ray * sec_rays / B
     kinds = {int(k): float(ms[kind == k].sum() / steps) for k in np.unique(kind)}
+    shadow = {}
+    if nee:
+        srays = r.shadow_count.cpu().numpy().astype(np.float64).sum()
+        sms = ms[kind == 7].sum() / steps
+        shadow = dict(shadow_rays_per_frame=int(srays), shadow_trace_ms_per_frame=float(sms),
+                      shadow_mrays_s=float(srays / (sms * 1e-3) / 1e6) if sms > 0 else 0.0)
     return dict(mode=mode, secondary_mrays_s=mrays, end_to_end_secondary_mrays_s=e2e,
                 frame_ms_mean=float(frame_ms.mean()), frame_ms_p50=float(np.percentile(frame_ms, 50)),
                 frame_ms_p99=float(np.percentile(frame_ms, 99)), wall_s=wall,
@@ -126,7 +132,7 @@ def bench_mode(api, sc, cfg, mode, steps, warmup, seed0):
                 tris_per_ray=float(tris_per_ray), bytes_per_ray=float(bytes_per_ray),
                 avg_trace_launch_ms=float(avg_launch_ms), trace_launches=launches,
                 bytes_per_launch=float(bytes_per_launch), ops_per_ray=float(ops_per_ray),
-                ops_per_launch=float(ops_per_launch), ms_by_kind=kinds)
+                ops_per_launch=float(ops_per_launch), ms_by_kind=kinds, **shadow)
 
 
 def cpu_baseline(scene, cfg, name, budget_s=15.0, seed=2310071821):
@@ -372,8 +378,8 @@ def bench_quality(api, sc, cfg, args):
     import torch
     w, h, B = cfg["w"], cfg["h"], cfg["bounces"]
 
-    def average(mode, tile, k, frames, seed0):
-        r = api.Renderer(sc, api.RenderConfig(w, h, 1, B, mode, tile, k))
+    def average(mode, tile, k, frames, seed0, nee=False):
+        r = api.Renderer(sc, api.RenderConfig(w, h, 1, B, mode, tile, k, nee=nee))
         acc = torch.zeros((h, w, 3), dtype=torch.float64, device="cuda:0")
         for i in range(frames):
             r.render(seed0 + i)
@@ -381,9 +387,9 @@ def bench_quality(api, sc, cfg, args):
         torch.cuda.synchronize()
         return acc / frames
 
-    def trace_speed(mode, tile, k):
+    def trace_speed(mode, tile, k, nee=False):
         timer = api.Timer(4096)
-        r = api.Renderer(sc, api.RenderConfig(w, h, 1, B, mode, tile, k), timer=timer)
+        r = api.Renderer(sc, api.RenderConfig(w, h, 1, B, mode, tile, k, nee=nee), timer=timer)
         for i in range(3):
             r.render(11 + i)
         torch.cuda.synchronize()
@@ -430,6 +436,15 @@ def bench_quality(api, sc, cfg, args):
                     "speedup_vs_incoherent": round(v / out["incoherent"]["secondary_mrays_s"], 3)})
         log(f"[quality] {mode} {tile} K={k}: {abl[-1]}")
     out["ablations"] = abl
+    # next-event estimation (the future-work extension): same expectation, less noise
+    nee_rows = []
+    for mode in ("incoherent", "reuse"):
+        q = psnr(average(mode, (8, 8), 8, args.quality_frames, 1, nee=True))
+        v = trace_speed(mode, (8, 8), 8, nee=True)
+        nee_rows.append({"mode": mode, "nee": True, "tile": [8, 8], "k": 8, "psnr_db": round(q, 3),
+                         "secondary_mrays_s": round(v, 1)})
+        log(f"[quality] {mode} + NEE: {nee_rows[-1]}")
+    out["nee"] = nee_rows
     return out
 
 
@@ -457,6 +472,8 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--max-jobs", type=int, default=64)
+    ap.add_argument("--nee", action="store_true",
+                    help="next-event estimation at Lambert points (shadow rays), reported beside the paths")
     ap.add_argument("--quality", action="store_true",
                     help="PSNR against a many-frame reference and the (W,H) x K speed sweep")
     ap.add_argument("--quality-frames", type=int, default=128)
@@ -526,7 +543,7 @@ def main():
     results = {}
     for i, mode in enumerate(args.modes.split(",")):
         log(f"[bench] mode {mode}: warmup {args.warmup}, steps {args.steps}")
-        results[mode] = bench_mode(api, sc, cfg, mode, args.steps, args.warmup, 2310071821 + 100000 * i)
+        results[mode] = bench_mode(api, sc, cfg, mode, args.steps, args.warmup, 2310071821 + 100000 * i, args.nee)
         log(f"[bench] {mode}: {json.dumps(results[mode])}")
     head = results.get("reuse") or next(iter(results.values()))
     log("[bench] memory ceilings")
@@ -558,12 +575,15 @@ def main():
         "data": "synthetic (seeded procedural scene standing in for the paper's archived scenes)",
         "config": {"workload": f"{args.config}: {cfg['w']}x{cfg['h']}, 1 spp, {cfg['bounces']} bounces, "
                                f"{scene.ntri} triangles, tile {cfg['tile'][0]}x{cfg['tile'][1]}, K={cfg['k']}",
-                   "mode": head["mode"], "parallelism": "single GPU"},
+                   "mode": head["mode"], "parallelism": "single GPU", "nee": bool(args.nee)},
         "modes": {m: {"secondary_mrays_s": round(v["secondary_mrays_s"], 3),
                       "end_to_end_secondary_mrays_s": round(v["end_to_end_secondary_mrays_s"], 3),
                       "frame_ms_p50": round(v["frame_ms_p50"], 4), "frame_ms_p99": round(v["frame_ms_p99"], 4),
                       "rays_per_bounce": v["rays_per_bounce"], "nodes_per_ray": round(v["nodes_per_ray"], 2),
-                      "tris_per_ray": round(v["tris_per_ray"], 2)} for m, v in results.items()},
+                      "tris_per_ray": round(v["tris_per_ray"], 2),
+                      **({"shadow_mrays_s": round(v["shadow_mrays_s"], 3),
+                          "shadow_rays_per_frame": v["shadow_rays_per_frame"]} if args.nee else {})}
+                  for m, v in results.items()},
         "p99_frame_ms": round(head["frame_ms_p99"], 4),
         "roofline": {"bound": "alu", "achieved": round(achieved_ops, 3), "peak": round(VALU_PEAK_TOPS, 2),
                      "unit": "TFLOP/s", "frac": round(achieved_ops / VALU_PEAK_TOPS, 4), "traffic": measured_traffic(head["mode"], args.config),

@@ -477,6 +477,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
                         best_t = tt;
                         best_p = pp;
                         tcull = tt * kCullScale;
+                        if (a.shadow) node = kDone;   // blocked: the shadow ray is answered
                     }
                 }
             }
