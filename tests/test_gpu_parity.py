@@ -288,3 +288,46 @@ def test_indoor_full_size_sampled_tiles(api, orc, torch_dev, mode):
     # property over the whole image: rays per bounce count the traced rays
     hp = g["hit_prim"].cpu().numpy()
     assert np.array_equal(g["rays_per_bounce"].cpu().numpy(), (hp != -2).reshape(B + 1, -1).sum(1))
+
+
+# ------------------------------------------------------------------ edge shapes and limits
+@pytest.mark.parametrize("w,h,tile,k,mode", [
+    (1, 1, (1, 1), 1, "reuse"), (1, 1, (8, 8), 8, "reuse"), (2, 3, (2, 2), 2, "reuse"), (7, 1, (4, 4), 16, "reuse"),
+    (1, 9, (1, 8), 4, "reuse"), (33, 17, (32, 32), 1024, "reuse"), (64, 64, (32, 32), 1024, "reuse"),
+    (5, 5, (1, 1), 1, "sorted"), (3, 2, (8, 8), 8, "incoherent"),
+])
+def test_render_parity_edge_shapes(api, orc, torch_dev, w, h, tile, k, mode):
+    s, sc, osc = both(api, orc, "mixed_small")
+    g = gpu_render(api, sc, w, h, 2, 3, mode, tile, k, 55)
+    o = osc.render(w, h, 2, 3, mode=mode, tile=tile, k=k, seed=55)
+    compare_render(g, o, tile, mode)
+
+
+def test_render_parity_deep_paths(api, orc, torch_dev):
+    # 16 bounces in the closed furnace: every path survives to the end
+    s, sc, osc = both(api, orc, "furnace")
+    g = gpu_render(api, sc, 24, 24, 3, 16, "reuse", (8, 8), 8, 9)
+    o = osc.render(24, 24, 3, 16, mode="reuse", tile=(8, 8), k=8, seed=9)
+    compare_render(g, o, (8, 8), "reuse")
+    assert (g["hit_prim"].cpu().numpy() >= 0).all()
+
+
+@pytest.mark.parametrize("mode", ["reuse", "sorted"])
+def test_indoor_4k_sampled_tiles(api, orc, torch_dev, mode):
+    # the largest frame the tests render: 3840x2160, 4 bounces, sampled tiles checked
+    s, sc, osc = both(api, orc, "indoor")
+    w, h, B, tile, k = 3840, 2160, 4, (8, 8), 8
+    g = gpu_render(api, sc, w, h, 1, B, mode, tile, k, 77)
+    ntx, nty = w // 8, h // 8
+    rng = np.random.default_rng(99)
+    mask = np.zeros(ntx * nty, np.uint8)
+    mask[rng.choice(ntx * nty, 12, replace=False)] = 1
+    mask[[0, ntx * nty - 1]] = 1
+    o = osc.render(w, h, 1, B, mode=mode, tile=tile, k=k, seed=77, tile_mask=mask)
+    pm = np.zeros((h, w), bool)
+    for t in np.where(mask)[0]:
+        ty, tx = divmod(int(t), ntx)
+        pm[ty * 8:(ty + 1) * 8, tx * 8:(tx + 1) * 8] = True
+    compare_render(g, o, tile, mode, pixel_mask=pm)
+    hp = g["hit_prim"].cpu().numpy()
+    assert np.array_equal(g["rays_per_bounce"].cpu().numpy(), (hp != -2).reshape(B + 1, -1).sum(1))
