@@ -40,7 +40,7 @@ OPS_PER_NODE, OPS_PER_TRI = 58, 74
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
-PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_trace_indoor_1080p.md")
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_trace_{config}_1080p.md")
 KERNEL_SOURCES = ("paper_2310_07182_amd/csrc/kernels.hip", "paper_2310_07182_amd/csrc/kernels.h",
                   "paper_2310_07182_amd/build.py")
 
@@ -49,13 +49,14 @@ def measured_traffic(mode, config):
     """Bytes per secondary traversal launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary, or None when it covers another workload or the kernel sources changed since."""
     import hashlib
-    if config != "indoor" or not os.path.exists(PROFILE_SUMMARY):
+    path = PROFILE_SUMMARY.format(config=config)
+    if not os.path.exists(path):
         return None
     digest = hashlib.sha256()
     for p in KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             digest.update(f.read())
-    with open(PROFILE_SUMMARY) as f:
+    with open(path) as f:
         for line in f:
             if line.startswith("traffic_bytes_per_launch "):
                 fields = dict(kv.split("=", 1) for kv in line.split()[1:])
