@@ -9,9 +9,10 @@ Headline (value): secondary Mrays/s in reuse mode = rays traced at bounces
 library's stream), the definition of the paper's Table 1.  The same figure for
 the incoherent and sorted modes, end-to-end rates and p50/p99 frame latency
 are reported beside it.  The roofline object describes the traversal kernel:
-algorithmic bytes per launch (nodes visited x 64 B + triangles tested x 48 B +
-32 B ray + 8 B hit, per ray, counted by the counting variant of the kernel in an
-untimed frame) divided by its average launch time.
+algorithmic operations and bytes per launch (nodes visited x 128 B for the
+four-wide nodes, 64 B for child-pair nodes, + triangles tested x 48 B + 32 B ray
++ 8 B hit, per ray, counted by the counting variant of the kernel in an untimed
+frame) divided by its average launch time.
 """
 from __future__ import annotations
 
@@ -35,6 +36,9 @@ NODE_BYTES, TRI_BYTES, RAY_BYTES, HIT_BYTES = 64, 48, 32, 8
 # edge functions, 6 sign tests, 2 add, 3 mul + 2 add for T, the division (~10),
 # 3 compares and 18 component selects.
 OPS_PER_NODE, OPS_PER_TRI = 58, 74
+# a four-wide node visit: four slab tests (4 x 26), the five compare-exchanges of the sorting
+# network on (distance, code) (5 x 5) and ~8 for the pushes and the choice of the next node
+OPS_PER_NODE4, NODE4_BYTES = 137, 128
 # MI355X vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit op per lane and cycle
 # (no packed FP32, an FMA counted once) = 39.3 T ops/s.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -72,6 +76,8 @@ def log(*a):
 
 def bench_mode(api, sc, cfg, mode, steps, warmup, seed0, nee=False):
     import torch
+    wide = bool(sc.info()["wide"])
+    node_bytes, ops_node = (NODE4_BYTES, OPS_PER_NODE4) if wide else (NODE_BYTES, OPS_PER_NODE)
     rc = api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], mode, tuple(cfg["tile"]), cfg["k"], nee=nee)
     # untimed counting frame: nodes / triangles per ray and rays per bounce
     rs = api.Renderer(sc, rc, stats=True)
@@ -112,11 +118,11 @@ def bench_mode(api, sc, cfg, mode, steps, warmup, seed0, nee=False):
     # algorithmic bytes of the traversal kernel (secondary bounces)
     nodes_per_ray = stats[1:, 0].sum() / max(rays_stats[1:].sum(), 1)
     tris_per_ray = stats[1:, 1].sum() / max(rays_stats[1:].sum(), 1)
-    bytes_per_ray = nodes_per_ray * NODE_BYTES + tris_per_ray * TRI_BYTES + RAY_BYTES + HIT_BYTES
+    bytes_per_ray = nodes_per_ray * node_bytes + tris_per_ray * TRI_BYTES + RAY_BYTES + HIT_BYTES
     launches = int(sec.sum())
     avg_launch_ms = ms[sec].mean()
     bytes_per_launch = bytes_per_ray * sec_rays / B
-    ops_per_ray = nodes_per_ray * OPS_PER_NODE + tris_per_ray * OPS_PER_TRI
+    ops_per_ray = nodes_per_ray * ops_node + tris_per_ray * OPS_PER_TRI
     ops_per_launch = ops_per_ray * sec_rays / B
     kinds = {int(k): float(ms[kind == k].sum() / steps) for k in np.unique(kind)}
     shadow = {}

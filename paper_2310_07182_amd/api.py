@@ -84,7 +84,8 @@ class Scene:
         i = capi.SceneInfo()
         check(lib().pt_scene_get_info(self.handle, C.byref(i)))
         return dict(ntri=i.ntri, nnodes=i.nnodes, max_depth=i.max_depth, max_leaf=i.max_leaf,
-                    lo=list(i.lo), hi=list(i.hi), sah_cost=i.sah_cost, device_bytes=i.device_bytes, nemit=i.nemit)
+                    lo=list(i.lo), hi=list(i.hi), sah_cost=i.sah_cost, device_bytes=i.device_bytes, nemit=i.nemit,
+                    nnodes4=i.nnodes4, max_depth4=i.max_depth4, wide=i.wide)
 
     def export_bvh(self):
         inf = self.info()

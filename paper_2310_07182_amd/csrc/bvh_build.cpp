@@ -204,6 +204,7 @@ bool build_bvh(const float* tris, uint32_t ntri, HostBvh& out, std::string& err)
     empty_root.c[2] = empty_root.c[3] = 0;
     if (ntri == 0) {
         out.nodes.push_back(empty_root);
+        collapse_bvh4(out.nodes, out.nodes4, out.max_depth4);
         return true;
     }
     Builder b;
@@ -284,7 +285,93 @@ bool build_bvh(const float* tris, uint32_t ntri, HostBvh& out, std::string& err)
         out.sah_cost = cost;
     }
     out.order = std::move(b.idx);
+    try {
+        collapse_bvh4(out.nodes, out.nodes4, out.max_depth4);
+    } catch (...) {
+        err = "host allocation failed";
+        return false;
+    }
     return true;
+}
+
+}  // namespace pt
+
+namespace pt {
+
+void collapse_bvh4(const std::vector<BvhNode>& n2, std::vector<Bvh4Node>& n4, uint32_t& max_depth4) {
+    struct Entry {
+        float lo[3], hi[3];
+        int32_t code;
+    };
+    auto half_area = [](const Entry& e) {
+        const double dx = (double)e.hi[0] - e.lo[0], dy = (double)e.hi[1] - e.lo[1], dz = (double)e.hi[2] - e.lo[2];
+        return dx * dy + dy * dz + dz * dx;
+    };
+    auto children = [&](int32_t k, Entry out[2]) {
+        const BvhNode& b = n2[(size_t)k];
+        out[0] = Entry{{b.f[0], b.f[2], b.f[8]}, {b.f[1], b.f[3], b.f[9]}, b.c[0]};
+        out[1] = Entry{{b.f[4], b.f[6], b.f[10]}, {b.f[5], b.f[7], b.f[11]}, b.c[1]};
+    };
+    n4.clear();
+    max_depth4 = 0;
+    if (n2.empty()) return;
+    struct Item {
+        int32_t k2;       // child-pair node to collapse
+        uint32_t slot;    // four-wide node it becomes
+        uint32_t depth;
+    };
+    n4.emplace_back();
+    std::vector<Item> stack{{0, 0, 1}};
+    while (!stack.empty()) {
+        const Item it = stack.back();
+        stack.pop_back();
+        max_depth4 = std::max(max_depth4, it.depth);
+        Entry e[4];
+        int ne = 0;
+        Entry two[2];
+        children(it.k2, two);
+        for (const Entry& x : two)
+            if (x.code != kEmpty) e[ne++] = x;
+        while (ne < 4) {
+            int best = -1;
+            double area = -1.0;
+            for (int j = 0; j < ne; ++j)
+                if (e[j].code >= 0 && half_area(e[j]) > area) {
+                    area = half_area(e[j]);
+                    best = j;
+                }
+            if (best < 0) break;
+            Entry sub[2];
+            children(e[best].code, sub);
+            e[best] = e[--ne];
+            for (const Entry& x : sub)
+                if (x.code != kEmpty) e[ne++] = x;
+        }
+        Bvh4Node nd;
+        for (int j = 0; j < 4; ++j) {
+            nd.pad[j] = 0;
+            if (j < ne) {
+                nd.lx[j] = e[j].lo[0]; nd.hx[j] = e[j].hi[0];
+                nd.ly[j] = e[j].lo[1]; nd.hy[j] = e[j].hi[1];
+                nd.lz[j] = e[j].lo[2]; nd.hz[j] = e[j].hi[2];
+                nd.c[j] = e[j].code;
+            } else {
+                nd.lx[j] = nd.ly[j] = nd.lz[j] = INFINITY;
+                nd.hx[j] = nd.hy[j] = nd.hz[j] = -INFINITY;
+                nd.c[j] = kEmpty;
+            }
+        }
+        // inner children get the next slots, visited child 0 first
+        for (int j = 0; j < ne; ++j)
+            if (e[j].code >= 0) {
+                const uint32_t slot = (uint32_t)n4.size();
+                n4.emplace_back();
+                nd.c[j] = (int32_t)slot;
+            }
+        for (int j = ne - 1; j >= 0; --j)
+            if (e[j].code >= 0) stack.push_back(Item{e[j].code, (uint32_t)nd.c[j], it.depth + 1});
+        n4[it.slot] = nd;
+    }
 }
 
 }  // namespace pt

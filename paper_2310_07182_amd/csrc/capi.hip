@@ -28,7 +28,8 @@ struct pt_scene_s {
     uint32_t ntri = 0, nmat = 0;
     float env[3] = {0, 0, 0};
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    size_t off_nodes = 0, off_btris = 0, off_otris = 0, off_mat = 0, off_mats = 0, off_emit = 0, bytes = 0;
+    size_t off_nodes = 0, off_nodes4 = 0, off_btris = 0, off_otris = 0, off_mat = 0, off_mats = 0, off_emit = 0,
+           bytes = 0;
     bool uploaded = false;
     int device = -1;
     DevScene dev{};
@@ -380,6 +381,8 @@ pt_status pt_scene_create(const pt_scene_desc* d, pt_scene* out) {
         size_t o = 0;
         s->off_nodes = o;
         o = align256(o + s->bvh.nodes.size() * sizeof(pt::BvhNode));
+        s->off_nodes4 = o;
+        o = align256(o + s->bvh.nodes4.size() * sizeof(pt::Bvh4Node));
         s->off_btris = o;
         o = align256(o + s->btris.size() * sizeof(float4));
         s->off_otris = o;
@@ -413,6 +416,7 @@ pt_status pt_scene_upload(pt_scene s, void* arena, size_t bytes, void* stream) {
         size_t n;
     } parts[] = {
         {s->off_nodes, s->bvh.nodes.data(), s->bvh.nodes.size() * sizeof(pt::BvhNode)},
+        {s->off_nodes4, s->bvh.nodes4.data(), s->bvh.nodes4.size() * sizeof(pt::Bvh4Node)},
         {s->off_btris, s->btris.data(), s->btris.size() * sizeof(float4)},
         {s->off_otris, s->otris.data(), s->otris.size() * sizeof(float4)},
         {s->off_mat, s->tri_mat.data(), s->tri_mat.size() * 4},
@@ -432,6 +436,9 @@ pt_status pt_scene_upload(pt_scene s, void* arena, size_t bytes, void* stream) {
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     DevScene& d = s->dev;
     d.nodes = (const float4*)(base + s->off_nodes);
+    d.nodes4 = (const float4*)(base + s->off_nodes4);
+    // four-wide traversal pushes up to three siblings per level: use it when the stack bound holds
+    d.wide = (pt::kPreferWide && 3u * s->bvh.max_depth4 + 4u <= (uint32_t)(pt::kStackLds + pt::kStackOvf)) ? 1u : 0u;
     d.btris = (const float4*)(base + s->off_btris);
     d.otris = (const float4*)(base + s->off_otris);
     d.tri_mat = (const uint32_t*)(base + s->off_mat);
@@ -463,6 +470,9 @@ pt_status pt_scene_get_info(pt_scene s, pt_scene_info* info) {
     info->sah_cost = s->bvh.sah_cost;
     info->device_bytes = s->bytes;
     info->nemit = (uint32_t)s->emit.size();
+    info->nnodes4 = (uint32_t)s->bvh.nodes4.size();
+    info->max_depth4 = s->bvh.max_depth4;
+    info->wide = (pt::kPreferWide && 3u * s->bvh.max_depth4 + 4u <= (uint32_t)(pt::kStackLds + pt::kStackOvf)) ? 1u : 0u;
     return PT_OK;
 }
 
@@ -470,6 +480,12 @@ pt_status pt_scene_export_bvh(pt_scene s, void* nodes, uint32_t* order) {
     if (!s) return fail(PT_EINVAL, "null scene");
     if (nodes) memcpy(nodes, s->bvh.nodes.data(), s->bvh.nodes.size() * sizeof(pt::BvhNode));
     if (order && !s->bvh.order.empty()) memcpy(order, s->bvh.order.data(), s->bvh.order.size() * sizeof(uint32_t));
+    return PT_OK;
+}
+
+pt_status pt_scene_export_bvh4(pt_scene s, void* nodes4) {
+    if (!s || !nodes4) return fail(PT_EINVAL, "null argument");
+    if (!s->bvh.nodes4.empty()) memcpy(nodes4, s->bvh.nodes4.data(), s->bvh.nodes4.size() * sizeof(pt::Bvh4Node));
     return PT_OK;
 }
 
@@ -956,9 +972,12 @@ static hipError_t batch_launch_step(pt_batch bt, const pt::StepJob* dtab, int nj
     ta.refill = bt->group.refill ? bt->group.refill : kDefaultRefill;
     ta.waves_per_cu = bt->group.waves_per_cu;
     ta.leaf_gate = (bt->group.leaf_gate ? bt->group.leaf_gate : pt::kDefaultLeafGate) - 1;
+    bool wide = true;
+    for (auto& J : bt->jobs)
+        if (J.used) wide = wide && J.job.scene->dev.wide != 0;
     {
         TimerScope tsc(timer, st, 0, -1);
-        e = pt::launch_trace_multi(dtab, njobs, ta, st);
+        e = pt::launch_trace_multi(dtab, njobs, ta, wide, st);
     }
     if (e != hipSuccess) return e;
     TimerScope tsc(timer, st, 2, -1);

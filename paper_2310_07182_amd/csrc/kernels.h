@@ -12,6 +12,8 @@ namespace pt {
 // Scene as the kernels see it (device pointers into the caller's arena).
 struct DevScene {
     const float4* nodes;     // [nnodes][4]  child-pair nodes
+    const float4* nodes4;    // [nnodes4][8] four-wide nodes of the same tree
+    uint32_t wide;           // traverse the four-wide nodes
     const float4* btris;     // [ntri][3]    BVH order; v0.w = original triangle id (int bits)
     const float4* otris;     // [ntri][3]    original order
     const uint32_t* tri_mat; // [ntri]
@@ -41,6 +43,7 @@ constexpr uint32_t kNoRay = 0xFFFFFFFFu;
 constexpr float kShadowTmax = 1.0f - 0x1p-10f;
 constexpr int kTraceBlock = 64;    // one wave per workgroup
 constexpr int kStackLds = 16;      // LDS stack entries per lane
+constexpr bool kPreferWide = true; // traverse the four-wide nodes when the scene allows it
 constexpr int kStackOvf = kMaxDepth - kStackLds + 16; // global overflow entries per lane
 constexpr int kMaxTraceBlocks = 256 * 32;  // cap of the persistent grid (bounds the overflow area)
 constexpr int kDefaultWavesPerCu = 24;     // persistent grid when the caller leaves it to the library
@@ -91,7 +94,8 @@ int trace_grid_blocks(int waves_per_cu = 0);   // persistent grid (workgroups): 
 hipError_t launch_trace(const DevScene& sc, const TraceArgs& a, bool stats, hipStream_t st);
 // merged launches over njobs jobs (table in device memory); total_rays = sum of nrays,
 // total_blocks = sum of the jobs' workgroups; all jobs share f.TS and the grouping mode
-hipError_t launch_trace_multi(const StepJob* jobs, int njobs, const TraceArgs& a, hipStream_t st);
+// wide: every job's scene has four-wide nodes within the stack bound
+hipError_t launch_trace_multi(const StepJob* jobs, int njobs, const TraceArgs& a, bool wide, hipStream_t st);
 hipError_t launch_raygen_multi(const StepJob* jobs, int njobs, uint32_t total_blocks, int TS, hipStream_t st);
 hipError_t launch_shade_multi(const StepJob* jobs, int njobs, uint32_t total_blocks, int TS, bool reuse,
                               hipStream_t st);

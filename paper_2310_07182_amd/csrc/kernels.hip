@@ -265,7 +265,17 @@ static_assert(kMaxLeaf >= 1 && kMaxLeaf <= 8, "leaf codes hold counts 1..8");
 static_assert(kTraceBlock == 64, "the pair list stores a lane in 6 bits");
 using PairT = std::conditional_t<(kMaxLeaf <= 4), uint8_t, uint16_t>;   // lane + triangle-in-leaf
 
-template <bool STATS, bool MULTI>
+__device__ __forceinline__ void cswap(float& ta, int32_t& ka, float& tb, int32_t& kb) {
+    const bool sw = tb < ta;
+    const float t = sw ? tb : ta;
+    const int32_t k = sw ? kb : ka;
+    tb = sw ? ta : tb;
+    kb = sw ? ka : kb;
+    ta = t;
+    ka = k;
+}
+
+template <bool STATS, bool MULTI, bool WIDE>
 __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a, uint32_t gthreads,
                                                        const StepJob* jobs, int njobs) {
     __shared__ int32_t stk[kStackLds][kTraceBlock];
@@ -286,6 +296,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
     int sp = 0, novf = 0;
     // scene and output of the lane's ray: kernel arguments for one job, per lane for a merged launch
     const float4* nodes = sc.nodes;
+    const float4* nodes4 = sc.nodes4;
     const float4* btris = sc.btris;
     int32_t* oprim = a.out_prim;
     float* ot = a.out_t;
@@ -313,6 +324,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
                         li = i - J.ray_start;
                         rays = J.q_in;
                         nodes = J.sc.nodes;
+                        nodes4 = J.sc.nodes4;
                         btris = J.sc.btris;
                         oprim = J.trace_prim;
                         ot = J.trace_t;
@@ -347,43 +359,96 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
         // ---- inner nodes; a leaf that is reached is postponed while the slot is free
         for (;;) {
             if (have && node >= 0) {
-                const float4* nd = nodes + 4 * (size_t)node;
-                const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
-                if (STATS) ++nv;
-                const int32_t c0 = __float_as_int(n3.x), c1 = __float_as_int(n3.y);
-                bool h0, h1;
-                const float t0 = slab(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, o, inv, tcull, h0);
-                const float t1 = slab(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, o, inv, tcull, h1);
-                h0 = h0 && c0 != kEmpty;
-                h1 = h1 && c1 != kEmpty;
-                if (h0 && h1) {
-                    const bool swp = t1 < t0;
-                    const int32_t far = swp ? c0 : c1;
-                    node = swp ? c1 : c0;
-                    if (sp == kStackLds) {
-                        // the BVH depth bound keeps the stack within kStackLds + kStackOvf
-                        // entries; the check keeps every access in bounds regardless
-                        if (novf + kStackLds / 2 > kStackOvf) {
-                            node = kDone;   // give the ray up (the pop below finds the stack empty)
-                            leaf = kNoLeaf;
-                            sp = 0;
-                            novf = 0;
-                        } else {
-                            // spill the lower half of the LDS stack to this lane's overflow column
-                            for (int e = 0; e < kStackLds / 2; ++e)
-                                a.ovf[(size_t)(novf + e) * gthreads + gtid] = stk[e][lane];
-                            for (int e = 0; e < kStackLds / 2; ++e) stk[e][lane] = stk[e + kStackLds / 2][lane];
-                            novf += kStackLds / 2;
-                            sp = kStackLds / 2;
+                if constexpr (WIDE) {
+                    // four children: nearest hit next, the other hits pushed far to near
+                    const float4* nd = nodes4 + 8 * (size_t)node;
+                    const float4 lx = nd[0], hx = nd[1], ly = nd[2], hy = nd[3], lz = nd[4], hz = nd[5], cc = nd[6];
+                    if (STATS) ++nv;
+                    bool h0, h1, h2, h3;
+                    float a0 = slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, o, inv, tcull, h0);
+                    float a1 = slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, o, inv, tcull, h1);
+                    float a2 = slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, o, inv, tcull, h2);
+                    float a3 = slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, o, inv, tcull, h3);
+                    int32_t k0 = __float_as_int(cc.x), k1 = __float_as_int(cc.y), k2 = __float_as_int(cc.z),
+                            k3 = __float_as_int(cc.w);
+                    h0 = h0 && k0 != kEmpty;
+                    h1 = h1 && k1 != kEmpty;
+                    h2 = h2 && k2 != kEmpty;
+                    h3 = h3 && k3 != kEmpty;
+                    const int nh = (int)h0 + (int)h1 + (int)h2 + (int)h3;
+                    a0 = h0 ? a0 : INFINITY;
+                    a1 = h1 ? a1 : INFINITY;
+                    a2 = h2 ? a2 : INFINITY;
+                    a3 = h3 ? a3 : INFINITY;
+                    // sorting network on (distance, code): misses (+inf) end up last
+                    cswap(a0, k0, a1, k1);
+                    cswap(a2, k2, a3, k3);
+                    cswap(a0, k0, a2, k2);
+                    cswap(a1, k1, a3, k3);
+                    cswap(a1, k1, a2, k2);
+                    if (nh == 0) {
+                        node = kDone;   // pop below
+                    } else {
+                        node = k0;
+                        if (sp + nh - 1 > kStackLds) {
+                            if (novf + kStackLds / 2 > kStackOvf) {
+                                node = kDone;   // unreachable within the depth bound of wide trees
+                                leaf = kNoLeaf;
+                                sp = 0;
+                                novf = 0;
+                            } else {
+                                for (int e = 0; e < kStackLds / 2; ++e)
+                                    a.ovf[(size_t)(novf + e) * gthreads + gtid] = stk[e][lane];
+                                for (int e = 0; e < kStackLds / 2; ++e) stk[e][lane] = stk[e + kStackLds / 2][lane];
+                                novf += kStackLds / 2;
+                                sp -= kStackLds / 2;
+                            }
+                        }
+                        if (node != kDone) {
+                            if (nh == 4) stk[sp++][lane] = k3;
+                            if (nh >= 3) stk[sp++][lane] = k2;
+                            if (nh >= 2) stk[sp++][lane] = k1;
                         }
                     }
-                    if (node != kDone) stk[sp++][lane] = far;
-                } else if (h0) {
-                    node = c0;
-                } else if (h1) {
-                    node = c1;
                 } else {
-                    node = kDone;   // pop below
+                    const float4* nd = nodes + 4 * (size_t)node;
+                    const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
+                    if (STATS) ++nv;
+                    const int32_t c0 = __float_as_int(n3.x), c1 = __float_as_int(n3.y);
+                    bool h0, h1;
+                    const float t0 = slab(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, o, inv, tcull, h0);
+                    const float t1 = slab(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, o, inv, tcull, h1);
+                    h0 = h0 && c0 != kEmpty;
+                    h1 = h1 && c1 != kEmpty;
+                    if (h0 && h1) {
+                        const bool swp = t1 < t0;
+                        const int32_t far = swp ? c0 : c1;
+                        node = swp ? c1 : c0;
+                        if (sp == kStackLds) {
+                            // the BVH depth bound keeps the stack within kStackLds + kStackOvf
+                            // entries; the check keeps every access in bounds regardless
+                            if (novf + kStackLds / 2 > kStackOvf) {
+                                node = kDone;   // give the ray up (the pop below finds the stack empty)
+                                leaf = kNoLeaf;
+                                sp = 0;
+                                novf = 0;
+                            } else {
+                                // spill the lower half of the LDS stack to this lane's overflow column
+                                for (int e = 0; e < kStackLds / 2; ++e)
+                                    a.ovf[(size_t)(novf + e) * gthreads + gtid] = stk[e][lane];
+                                for (int e = 0; e < kStackLds / 2; ++e) stk[e][lane] = stk[e + kStackLds / 2][lane];
+                                novf += kStackLds / 2;
+                                sp = kStackLds / 2;
+                            }
+                        }
+                        if (node != kDone) stk[sp++][lane] = far;
+                    } else if (h0) {
+                        node = c0;
+                    } else if (h1) {
+                        node = c1;
+                    } else {
+                        node = kDone;   // pop below
+                    }
                 }
                 if (node == kDone || (node < 0 && leaf == kNoLeaf)) {
                     if (node != kDone) leaf = node;
@@ -1088,7 +1153,7 @@ int trace_grid_blocks(int waves_per_cu) {
     if (g_trace_blocks[dev] == 0) {
         int cus = 0, per = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace<false, false>, kTraceBlock, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trace<false, false, false>, kTraceBlock, 0) != hipSuccess ||
             per <= 0)
             per = 8;
         int g = cus * per;
@@ -1109,19 +1174,28 @@ hipError_t launch_trace(const DevScene& sc, const TraceArgs& a, bool stats, hipS
     const uint32_t gthreads = (uint32_t)g * kTraceBlock;
     if (a.refill < 1 || a.refill > 64) return hipErrorInvalidValue;
     const StepJob* none = nullptr;
-    if (stats)
-        hipLaunchKernelGGL((k_trace<true, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+    const bool wide = kPreferWide && sc.wide;
+    if (stats && wide)
+        hipLaunchKernelGGL((k_trace<true, false, true>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+    else if (stats)
+        hipLaunchKernelGGL((k_trace<true, false, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+    else if (wide)
+        hipLaunchKernelGGL((k_trace<false, false, true>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
     else
-        hipLaunchKernelGGL((k_trace<false, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+        hipLaunchKernelGGL((k_trace<false, false, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
     return hipGetLastError();
 }
 
-hipError_t launch_trace_multi(const StepJob* jobs, int njobs, const TraceArgs& a, hipStream_t st) {
+hipError_t launch_trace_multi(const StepJob* jobs, int njobs, const TraceArgs& a, bool wide, hipStream_t st) {
     const int g = trace_grid_blocks(a.waves_per_cu);
     const uint32_t gthreads = (uint32_t)g * kTraceBlock;
     if (a.refill < 1 || a.refill > 64 || njobs < 1) return hipErrorInvalidValue;
     DevScene none{};
-    hipLaunchKernelGGL((k_trace<false, true>), dim3(g), dim3(kTraceBlock), 0, st, none, a, gthreads, jobs, njobs);
+    if (kPreferWide && wide)
+        hipLaunchKernelGGL((k_trace<false, true, true>), dim3(g), dim3(kTraceBlock), 0, st, none, a, gthreads, jobs, njobs);
+    else
+        hipLaunchKernelGGL((k_trace<false, true, false>), dim3(g), dim3(kTraceBlock), 0, st, none, a, gthreads, jobs,
+                           njobs);
     return hipGetLastError();
 }
 

@@ -28,13 +28,29 @@ struct BvhNode {
 };
 static_assert(sizeof(BvhNode) == 64, "node size");
 
+// Four-wide node, 128 bytes: the boxes of up to four children (structure of arrays) and
+// their codes (same code convention; kEmpty for an unused slot).
+struct Bvh4Node {
+    float lx[4], hx[4], ly[4], hy[4], lz[4], hz[4];
+    int32_t c[4];
+    int32_t pad[4];
+};
+static_assert(sizeof(Bvh4Node) == 128, "node size");
+
 struct HostBvh {
     std::vector<BvhNode> nodes;
+    std::vector<Bvh4Node> nodes4;  // the same tree collapsed to four children per node
     std::vector<uint32_t> order;   // BVH slot -> original triangle id
     uint32_t max_depth = 0;
     uint32_t max_leaf = 0;
     double sah_cost = 0.0;
+    uint32_t max_depth4 = 0;       // inner-node depth of the four-wide tree
 };
+
+// Collapses the child-pair tree into four-wide nodes: a node's children are expanded,
+// largest surface area first, into their own children until there are four or only
+// leaves are left.  Leaf codes (triangle ranges) are unchanged.
+void collapse_bvh4(const std::vector<BvhNode>& n2, std::vector<Bvh4Node>& n4, uint32_t& max_depth4);
 
 // Binned-SAH build over the triangles (host, multi-threaded, deterministic output).
 bool build_bvh(const float* tris, uint32_t ntri, HostBvh& out, std::string& err);

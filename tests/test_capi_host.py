@@ -22,7 +22,7 @@ def L():
 
 def test_exports_every_declared_symbol(L):
     hdr = open(os.path.join(ROOT, "include", "pt.h")).read()
-    decl = set(re.findall(r"^(?:pt_status|size_t|const char\*)\s+(pt_[a-z_]+)\s*\(", hdr, re.M))
+    decl = set(re.findall(r"^(?:pt_status|size_t|const char\*)\s+(pt_[a-z0-9_]+)\s*\(", hdr, re.M))
     assert len(decl) >= 18
     for name in sorted(decl):
         assert hasattr(L, name), name
@@ -232,3 +232,85 @@ def test_scene_counts_emitters(L):
     em = s["mats"]["emission"].max(axis=1) > 0
     assert info.nemit == int(em[s["tri_mat"]].sum()) > 0
     L.pt_scene_free(h)
+
+
+def _bvh4(L, h):
+    info = capi.SceneInfo()
+    assert L.pt_scene_get_info(h, C.byref(info)) == 0
+    raw = np.zeros((max(info.nnodes4, 1), 32), np.float32)
+    assert L.pt_scene_export_bvh4(h, raw.ctypes.data) == 0
+    return info, raw[: info.nnodes4]
+
+
+@pytest.mark.parametrize("fn", [scenes.tiny, scenes.furnace, scenes.mixed_small, scenes.mid])
+def test_bvh4_valid(L, fn):
+    """The four-wide tree: every inner node is reached once, every child box holds its
+    subtree, and the leaves cover every triangle exactly once."""
+    s = fn()
+    st, h, keep = _create(L, s)
+    assert st == 0
+    info, raw = _bvh4(L, h)
+    nodes2, order = (lambda i: (i, None))(None)
+    order = np.zeros(len(s["tris"]), np.uint32)
+    info2 = capi.SceneInfo()
+    L.pt_scene_get_info(h, C.byref(info2))
+    n2 = np.zeros((info2.nnodes, 16), np.float32)
+    L.pt_scene_export_bvh(h, n2.ctypes.data, order.ctypes.data)
+    tris = np.asarray(s["tris"], np.float32).reshape(-1, 3, 3)
+    boxes = raw[:, :24].reshape(-1, 6, 4)          # lx hx ly hy lz hz, x 4 children
+    codes = raw[:, 24:28].view(np.int32)
+    EMPTY = np.iinfo(np.int32).min
+    seen_tri = np.zeros(len(tris), np.int32)
+    seen_node = np.zeros(len(raw), np.int32)
+    stack = [(0, 1)]
+    max_depth = 0
+    while stack:
+        ni, depth = stack.pop()
+        seen_node[ni] += 1
+        max_depth = max(max_depth, depth)
+        nchild = 0
+        for c in range(4):
+            code = int(codes[ni, c])
+            if code == EMPTY:
+                continue
+            nchild += 1
+            lo = np.array([boxes[ni, 0, c], boxes[ni, 2, c], boxes[ni, 4, c]])
+            hi = np.array([boxes[ni, 1, c], boxes[ni, 3, c], boxes[ni, 5, c]])
+            if code >= 0:
+                assert 0 < code < len(raw)
+                for cc in range(4):
+                    if int(codes[code, cc]) == EMPTY:
+                        continue
+                    glo = np.array([boxes[code, 0, cc], boxes[code, 2, cc], boxes[code, 4, cc]])
+                    ghi = np.array([boxes[code, 1, cc], boxes[code, 3, cc], boxes[code, 5, cc]])
+                    assert (glo >= lo).all() and (ghi <= hi).all()
+                stack.append((code, depth + 1))
+            else:
+                v = ~code & 0xFFFFFFFF
+                first, cnt = v >> 3, (v & 7) + 1
+                assert cnt <= 4 and first + cnt <= len(tris)
+                for j in range(first, first + cnt):
+                    tv = tris[order[j]]
+                    assert (tv.min(0) >= lo).all() and (tv.max(0) <= hi).all()
+                    seen_tri[order[j]] += 1
+        assert nchild >= (1 if ni == 0 else 2)
+    assert (seen_tri == 1).all()
+    assert (seen_node == 1).all()
+    assert max_depth == info.max_depth4
+    assert info.nnodes4 < info2.nnodes
+    assert info.wide == (1 if 3 * info.max_depth4 + 4 <= 80 else 0)
+    L.pt_scene_free(h)
+
+
+def test_bvh4_empty_and_single_leaf(L):
+    s = scenes.tiny()
+    one = dict(s)
+    one["tris"] = np.asarray(s["tris"])[:3]
+    one["tri_mat"] = np.asarray(s["tri_mat"])[:3]
+    for sc in (one,):
+        st, h, keep = _create(L, scenes.Scene(sc))
+        assert st == 0
+        info, raw = _bvh4(L, h)
+        codes = raw[:, 24:28].view(np.int32)
+        assert info.nnodes4 == 1 and codes[0, 0] < 0 and (codes[0, 1:] == np.iinfo(np.int32).min).all()
+        L.pt_scene_free(h)
