@@ -102,10 +102,11 @@ class OracleScene:
                                         len(self._mats), _p(self._env))
         if not self.h:
             raise MemoryError("oracle scene allocation failed")
+        self._free = lib().orc_scene_free   # held here: module globals may be gone at interpreter exit
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().orc_scene_free(self.h)
+        if getattr(self, "h", None) and getattr(self, "_free", None):
+            self._free(self.h)
             self.h = None
 
     def bounds(self):

@@ -130,6 +130,7 @@ pt_status check_group(pt_group g, int bounces) {
     if (g.refill > 64) return fail(PT_EINVAL, "refill must be in [0, 64] (got %d)", g.refill);
     if (g.leaf_gate > 64) return fail(PT_EINVAL, "leaf_gate must be in [0, 64] (got %d)", g.leaf_gate);
     if (g.nee > 1) return fail(PT_EINVAL, "nee must be 0 or 1 (got %d)", g.nee);
+    if (g.traversal > 3) return fail(PT_EINVAL, "traversal must be in [0, 3] (got %d)", g.traversal);
     return PT_OK;
 }
 
@@ -210,7 +211,7 @@ Layout layout(const Frame& f) {
     L.state = o;
     o = align256(o + qb);
     L.work = o;
-    o = align256(o + launches * 4);
+    o = align256(o + launches * pt::kWorkWords * 4);
     L.partial = o;
     o = align256(o + launches * pt::kMaxTraceBlocks * 4);
     if (is_sorted_mode(f.mode)) {
@@ -233,7 +234,7 @@ Layout layout(const Frame& f) {
         L.st = o;
         o = align256(o + (size_t)f.nslots * 4);
         L.swork = o;
-        o = align256(o + launches * 4);
+        o = align256(o + launches * pt::kWorkWords * 4);
         L.spartial = o;
         o = align256(o + launches * pt::kMaxTraceBlocks * 4);
     }
@@ -519,6 +520,10 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
     hipError_t ge = hipGetDevice(&dev);
     if (ge != hipSuccess) return hip_fail(ge, "hipGetDevice");
     if (dev != scene->device) return fail(PT_EINVAL, "scene was uploaded on device %d, current device is %d", scene->device, dev);
+    const int kind = (int)g.traversal - 1;   // -1: the scene's own choice
+    if (kind > pt::trace_kind(scene->dev))
+        return fail(PT_EINVAL, "traversal %d is not available for this scene (at most %d)", g.traversal,
+                    pt::trace_kind(scene->dev) + 1);
 
     Frame f = make_frame(w, h, spp, B, mode, g, seed);
     if (is_sorted_mode(mode) && f.nslots > (1u << 27))
@@ -537,9 +542,9 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
     hipError_t e;
     {
         TimerScope ts(out->timer, st, 6, -1);
-        e = pt::launch_zero(work, launches, st);
+        e = pt::launch_zero(work, launches * pt::kWorkWords, st);
         if (e == hipSuccess && out->stats) e = pt::launch_zero((uint32_t*)out->stats, (size_t)(B + 1) * 4, st);
-        if (e == hipSuccess && f.nee) e = pt::launch_zero((uint32_t*)(ws + L.swork), launches, st);
+        if (e == hipSuccess && f.nee) e = pt::launch_zero((uint32_t*)(ws + L.swork), launches * pt::kWorkWords, st);
         if (e == hipSuccess && out->shadow_count) e = pt::launch_zero(out->shadow_count, launches, st);
     }
     if (e != hipSuccess) return hip_fail(e, "launch (zero)");
@@ -579,7 +584,7 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
             pt::TraceArgs ta{};
             ta.rays = tq;
             ta.n = n;
-            ta.work = work + li;
+            ta.work = work + li * pt::kWorkWords;
             ta.out_prim = out->hit_prim + li * plane;
             ta.out_t = out->hit_t + li * plane;
             ta.partial = out->ray_count ? partial + li * pt::kMaxTraceBlocks : nullptr;
@@ -589,6 +594,7 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
             ta.refill = g.refill ? g.refill : kDefaultRefill;
             ta.waves_per_cu = g.waves_per_cu;
             ta.leaf_gate = (g.leaf_gate ? g.leaf_gate : pt::kDefaultLeafGate) - 1;
+            ta.kind = kind;
             {
                 TimerScope ts(out->timer, st, 0, b);
                 e = pt::launch_trace(scene->dev, ta, out->stats != nullptr, st);
@@ -608,7 +614,7 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
                 pt::TraceArgs sa{};
                 sa.rays = shray;
                 sa.n = n;
-                sa.work = (uint32_t*)(ws + L.swork) + li;
+                sa.work = (uint32_t*)(ws + L.swork) + li * pt::kWorkWords;
                 sa.out_prim = sprim;
                 sa.out_t = (float*)(ws + L.st);
                 sa.partial = out->shadow_count ? (uint32_t*)(ws + L.spartial) + li * pt::kMaxTraceBlocks : nullptr;
@@ -619,6 +625,7 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
                 sa.refill = g.refill ? g.refill : kDefaultRefill;
                 sa.waves_per_cu = g.waves_per_cu;
                 sa.leaf_gate = (g.leaf_gate ? g.leaf_gate : pt::kDefaultLeafGate) - 1;
+                sa.kind = kind;
                 {
                     TimerScope ts(out->timer, st, 7, b);
                     e = pt::launch_trace(scene->dev, sa, false, st);
@@ -648,7 +655,7 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
 }
 
 size_t pt_trace_workspace_bytes(void) {
-    return 256 + align256((size_t)pt::kMaxTraceBlocks * pt::kTraceBlock * pt::kStackOvf * 4);
+    return align256((size_t)pt::kWorkWords * 4) + align256((size_t)pt::kMaxTraceBlocks * pt::kTraceBlock * pt::kStackOvf * 4);
 }
 
 pt_status pt_trace(pt_scene scene, const float* rays, uint32_t n, int refill, int32_t* prim, float* t,
@@ -665,11 +672,12 @@ pt_status pt_trace(pt_scene scene, const float* rays, uint32_t n, int refill, in
     ta.work = (uint32_t*)workspace;
     ta.out_prim = prim;
     ta.out_t = t;
-    ta.ovf = (int32_t*)((char*)workspace + 256);
+    ta.ovf = (int32_t*)((char*)workspace + align256((size_t)pt::kWorkWords * 4));
     ta.by_pixel = 0;
     ta.refill = refill ? refill : kDefaultRefill;
     ta.leaf_gate = pt::kDefaultLeafGate - 1;
-    hipError_t e = pt::launch_zero(ta.work, 1, st);
+    ta.kind = -1;
+    hipError_t e = pt::launch_zero(ta.work, pt::kWorkWords, st);
     if (e != hipSuccess) return hip_fail(e, "launch (zero)");
     e = pt::launch_trace(scene->dev, ta, false, st);
     if (e != hipSuccess) return hip_fail(e, "launch (trace)");
@@ -766,7 +774,7 @@ static size_t batch_table_stride(int max_jobs) { return align256((size_t)max_job
 
 size_t pt_batch_base_bytes(int max_jobs) {
     if (max_jobs <= 0 || max_jobs > 65536) return 0;
-    return kBatchRing * batch_table_stride(max_jobs) + align256(kBatchRing * 4) +
+    return kBatchRing * batch_table_stride(max_jobs) + align256((size_t)kBatchRing * pt::kWorkWords * 4) +
            align256((size_t)pt::kMaxTraceBlocks * pt::kTraceBlock * pt::kStackOvf * 4);
 }
 
@@ -829,7 +837,7 @@ pt_status pt_batch_create(int max_jobs, pt_group group, void* arena, size_t byte
     bt->table_stride = batch_table_stride(max_jobs);
     bt->table_off = 0;
     bt->counter_off = kBatchRing * bt->table_stride;
-    bt->ovf_off = bt->counter_off + align256(kBatchRing * 4);
+    bt->ovf_off = bt->counter_off + align256((size_t)kBatchRing * pt::kWorkWords * 4);
     bt->pool_off = base;
     try {
         bt->jobs.resize(max_jobs);
@@ -876,6 +884,8 @@ pt_status pt_batch_submit(pt_batch bt, const pt_job* job, uint32_t* job_id) {
     if (!bt || !job || !job_id) return fail(PT_EINVAL, "null argument");
     if (!job->scene || !job->scene->uploaded) return fail(PT_EINVAL, "job scene is not uploaded");
     if (job->scene->device != bt->device) return fail(PT_EINVAL, "job scene lives on another device");
+    if ((int)bt->group.traversal - 1 > pt::trace_kind(job->scene->dev))
+        return fail(PT_EINVAL, "traversal %d is not available for this job's scene", bt->group.traversal);
     if (job->mode != PT_MODE_INCOHERENT && job->mode != PT_MODE_REUSE)
         return fail(PT_EUNSUPPORTED, "batches support the incoherent and reuse modes");
     if (job->w <= 0 || job->h <= 0 || job->spp <= 0 || job->bounces < 0 || job->bounces > 64)
@@ -960,7 +970,7 @@ static hipError_t batch_launch_step(pt_batch bt, const pt::StepJob* dtab, int nj
     hipError_t e;
     {
         TimerScope tsc(timer, st, 1, -1);
-        e = pt::launch_zero(counter, 1, st);
+        e = pt::launch_zero(counter, pt::kWorkWords, st);
         if (e == hipSuccess) e = pt::launch_raygen_multi(dtab, njobs, blocks, ts, st);
     }
     if (e != hipSuccess) return e;
@@ -972,12 +982,15 @@ static hipError_t batch_launch_step(pt_batch bt, const pt::StepJob* dtab, int nj
     ta.refill = bt->group.refill ? bt->group.refill : kDefaultRefill;
     ta.waves_per_cu = bt->group.waves_per_cu;
     ta.leaf_gate = (bt->group.leaf_gate ? bt->group.leaf_gate : pt::kDefaultLeafGate) - 1;
-    bool wide = true;
+    // one kernel for every job: the one asked for, else the narrowest kind any of their scenes needs
+    int kind = pt::kTraceWideQueue;
     for (auto& J : bt->jobs)
-        if (J.used) wide = wide && J.job.scene->dev.wide != 0;
+        if (J.used) kind = std::min(kind, pt::trace_kind(J.job.scene->dev));
+    if (bt->group.traversal) kind = bt->group.traversal - 1;   // every job's scene allows it (checked at submit)
+    ta.kind = kind;
     {
         TimerScope tsc(timer, st, 0, -1);
-        e = pt::launch_trace_multi(dtab, njobs, ta, wide, st);
+        e = pt::launch_trace_multi(dtab, njobs, ta, kind, st);
     }
     if (e != hipSuccess) return e;
     TimerScope tsc(timer, st, 2, -1);
@@ -1010,7 +1023,7 @@ pt_status pt_batch_step(pt_batch bt, void* stream, int* active) {
     pt::StepJob* dtab = (pt::StepJob*)(bt->arena + bt->table_off + (size_t)slot * bt->table_stride);
     hipError_t e = hipMemcpyAsync(dtab, tab.data(), (size_t)n * sizeof(pt::StepJob), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (launch table)");
-    uint32_t* counter = (uint32_t*)(bt->arena + bt->counter_off) + slot;
+    uint32_t* counter = (uint32_t*)(bt->arena + bt->counter_off) + (size_t)slot * pt::kWorkWords;
     e = batch_launch_step(bt, dtab, n, blocks, rays, reuse, counter, nullptr, st);
     if (e != hipSuccess) return hip_fail(e, "launch (batch step)");
     e = hipEventRecord(bt->ring_ev[slot], st);
@@ -1100,7 +1113,7 @@ pt_status pt_batch_run(pt_batch bt, int use_graph, pt_timer timer, void* stream)
         batch_drop_graph(bt);
         size_t need = 0;
         for (int k = 0; k < nsteps; ++k) need += align256(tabs[k].size() * sizeof(pt::StepJob));
-        need += align256((size_t)nsteps * 4);
+        need += align256((size_t)nsteps * pt::kWorkWords * 4);
         size_t off = 0;
         if (!pool_alloc(bt, need, &off)) return fail(PT_ENOMEM, "arena has no room for the schedule (%zu bytes)", need);
         bt->sched_off = off;
@@ -1118,11 +1131,12 @@ pt_status pt_batch_run(pt_batch bt, int use_graph, pt_timer timer, void* stream)
     }
     auto enqueue = [&](pt_timer tm) -> hipError_t {
         size_t o = bt->sched_off;
-        uint32_t* counters = (uint32_t*)(bt->arena + bt->sched_off + bt->sched_bytes - align256((size_t)nsteps * 4));
+        uint32_t* counters =
+            (uint32_t*)(bt->arena + bt->sched_off + bt->sched_bytes - align256((size_t)nsteps * pt::kWorkWords * 4));
         for (int k = 0; k < nsteps; ++k) {
             const pt::StepJob* dtab = (const pt::StepJob*)(bt->arena + o);
             hipError_t e = batch_launch_step(bt, dtab, (int)tabs[k].size(), tblocks[k], trays[k], treuse[k] != 0,
-                                             counters + k, tm, st);
+                                             counters + (size_t)k * pt::kWorkWords, tm, st);
             if (e != hipSuccess) return e;
             o += align256(tabs[k].size() * sizeof(pt::StepJob));
         }

@@ -44,9 +44,15 @@ constexpr float kShadowTmax = 1.0f - 0x1p-10f;
 constexpr int kTraceBlock = 64;    // one wave per workgroup
 constexpr int kStackLds = 16;      // LDS stack entries per lane
 constexpr bool kPreferWide = true; // traverse the four-wide nodes when the scene allows it
+constexpr bool kLeafQueue = true;  // four-wide traversal queues its triangle tests per wave
 constexpr int kStackOvf = kMaxDepth - kStackLds + 16; // global overflow entries per lane
 constexpr int kMaxTraceBlocks = 256 * 32;  // cap of the persistent grid (bounds the overflow area)
 constexpr int kDefaultWavesPerCu = 24;     // persistent grid when the caller leaves it to the library
+// A launch hands out its rays through kRayCounters counters kCounterStride words apart
+// (kWorkWords words of work area per launch, zero at launch).
+constexpr int kRayCounters = 8;
+constexpr int kCounterStride = 64;
+constexpr int kWorkWords = kRayCounters * kCounterStride;
 constexpr int kDefaultLeafGate = 8;        // pt_group.leaf_gate when the caller leaves it to the library
 
 struct TraceArgs {
@@ -54,7 +60,7 @@ struct TraceArgs {
     uint32_t n;
     int32_t* out_prim;         // indexed by pixel (by_pixel) or by ray
     float* out_t;
-    uint32_t* work;            // batch counter, zero at launch
+    uint32_t* work;            // kWorkWords words: the ray counters, zero at launch
     uint32_t* partial;         // optional [grid] per-workgroup count of traced rays
     unsigned long long* stats; // optional [2]
     int32_t* ovf;              // [kStackOvf][grid threads]
@@ -64,6 +70,7 @@ struct TraceArgs {
     int leaf_gate;             // the inner-node phase ends when at most this many lanes lack a leaf
     int shadow;                // shadow rays: blocked iff a triangle lies at 0 < t < kShadowTmax (units of d)
     int skip_empty;            // rays whose pixel word is kNoRay are skipped (not traced, no output)
+    int kind;                  // traversal kernel (kTraceChildPair...), -1 = trace_kind of the scene
 };
 
 // One job of a merged launch (batched rendering): the shade, raygen and trace launches of a
@@ -95,7 +102,11 @@ hipError_t launch_trace(const DevScene& sc, const TraceArgs& a, bool stats, hipS
 // merged launches over njobs jobs (table in device memory); total_rays = sum of nrays,
 // total_blocks = sum of the jobs' workgroups; all jobs share f.TS and the grouping mode
 // wide: every job's scene has four-wide nodes within the stack bound
-hipError_t launch_trace_multi(const StepJob* jobs, int njobs, const TraceArgs& a, bool wide, hipStream_t st);
+// traversal kernel of a scene: child-pair nodes, four-wide nodes, or four-wide nodes with the
+// per-wave queue of triangle tests (scenes of at most 2^26 triangles)
+constexpr int kTraceChildPair = 0, kTraceWide = 1, kTraceWideQueue = 2;
+int trace_kind(const DevScene& sc);   // the fastest kind the scene allows; every smaller kind works too
+hipError_t launch_trace_multi(const StepJob* jobs, int njobs, const TraceArgs& a, int kind, hipStream_t st);
 hipError_t launch_raygen_multi(const StepJob* jobs, int njobs, uint32_t total_blocks, int TS, hipStream_t st);
 hipError_t launch_shade_multi(const StepJob* jobs, int njobs, uint32_t total_blocks, int TS, bool reuse,
                               hipStream_t st);

@@ -275,6 +275,16 @@ __device__ __forceinline__ void cswap(float& ta, int32_t& ka, float& tb, int32_t
     ka = k;
 }
 
+// Rays are handed out by kRayCounters counters, one per XCD (workgroups are dispatched to
+// the XCDs round robin), counter c owning the chunks of 64 rays whose chunk number is c
+// modulo kRayCounters.  The counters advance at about the same pace, so the rays in flight
+// stay in one compact stretch of the queue while the atomics spread over kRayCounters
+// addresses instead of queueing on one.  A wave whose counter has run out moves on to the
+// next; after all of them the wave is done.
+__device__ __forceinline__ uint64_t claimed_ray(uint32_t v, uint32_t c) {
+    return ((((uint64_t)(v >> 6)) * kRayCounters + c) << 6) | (v & 63u);
+}
+
 template <bool STATS, bool MULTI, bool WIDE>
 __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a, uint32_t gthreads,
                                                        const StepJob* jobs, int njobs) {
@@ -288,6 +298,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
     uint32_t traced = 0;
     bool have = false;
     bool exhausted = false;   // wave-uniform: the queue is used up
+    uint32_t cq = blockIdx.x % kRayCounters;   // wave-uniform: the counter claimed from
+    int tries = 0;
     uint32_t oi = 0;
     V3 o = mk3(0.f, 0.f, 0.f), inv = o;
     RayPre rp{};
@@ -305,13 +317,18 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
         const unsigned long long idle = __ballot(!have);
         if (!exhausted && idle != 0 && (__popcll(idle) >= a.refill || idle == ~0ull)) {
             const uint32_t need = (uint32_t)__popcll(idle);
+            const uint32_t c = cq;
             uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(a.work, need);
+            if (lane == 0) base = atomicAdd(a.work + c * kCounterStride, need);
             base = __shfl(base, 0);
-            if (base + need >= n) exhausted = true;
+            if (claimed_ray(base + need, c) >= n) {   // this counter has no rays left
+                if (++tries == kRayCounters) exhausted = true;
+                cq = (cq + 1u) % kRayCounters;
+            }
             if (!have) {
-                const uint32_t i = base + (uint32_t)__popcll(idle & lt);
-                if (i < n) {
+                const uint64_t i64 = claimed_ray(base + (uint32_t)__popcll(idle & lt), c);
+                const uint32_t i = (uint32_t)i64;
+                if (i64 < n) {
                     const float4* rays = a.rays;
                     uint32_t li = i;
                     if constexpr (MULTI) {
@@ -557,6 +574,273 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
         }
     }
     // per-workgroup count of traced rays (no atomics on a shared counter)
+    unsigned int tsum = traced;
+    for (int off = 32; off > 0; off >>= 1) tsum += __shfl_down(tsum, off);
+    if (a.partial && lane == 0) a.partial[blockIdx.x] = tsum;
+    if (STATS) {
+        for (int off = 32; off > 0; off >>= 1) {
+            nv += __shfl_down(nv, off);
+            nt += __shfl_down(nt, off);
+        }
+        if (lane == 0) {
+            atomicAdd(a.stats, nv);
+            atomicAdd(a.stats + 1, nt);
+        }
+    }
+}
+
+// Closest-hit traversal over the four-wide nodes with a per-wave queue of triangle tests.
+// A lane that reaches a leaf appends (lane, triangle) entries for its triangles to a ring
+// in LDS and walks on at once; never holding a leaf, it never waits for one.  The wave
+// tests the queue 64 entries at a time, one entry per lane with the owner's ray (taken
+// by cross-lane shuffles), and folds each hit into the owner's (t, prim id) minimum,
+// kept in LDS as one 64-bit key (t's bits above the prim id: both are non-negative, so
+// the integer order is the lexicographic one) by an LDS atomic minimum.  A partial block
+// is tested when `leaf_gate` + 1 lanes have finished walking and wait on queued tests, or
+// when no lane can walk on.  Owners re-read their key after every block to cull against
+// it.  Culling prunes only, and every queued triangle is tested, so the result is the
+// exact (t, prim id) minimum, as in k_trace.
+constexpr int kLeafQ = 512;                    // ring entries per wave
+constexpr uint32_t kQTriBits = 26;             // triangle index bits of an entry; the lane sits above
+constexpr uint32_t kQTriMask = (1u << kQTriBits) - 1u;
+static_assert(kLeafQ >= 2 * kTraceBlock + kTraceBlock * kMaxLeaf, "one step appends at most 64 leaves");
+static_assert((kLeafQ & (kLeafQ - 1)) == 0, "the ring wraps by masking");
+
+__device__ __forceinline__ unsigned long long hit_key(float t, uint32_t p) {
+    return ((unsigned long long)__float_as_uint(t) << 32) | p;
+}
+
+template <bool STATS, bool MULTI>
+__global__ __launch_bounds__(kTraceBlock) void k_trace_q(DevScene sc, TraceArgs a, uint32_t gthreads,
+                                                         const StepJob* jobs, int njobs) {
+    __shared__ int32_t stk[kStackLds][kTraceBlock];
+    __shared__ uint32_t queue[kLeafQ];
+    __shared__ unsigned long long bestk[kTraceBlock];
+    const int lane = threadIdx.x;
+    const uint32_t gtid = blockIdx.x * kTraceBlock + lane;
+    const uint32_t n = a.n;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    // a shadow ray keeps hits at t < kShadowTmax; prim ids are below INT32_MAX
+    const unsigned long long key0 = a.shadow ? hit_key(kShadowTmax, 0u) : hit_key(INFINITY, (uint32_t)INT32_MAX);
+    unsigned long long nv = 0, nt = 0;
+    uint32_t traced = 0;
+    bool have = false;
+    bool exhausted = false;          // wave-uniform: the queue of rays is used up
+    uint32_t cq = blockIdx.x % kRayCounters;   // wave-uniform: the counter claimed from
+    int tries = 0;
+    uint32_t qhead = 0, qtail = 0;   // wave-uniform ring positions: tested up to qhead, filled up to qtail
+    uint32_t last = 0;               // position of the lane's last entry; pending while qhead <= last
+    uint32_t oi = 0;
+    V3 o = mk3(0.f, 0.f, 0.f), inv = o;
+    RayPre rp{};
+    int32_t excl = -1, node = kDone;
+    float tcull = INFINITY;
+    int sp = 0, novf = 0;
+    const float4* nodes4 = sc.nodes4;
+    const float4* btris = sc.btris;
+    int32_t* oprim = a.out_prim;
+    float* ot = a.out_t;
+    for (;;) {
+        // ---- refill idle lanes with the next rays of the queue
+        const unsigned long long idle = __ballot(!have);
+        if (!exhausted && idle != 0 && (__popcll(idle) >= a.refill || idle == ~0ull)) {
+            const uint32_t need = (uint32_t)__popcll(idle);
+            const uint32_t c = cq;
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(a.work + c * kCounterStride, need);
+            base = __shfl(base, 0);
+            if (claimed_ray(base + need, c) >= n) {   // this counter has no rays left
+                if (++tries == kRayCounters) exhausted = true;
+                cq = (cq + 1u) % kRayCounters;
+            }
+            if (!have) {
+                const uint64_t i64 = claimed_ray(base + (uint32_t)__popcll(idle & lt), c);
+                const uint32_t i = (uint32_t)i64;
+                if (i64 < n) {
+                    const float4* rays = a.rays;
+                    uint32_t li = i;
+                    if constexpr (MULTI) {
+                        int lo = 0, hi = njobs - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (jobs[mid].ray_start <= i) lo = mid; else hi = mid - 1;
+                        }
+                        const StepJob& J = jobs[lo];
+                        li = i - J.ray_start;
+                        rays = J.q_in;
+                        nodes4 = J.sc.nodes4;
+                        btris = J.sc.btris;
+                        oprim = J.trace_prim;
+                        ot = J.trace_t;
+                    }
+                    const float4 r0 = rays[2 * (size_t)li], r1 = rays[2 * (size_t)li + 1];
+                    const uint32_t pix = __float_as_uint(r1.w);
+                    if (!(a.by_pixel || a.skip_empty) || pix != kNoRay) {
+                        o = xyz(r0);
+                        const V3 d = xyz(r1);
+                        excl = __float_as_int(r0.w);
+                        inv = mk3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
+                        rp = prepare(o, d);
+                        bestk[lane] = key0;
+                        tcull = a.shadow ? kShadowTmax * kCullScale : INFINITY;
+                        sp = 0;
+                        novf = 0;
+                        node = 0;
+                        last = qhead - 1u;
+                        oi = a.by_pixel ? pix : li;
+                        have = true;
+                    }
+                }
+            }
+        }
+        if (__ballot(have) == 0) {
+            if (exhausted) break;
+            continue;
+        }
+        // ---- a lane on a leaf queues its triangles and takes the next node
+        const bool on_leaf = have && node < 0 && node != kDone;
+        const uint32_t code = ~(uint32_t)node;
+        const uint32_t cnt = on_leaf ? (code & 7u) + 1u : 0u;
+        uint32_t off = 0, total = 0;
+#pragma unroll
+        for (int bit = 0; bit < kLeafCountBits; ++bit) {
+            const unsigned long long qb = __ballot((cnt >> bit) & 1u);
+            off += (uint32_t)__popcll(qb & lt) << bit;
+            total += (uint32_t)__popcll(qb) << bit;
+        }
+        if (on_leaf) {
+            const uint32_t first = code >> 3;
+            for (uint32_t j = 0; j < cnt; ++j)
+                queue[(qtail + off + j) & (uint32_t)(kLeafQ - 1)] = ((uint32_t)lane << kQTriBits) | (first + j);
+            last = qtail + off + cnt - 1u;
+            if (sp == 0 && novf > 0) {
+                const int m = novf < kStackLds / 2 ? novf : kStackLds / 2;
+                for (int e = 0; e < m; ++e) stk[e][lane] = a.ovf[(size_t)(novf - m + e) * gthreads + gtid];
+                novf -= m;
+                sp = m;
+            }
+            node = sp > 0 ? stk[--sp][lane] : kDone;
+        }
+        qtail += total;
+        // ---- one inner node: the nearest hit child next, the other hits pushed far to near
+        if (have && node >= 0) {
+            const float4* nd = nodes4 + 8 * (size_t)node;
+            const float4 lx = nd[0], hx = nd[1], ly = nd[2], hy = nd[3], lz = nd[4], hz = nd[5], cc = nd[6];
+            if (STATS) ++nv;
+            bool h0, h1, h2, h3;
+            float a0 = slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, o, inv, tcull, h0);
+            float a1 = slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, o, inv, tcull, h1);
+            float a2 = slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, o, inv, tcull, h2);
+            float a3 = slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, o, inv, tcull, h3);
+            int32_t k0 = __float_as_int(cc.x), k1 = __float_as_int(cc.y), k2 = __float_as_int(cc.z),
+                    k3 = __float_as_int(cc.w);
+            h0 = h0 && k0 != kEmpty;
+            h1 = h1 && k1 != kEmpty;
+            h2 = h2 && k2 != kEmpty;
+            h3 = h3 && k3 != kEmpty;
+            const int nh = (int)h0 + (int)h1 + (int)h2 + (int)h3;
+            a0 = h0 ? a0 : INFINITY;
+            a1 = h1 ? a1 : INFINITY;
+            a2 = h2 ? a2 : INFINITY;
+            a3 = h3 ? a3 : INFINITY;
+            cswap(a0, k0, a1, k1);
+            cswap(a2, k2, a3, k3);
+            cswap(a0, k0, a2, k2);
+            cswap(a1, k1, a3, k3);
+            cswap(a1, k1, a2, k2);
+            if (nh == 0) {
+                if (sp == 0 && novf > 0) {
+                    const int m = novf < kStackLds / 2 ? novf : kStackLds / 2;
+                    for (int e = 0; e < m; ++e) stk[e][lane] = a.ovf[(size_t)(novf - m + e) * gthreads + gtid];
+                    novf -= m;
+                    sp = m;
+                }
+                node = sp > 0 ? stk[--sp][lane] : kDone;
+            } else {
+                node = k0;
+                if (sp + nh - 1 > kStackLds) {
+                    if (novf + kStackLds / 2 > kStackOvf) {
+                        node = kDone;   // unreachable within the depth bound of wide trees
+                        sp = 0;
+                        novf = 0;
+                    } else {
+                        for (int e = 0; e < kStackLds / 2; ++e)
+                            a.ovf[(size_t)(novf + e) * gthreads + gtid] = stk[e][lane];
+                        for (int e = 0; e < kStackLds / 2; ++e) stk[e][lane] = stk[e + kStackLds / 2][lane];
+                        novf += kStackLds / 2;
+                        sp -= kStackLds / 2;
+                    }
+                }
+                if (node != kDone) {
+                    if (nh == 4) stk[sp++][lane] = k3;
+                    if (nh >= 3) stk[sp++][lane] = k2;
+                    if (nh >= 2) stk[sp++][lane] = k1;
+                }
+            }
+        }
+        // ---- queued triangle tests: every whole block of 64, and a partial one when lanes wait on it
+        const bool waiting = have && node == kDone && (int32_t)(last - qhead) >= 0;
+        const int walking = __popcll(__ballot(have && node != kDone));
+        bool partial = qtail != qhead && (walking == 0 || __popcll(__ballot(waiting)) > a.leaf_gate);
+        if (qtail - qhead >= (uint32_t)kTraceBlock || partial) {
+            const int perm = rp.kx | (rp.ky << 2) | (rp.kz << 4);
+            __syncthreads();   // the entries written above are visible to every lane
+            do {
+                const uint32_t p = qhead + (uint32_t)lane;
+                const bool valid = (int32_t)(qtail - p) > 0;
+                const uint32_t e = valid ? queue[p & (uint32_t)(kLeafQ - 1)] : 0u;
+                const int src = (int)(e >> kQTriBits);
+                RayPre r;
+                r.ox = __shfl(rp.ox, src);
+                r.oy = __shfl(rp.oy, src);
+                r.oz = __shfl(rp.oz, src);
+                r.sx = __shfl(rp.sx, src);
+                r.sy = __shfl(rp.sy, src);
+                r.sz = __shfl(rp.sz, src);
+                const int qperm = __shfl(perm, src);
+                r.kx = qperm & 3;
+                r.ky = (qperm >> 2) & 3;
+                r.kz = (qperm >> 4) & 3;
+                const int32_t qexcl = __shfl(excl, src);
+                const float4* qtris = btris;
+                if constexpr (MULTI) {
+                    const uint64_t bp = (uint64_t)(uintptr_t)btris;
+                    const uint32_t lo = __shfl((uint32_t)bp, src), hi = __shfl((uint32_t)(bp >> 32), src);
+                    qtris = (const float4*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+                }
+                if (valid) {
+                    const float4* tp = qtris + 3 * (size_t)(e & kQTriMask);
+                    const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
+                    const int32_t id = __float_as_int(p0.w);
+                    if (STATS) ++nt;
+                    float th;
+                    if (tri_test(r, p0, p1, p2, th) && id != qexcl) atomicMin(&bestk[src], hit_key(th, (uint32_t)id));
+                }
+                const uint32_t left = qtail - qhead;
+                qhead += left < (uint32_t)kTraceBlock ? left : (uint32_t)kTraceBlock;
+                partial = false;
+            } while (qtail - qhead >= (uint32_t)kTraceBlock);
+            __syncthreads();   // the minima are complete; the ring slots are free again
+            if (have) {
+                const unsigned long long k = bestk[lane];
+                tcull = __uint_as_float((uint32_t)(k >> 32)) * kCullScale;
+                if (a.shadow && k != key0) {   // blocked: the shadow ray is answered
+                    node = kDone;
+                    sp = 0;
+                    novf = 0;
+                }
+            }
+        }
+        // ---- finished rays whose tests are all done
+        if (have && node == kDone && (int32_t)(last - qhead) < 0) {
+            const unsigned long long k = bestk[lane];
+            const uint32_t kp = (uint32_t)k;
+            oprim[oi] = k == key0 ? -1 : (int32_t)kp;
+            ot[oi] = __uint_as_float((uint32_t)(k >> 32));
+            ++traced;
+            have = false;
+        }
+    }
     unsigned int tsum = traced;
     for (int off = 32; off > 0; off >>= 1) tsum += __shfl_down(tsum, off);
     if (a.partial && lane == 0) a.partial[blockIdx.x] = tsum;
@@ -1169,29 +1453,47 @@ int trace_grid_blocks(int waves_per_cu) {
     return g;
 }
 
+int trace_kind(const DevScene& sc) {
+    if (!(kPreferWide && sc.wide)) return kTraceChildPair;
+    return (kLeafQueue && sc.ntri <= kQTriMask + 1u) ? kTraceWideQueue : kTraceWide;
+}
+
 hipError_t launch_trace(const DevScene& sc, const TraceArgs& a, bool stats, hipStream_t st) {
     const int g = trace_grid_blocks(a.waves_per_cu);
     const uint32_t gthreads = (uint32_t)g * kTraceBlock;
     if (a.refill < 1 || a.refill > 64) return hipErrorInvalidValue;
     const StepJob* none = nullptr;
-    const bool wide = kPreferWide && sc.wide;
-    if (stats && wide)
-        hipLaunchKernelGGL((k_trace<true, false, true>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
-    else if (stats)
-        hipLaunchKernelGGL((k_trace<true, false, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
-    else if (wide)
-        hipLaunchKernelGGL((k_trace<false, false, true>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
-    else
-        hipLaunchKernelGGL((k_trace<false, false, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+    if (a.kind > trace_kind(sc)) return hipErrorInvalidValue;
+    switch (a.kind >= 0 ? a.kind : trace_kind(sc)) {
+    case kTraceWideQueue:
+        if (stats)
+            hipLaunchKernelGGL((k_trace_q<true, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+        else
+            hipLaunchKernelGGL((k_trace_q<false, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+        break;
+    case kTraceWide:
+        if (stats)
+            hipLaunchKernelGGL((k_trace<true, false, true>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+        else
+            hipLaunchKernelGGL((k_trace<false, false, true>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+        break;
+    default:
+        if (stats)
+            hipLaunchKernelGGL((k_trace<true, false, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+        else
+            hipLaunchKernelGGL((k_trace<false, false, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_trace_multi(const StepJob* jobs, int njobs, const TraceArgs& a, bool wide, hipStream_t st) {
+hipError_t launch_trace_multi(const StepJob* jobs, int njobs, const TraceArgs& a, int kind, hipStream_t st) {
     const int g = trace_grid_blocks(a.waves_per_cu);
     const uint32_t gthreads = (uint32_t)g * kTraceBlock;
     if (a.refill < 1 || a.refill > 64 || njobs < 1) return hipErrorInvalidValue;
     DevScene none{};
-    if (kPreferWide && wide)
+    if (kind == kTraceWideQueue)
+        hipLaunchKernelGGL((k_trace_q<false, true>), dim3(g), dim3(kTraceBlock), 0, st, none, a, gthreads, jobs, njobs);
+    else if (kind == kTraceWide)
         hipLaunchKernelGGL((k_trace<false, true, true>), dim3(g), dim3(kTraceBlock), 0, st, none, a, gthreads, jobs, njobs);
     else
         hipLaunchKernelGGL((k_trace<false, true, false>), dim3(g), dim3(kTraceBlock), 0, st, none, a, gthreads, jobs,

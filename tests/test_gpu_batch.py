@@ -53,7 +53,7 @@ def _same(torch, ref, out, tag):
         assert torch.equal(a.view(torch.int32), b.view(torch.int32)), (tag, key)
 
 
-def _new_batch(api, max_jobs, specs, sc, extra=0):
+def _new_batch(api, max_jobs, specs, sc, extra=0, traversal=0):
     b = api.Batch(max_jobs, 1, tile=TILE, k=K)
     need = api.Batch.base_bytes(max_jobs)
     outs = []
@@ -63,7 +63,7 @@ def _new_batch(api, max_jobs, specs, sc, extra=0):
         need += b.job_bytes(b.job_struct(sc[name], w, h, spp, B, mode, seed, o))
         outs.append(o)
     del b
-    return api.Batch(max_jobs, need + extra, tile=TILE, k=K), outs
+    return api.Batch(max_jobs, need + extra, tile=TILE, k=K, traversal=traversal), outs
 
 
 def test_batch_stepped_with_staggered_arrivals_equals_alone(env):
@@ -96,11 +96,11 @@ def test_batch_stepped_with_staggered_arrivals_equals_alone(env):
         _same(torch, refs[i], outs[i], spec)
 
 
-@pytest.mark.parametrize("use_graph", [False, True])
-def test_batch_static_run_equals_alone(env, use_graph):
+@pytest.mark.parametrize("use_graph,traversal", [(False, "auto"), (True, "auto"), (False, "pair"), (True, "wide")])
+def test_batch_static_run_equals_alone(env, use_graph, traversal):
     torch, api, sc = env
     refs = [_alone(torch, api, sc, spec) for spec in JOBS]
-    b, outs = _new_batch(api, len(JOBS), JOBS, sc, extra=1 << 20)
+    b, outs = _new_batch(api, len(JOBS), JOBS, sc, extra=1 << 20, traversal=traversal)
     for i, (name, w, h, spp, B, mode, seed) in enumerate(JOBS):
         assert b.submit(b.job_struct(sc[name], w, h, spp, B, mode, seed, outs[i])) is not None
     for rep in range(3):
@@ -108,7 +108,7 @@ def test_batch_static_run_equals_alone(env, use_graph):
             o.radiance.fill_(-7.0)
             o.hit_prim.fill_(-7)
             o.hit_t.fill_(-7.0)
-        _say(f"[gpu] static batch run graph={use_graph} rep={rep}")
+        _say(f"[gpu] static batch run graph={use_graph} traversal={traversal} rep={rep}")
         b.run(use_graph=use_graph)
         torch.cuda.synchronize()
         for i, spec in enumerate(JOBS):

@@ -264,14 +264,43 @@ def test_workspace_too_small_is_enomem(api, torch_dev):
     assert st == capi.PT_ENOMEM
 
 
+# ------------------------------------------------------------------ every traversal kernel
+@pytest.mark.parametrize("traversal", ["pair", "wide", "queue"])
+@pytest.mark.parametrize("mode,nee,refill,leaf_gate", [("incoherent", False, 0, 0), ("reuse", False, 1, 1),
+                                                       ("sorted", False, 64, 64), ("reuse", True, 16, 33),
+                                                       ("incoherent", True, 48, 8)])
+def test_render_parity_traversal_kinds(api, orc, torch_dev, traversal, mode, nee, refill, leaf_gate):
+    s, sc, osc = both(api, orc, "mixed_small")
+    assert sc.info()["wide"] == 1
+    _say(f"[gpu] traversal={traversal} mode={mode} nee={nee} refill={refill} leaf_gate={leaf_gate}")
+    g = api.render(sc, 83, 61, 1, 3, mode, (8, 8), 8, None, 47, refill=refill, leaf_gate=leaf_gate, nee=nee,
+                   traversal=traversal)
+    torch_dev.cuda.synchronize()
+    o = osc.render(83, 61, 1, 3, mode=mode, tile=(8, 8), k=8, seed=47, nee=nee)
+    compare_render(g, o, (8, 8), mode)
+    if nee:
+        assert np.array_equal(g["shadow_rays_per_bounce"].cpu().numpy(), o["shadow_rays"].astype(np.int64))
+
+
+def test_traversal_kind_out_of_range_is_einval(api, orc, torch_dev):
+    from paper_2310_07182_amd import capi
+    s, sc, osc = both(api, orc, "tiny")
+    with pytest.raises(capi.PtError) as e:
+        api.render(sc, 16, 16, 1, 1, "reuse", (4, 4), 2, None, 1, traversal=4)
+    assert e.value.status == capi.PT_EINVAL
+
+
 # ------------------------------------------------------------------ full-size workload, sampled tiles
-@pytest.mark.parametrize("mode", ["reuse", "incoherent", "sorted"])
-def test_indoor_full_size_sampled_tiles(api, orc, torch_dev, mode):
+@pytest.mark.parametrize("mode,traversal", [("reuse", "auto"), ("incoherent", "auto"), ("sorted", "auto"),
+                                            ("reuse", "pair"), ("sorted", "wide")])
+def test_indoor_full_size_sampled_tiles(api, orc, torch_dev, mode, traversal):
     s, sc, osc = both(api, orc, "indoor")
     cfg = scenes.CONFIGS["indoor"]
     w, h, B, tile, k = cfg["w"], cfg["h"], cfg["bounces"], cfg["tile"], cfg["k"]
     seed = 2310071821
-    g = gpu_render(api, sc, w, h, 1, B, mode, tile, k, seed)
+    _say(f"[gpu] indoor traversal={traversal}")
+    g = api.render(sc, w, h, 1, B, mode, tile, k, None, seed, traversal=traversal)
+    torch_dev.cuda.synchronize()
     ntx, nty = (w + tile[0] - 1) // tile[0], (h + tile[1] - 1) // tile[1]
     rng = np.random.default_rng(123)
     pick = rng.choice(ntx * nty, 24, replace=False)
