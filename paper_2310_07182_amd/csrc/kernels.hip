@@ -346,26 +346,26 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
                         oprim = J.trace_prim;
                         ot = J.trace_t;
                     }
+                    // set up without a branch on the pixel word, so that the three loads of
+                    // the ray are issued together (one wait, not two in a row)
                     const float4 r0 = rays[2 * (size_t)li], r1 = rays[2 * (size_t)li + 1];
                     const uint32_t pix = __float_as_uint(r1.w);
-                    if (!(a.by_pixel || a.skip_empty) || pix != kNoRay) {
-                        o = xyz(r0);
-                        const V3 d = xyz(r1);
-                        excl = __float_as_int(r0.w);
-                        inv = mk3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
-                        rp = prepare(o, d);
-                        // a shadow ray only asks whether anything lies before the light point:
-                        // hits are kept from t < kShadowTmax on, and INT32_MIN never loses a tie
-                        best_t = a.shadow ? kShadowTmax : INFINITY;
-                        tcull = a.shadow ? kShadowTmax * kCullScale : INFINITY;
-                        best_p = a.shadow ? INT32_MIN : INT32_MAX;
-                        sp = 0;
-                        novf = 0;
-                        node = 0;
-                        leaf = kNoLeaf;
-                        oi = a.by_pixel ? pix : li;
-                        have = true;
-                    }
+                    o = xyz(r0);
+                    const V3 d = xyz(r1);
+                    excl = __float_as_int(r0.w);
+                    inv = mk3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
+                    rp = prepare(o, d);
+                    // a shadow ray only asks whether anything lies before the light point:
+                    // hits are kept from t < kShadowTmax on, and INT32_MIN never loses a tie
+                    best_t = a.shadow ? kShadowTmax : INFINITY;
+                    tcull = a.shadow ? kShadowTmax * kCullScale : INFINITY;
+                    best_p = a.shadow ? INT32_MIN : INT32_MAX;
+                    sp = 0;
+                    novf = 0;
+                    node = 0;
+                    leaf = kNoLeaf;
+                    oi = a.by_pixel ? pix : li;
+                    have = !(a.by_pixel || a.skip_empty) || pix != kNoRay;   // else the lane stays idle
                 }
             }
         }
@@ -673,23 +673,23 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_q(DevScene sc, TraceArgs 
                         oprim = J.trace_prim;
                         ot = J.trace_t;
                     }
+                    // set up without a branch on the pixel word, so that the three loads of
+                    // the ray are issued together (one wait, not two in a row)
                     const float4 r0 = rays[2 * (size_t)li], r1 = rays[2 * (size_t)li + 1];
                     const uint32_t pix = __float_as_uint(r1.w);
-                    if (!(a.by_pixel || a.skip_empty) || pix != kNoRay) {
-                        o = xyz(r0);
-                        const V3 d = xyz(r1);
-                        excl = __float_as_int(r0.w);
-                        inv = mk3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
-                        rp = prepare(o, d);
-                        bestk[lane] = key0;
-                        tcull = a.shadow ? kShadowTmax * kCullScale : INFINITY;
-                        sp = 0;
-                        novf = 0;
-                        node = 0;
-                        last = qhead - 1u;
-                        oi = a.by_pixel ? pix : li;
-                        have = true;
-                    }
+                    o = xyz(r0);
+                    const V3 d = xyz(r1);
+                    excl = __float_as_int(r0.w);
+                    inv = mk3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
+                    rp = prepare(o, d);
+                    bestk[lane] = key0;
+                    tcull = a.shadow ? kShadowTmax * kCullScale : INFINITY;
+                    sp = 0;
+                    novf = 0;
+                    node = 0;
+                    last = qhead - 1u;
+                    oi = a.by_pixel ? pix : li;
+                    have = !(a.by_pixel || a.skip_empty) || pix != kNoRay;   // else the lane stays idle
                 }
             }
         }
