@@ -9,10 +9,11 @@ Headline (value): secondary Mrays/s in reuse mode = rays traced at bounces
 library's stream), the definition of the paper's Table 1.  The same figure for
 the incoherent and sorted modes, end-to-end rates and p50/p99 frame latency
 are reported beside it.  The roofline object describes the traversal kernel:
-algorithmic operations and bytes per launch (nodes visited x 128 B for the
-four-wide nodes, 64 B for child-pair nodes, + triangles tested x 48 B + 32 B ray
-+ 8 B hit, per ray, counted by the counting variant of the kernel in an untimed
-frame) divided by its average launch time.
+algorithmic operations and bytes per launch (nodes visited x 56 B read of the
+quantized four-wide nodes, 128 B of the float four-wide nodes, 64 B of child-pair
+nodes, + triangles tested x 48 B + 32 B ray + 8 B hit, per ray, counted by the
+counting variant of the kernel in an untimed frame) divided by its average launch
+time.
 """
 from __future__ import annotations
 
@@ -39,6 +40,12 @@ OPS_PER_NODE, OPS_PER_TRI = 58, 74
 # a four-wide node visit: four slab tests (4 x 26), the five compare-exchanges of the sorting
 # network on (distance, code) (5 x 5) and ~8 for the pushes and the choice of the next node
 OPS_PER_NODE4, NODE4_BYTES = 137, 128
+# a quantized four-wide node visit: per node the three steps 2^e (4 ops each), a = 2^e / d
+# (3 mul), b = (p - o) / d (3 sub, 3 mul), the moved b for near and far planes (3 mul, 6 add)
+# and the choice of near/far plane bytes by the ray's signs (3 cmp, 6 select) = 39; per child
+# 6 byte conversions, 6 fused multiply-adds, 3 max, 2 min, 1 mul, 2 cmp, 1 and = 21; then
+# the sorting network (25) and the pushes (8).  Bytes read: 56 of the 64-byte node.
+OPS_PER_NODE4Q, NODE4Q_BYTES = 156, 56
 # MI355X vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit op per lane and cycle
 # (no packed FP32, an FMA counted once) = 39.3 T ops/s.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -70,14 +77,32 @@ def measured_traffic(mode, config):
     return None
 
 
+def kernel_label(sc):
+    inf = sc.info()
+    if inf["wide"] and inf["quant"] and inf["ntri"] <= (1 << 26):
+        return "k_trace_q (closest hit over quantized four-wide nodes, per-wave triangle-test queue)"
+    if inf["wide"] and inf["ntri"] <= (1 << 26):
+        return "k_trace_q (closest hit over four-wide nodes, per-wave triangle-test queue)"
+    return "k_trace (closest hit, " + ("four-wide" if inf["wide"] else "child-pair") + " nodes)"
+
+
+def node_costs(sc):
+    """(bytes, ops) of one node visit of the traversal kernel the library picks for the scene."""
+    inf = sc.info()
+    if inf["wide"] and inf["quant"] and inf["ntri"] <= (1 << 26):
+        return NODE4Q_BYTES, OPS_PER_NODE4Q
+    if inf["wide"]:
+        return NODE4_BYTES, OPS_PER_NODE4
+    return NODE_BYTES, OPS_PER_NODE
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
 def bench_mode(api, sc, cfg, mode, steps, warmup, seed0, nee=False):
     import torch
-    wide = bool(sc.info()["wide"])
-    node_bytes, ops_node = (NODE4_BYTES, OPS_PER_NODE4) if wide else (NODE_BYTES, OPS_PER_NODE)
+    node_bytes, ops_node = node_costs(sc)
     rc = api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], mode, tuple(cfg["tile"]), cfg["k"], nee=nee)
     # untimed counting frame: nodes / triangles per ray and rays per bounce
     rs = api.Renderer(sc, rc, stats=True)
@@ -594,7 +619,7 @@ def main():
         "p99_frame_ms": round(head["frame_ms_p99"], 4),
         "roofline": {"bound": "alu", "achieved": round(achieved_ops, 3), "peak": round(VALU_PEAK_TOPS, 2),
                      "unit": "TFLOP/s", "frac": round(achieved_ops / VALU_PEAK_TOPS, 4), "traffic": measured_traffic(head["mode"], args.config),
-                     "kernel": "k_trace (closest-hit traversal), secondary bounces",
+                     "kernel": kernel_label(scene) + ", secondary bounces",
                      "op": "32-bit VALU lane operation (compare/min/max/select counted like add/mul)",
                      "ops_per_ray": round(head["ops_per_ray"], 1),
                      "algorithmic_bytes_per_ray": round(head["bytes_per_ray"], 1),

@@ -32,7 +32,7 @@ def camera_struct(cam: dict) -> capi.Camera:
 
 
 # pt_group.traversal by name
-TRAVERSALS = {"auto": 0, "pair": 1, "wide": 2, "queue": 3}
+TRAVERSALS = {"auto": 0, "pair": 1, "wide": 2, "queue": 3, "quant": 4}
 
 
 def group_struct(tile=(8, 8), k=8, reuse_max_bounce=0xFFFF, refill=0, waves_per_cu=0, leaf_gate=0,
@@ -90,7 +90,7 @@ class Scene:
         check(lib().pt_scene_get_info(self.handle, C.byref(i)))
         return dict(ntri=i.ntri, nnodes=i.nnodes, max_depth=i.max_depth, max_leaf=i.max_leaf,
                     lo=list(i.lo), hi=list(i.hi), sah_cost=i.sah_cost, device_bytes=i.device_bytes, nemit=i.nemit,
-                    nnodes4=i.nnodes4, max_depth4=i.max_depth4, wide=i.wide)
+                    nnodes4=i.nnodes4, max_depth4=i.max_depth4, wide=i.wide, quant=i.quant)
 
     def export_bvh(self):
         inf = self.info()

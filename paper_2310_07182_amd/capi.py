@@ -49,7 +49,8 @@ class SceneInfo(C.Structure):
     _fields_ = [("ntri", C.c_uint32), ("nnodes", C.c_uint32), ("max_depth", C.c_uint32),
                 ("max_leaf", C.c_uint32), ("lo", C.c_float * 3), ("hi", C.c_float * 3),
                 ("sah_cost", C.c_double), ("device_bytes", C.c_uint64), ("nemit", C.c_uint32),
-                ("nnodes4", C.c_uint32), ("max_depth4", C.c_uint32), ("wide", C.c_uint32)]
+                ("nnodes4", C.c_uint32), ("max_depth4", C.c_uint32), ("wide", C.c_uint32),
+                ("quant", C.c_uint32)]
 
 
 class Outputs(C.Structure):
@@ -74,6 +75,7 @@ PROTOTYPES = {
     "pt_scene_get_info": (_st, [_vp, C.POINTER(SceneInfo)]),
     "pt_scene_export_bvh": (_st, [_vp, _vp, _vp]),
     "pt_scene_export_bvh4": (_st, [_vp, _vp]),
+    "pt_scene_export_bvh4q": (_st, [_vp, _vp]),
     "pt_scene_free": (_st, [_vp]),
     "pt_render_workspace_bytes": (_sz, [_i32, _i32, _i32, _i32, _i32, Group]),
     "pt_render": (_st, [_vp, C.POINTER(Camera), _i32, _i32, _i32, _i32, _i32, Group, C.c_uint64, _vp, _sz,

@@ -205,6 +205,7 @@ bool build_bvh(const float* tris, uint32_t ntri, HostBvh& out, std::string& err)
     if (ntri == 0) {
         out.nodes.push_back(empty_root);
         collapse_bvh4(out.nodes, out.nodes4, out.max_depth4);
+        out.quant_ok = quantize_bvh4(out.nodes4, out.nodes4q);
         return true;
     }
     Builder b;
@@ -287,6 +288,7 @@ bool build_bvh(const float* tris, uint32_t ntri, HostBvh& out, std::string& err)
     out.order = std::move(b.idx);
     try {
         collapse_bvh4(out.nodes, out.nodes4, out.max_depth4);
+        out.quant_ok = quantize_bvh4(out.nodes4, out.nodes4q);
     } catch (...) {
         err = "host allocation failed";
         return false;
@@ -372,6 +374,78 @@ void collapse_bvh4(const std::vector<BvhNode>& n2, std::vector<Bvh4Node>& n4, ui
             if (e[j].code >= 0) stack.push_back(Item{e[j].code, (uint32_t)nd.c[j], it.depth + 1});
         n4[it.slot] = nd;
     }
+}
+
+
+bool quantize_bvh4(const std::vector<Bvh4Node>& n4, std::vector<Bvh4QNode>& q) {
+    bool ok = true;
+    q.assign(n4.size(), Bvh4QNode{});
+    for (size_t i = 0; i < n4.size(); ++i) {
+        const Bvh4Node& n = n4[i];
+        Bvh4QNode& o = q[i];
+        const float* lo4[3] = {n.lx, n.ly, n.lz};
+        const float* hi4[3] = {n.hx, n.hy, n.hz};
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        bool any = false;
+        for (int j = 0; j < 4; ++j) {
+            o.c[j] = n.c[j];
+            if (n.c[j] == kEmpty) continue;
+            any = true;
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = std::min(lo[a], lo4[a][j]);
+                hi[a] = std::max(hi[a], hi4[a][j]);
+            }
+        }
+        uint32_t ql[3] = {0, 0, 0}, qh[3] = {0, 0, 0};
+        int e[3] = {0, 0, 0};
+        if (any) {
+            for (int a = 0; a < 3; ++a) {
+                // the smallest step 2^e that spans the node in at most 255 steps (upper bound of the extent)
+                const double ext = std::nextafter((double)hi[a] - (double)lo[a], INFINITY);
+                int ea = -100;
+                if (ext > 0.0) ea = std::max(-100, (int)std::ceil(std::log2(ext / 255.0)));
+                while (std::ceil(ext / std::ldexp(1.0, ea)) > 255.0) ++ea;
+                if (ea > kQMaxExp) {
+                    ok = false;
+                    ea = kQMaxExp;   // the node is unusable; keep the byte in range
+                }
+                e[a] = ea;
+                const double step = std::ldexp(1.0, ea);
+                for (int j = 0; j < 4; ++j) {
+                    uint32_t l = 255, h = 0;
+                    if (n.c[j] != kEmpty) {
+                        // differences bounded outward (one ulp beyond a rounded double), so that
+                        // p + l * step <= child lo and p + h * step >= child hi hold exactly
+                        const double dl = std::max(0.0, std::nextafter((double)lo4[a][j] - (double)lo[a], -INFINITY));
+                        const double dh = std::nextafter((double)hi4[a][j] - (double)lo[a], INFINITY);
+                        l = (uint32_t)std::min(255.0, std::floor(dl / step));
+                        h = (uint32_t)std::min(255.0, std::ceil(dh / step));
+                    }
+                    ql[a] |= l << (8 * j);
+                    qh[a] |= h << (8 * j);
+                }
+            }
+        } else {
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = 0.0f;
+                ql[a] = 0xFFFFFFFFu;
+                qh[a] = 0u;
+            }
+        }
+        o.px = lo[0];
+        o.py = lo[1];
+        o.pz = lo[2];
+        o.exps = (int32_t)(((uint32_t)(uint8_t)(int8_t)e[0]) | ((uint32_t)(uint8_t)(int8_t)e[1] << 8) |
+                           ((uint32_t)(uint8_t)(int8_t)e[2] << 16));
+        o.qlx = ql[0];
+        o.qhx = qh[0];
+        o.qly = ql[1];
+        o.qhy = qh[1];
+        o.qlz = ql[2];
+        o.qhz = qh[2];
+        o.pad0 = o.pad1 = 0;
+    }
+    return ok;
 }
 
 }  // namespace pt

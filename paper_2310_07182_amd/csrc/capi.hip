@@ -28,7 +28,7 @@ struct pt_scene_s {
     uint32_t ntri = 0, nmat = 0;
     float env[3] = {0, 0, 0};
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    size_t off_nodes = 0, off_nodes4 = 0, off_btris = 0, off_otris = 0, off_mat = 0, off_mats = 0, off_emit = 0,
+    size_t off_nodes = 0, off_nodes4 = 0, off_nodes4q = 0, off_btris = 0, off_otris = 0, off_mat = 0, off_mats = 0, off_emit = 0,
            bytes = 0;
     bool uploaded = false;
     int device = -1;
@@ -130,7 +130,7 @@ pt_status check_group(pt_group g, int bounces) {
     if (g.refill > 64) return fail(PT_EINVAL, "refill must be in [0, 64] (got %d)", g.refill);
     if (g.leaf_gate > 64) return fail(PT_EINVAL, "leaf_gate must be in [0, 64] (got %d)", g.leaf_gate);
     if (g.nee > 1) return fail(PT_EINVAL, "nee must be 0 or 1 (got %d)", g.nee);
-    if (g.traversal > 3) return fail(PT_EINVAL, "traversal must be in [0, 3] (got %d)", g.traversal);
+    if (g.traversal > 4) return fail(PT_EINVAL, "traversal must be in [0, 4] (got %d)", g.traversal);
     return PT_OK;
 }
 
@@ -384,6 +384,8 @@ pt_status pt_scene_create(const pt_scene_desc* d, pt_scene* out) {
         o = align256(o + s->bvh.nodes.size() * sizeof(pt::BvhNode));
         s->off_nodes4 = o;
         o = align256(o + s->bvh.nodes4.size() * sizeof(pt::Bvh4Node));
+        s->off_nodes4q = o;
+        o = align256(o + s->bvh.nodes4q.size() * sizeof(pt::Bvh4QNode));
         s->off_btris = o;
         o = align256(o + s->btris.size() * sizeof(float4));
         s->off_otris = o;
@@ -418,6 +420,7 @@ pt_status pt_scene_upload(pt_scene s, void* arena, size_t bytes, void* stream) {
     } parts[] = {
         {s->off_nodes, s->bvh.nodes.data(), s->bvh.nodes.size() * sizeof(pt::BvhNode)},
         {s->off_nodes4, s->bvh.nodes4.data(), s->bvh.nodes4.size() * sizeof(pt::Bvh4Node)},
+        {s->off_nodes4q, s->bvh.nodes4q.data(), s->bvh.nodes4q.size() * sizeof(pt::Bvh4QNode)},
         {s->off_btris, s->btris.data(), s->btris.size() * sizeof(float4)},
         {s->off_otris, s->otris.data(), s->otris.size() * sizeof(float4)},
         {s->off_mat, s->tri_mat.data(), s->tri_mat.size() * 4},
@@ -438,6 +441,8 @@ pt_status pt_scene_upload(pt_scene s, void* arena, size_t bytes, void* stream) {
     DevScene& d = s->dev;
     d.nodes = (const float4*)(base + s->off_nodes);
     d.nodes4 = (const float4*)(base + s->off_nodes4);
+    d.nodes4q = (const float4*)(base + s->off_nodes4q);
+    d.quant = s->bvh.quant_ok ? 1u : 0u;
     // four-wide traversal pushes up to three siblings per level: use it when the stack bound holds
     d.wide = (pt::kPreferWide && 3u * s->bvh.max_depth4 + 4u <= (uint32_t)(pt::kStackLds + pt::kStackOvf)) ? 1u : 0u;
     d.btris = (const float4*)(base + s->off_btris);
@@ -474,6 +479,7 @@ pt_status pt_scene_get_info(pt_scene s, pt_scene_info* info) {
     info->nnodes4 = (uint32_t)s->bvh.nodes4.size();
     info->max_depth4 = s->bvh.max_depth4;
     info->wide = (pt::kPreferWide && 3u * s->bvh.max_depth4 + 4u <= (uint32_t)(pt::kStackLds + pt::kStackOvf)) ? 1u : 0u;
+    info->quant = s->bvh.quant_ok ? 1u : 0u;
     return PT_OK;
 }
 
@@ -487,6 +493,13 @@ pt_status pt_scene_export_bvh(pt_scene s, void* nodes, uint32_t* order) {
 pt_status pt_scene_export_bvh4(pt_scene s, void* nodes4) {
     if (!s || !nodes4) return fail(PT_EINVAL, "null argument");
     if (!s->bvh.nodes4.empty()) memcpy(nodes4, s->bvh.nodes4.data(), s->bvh.nodes4.size() * sizeof(pt::Bvh4Node));
+    return PT_OK;
+}
+
+pt_status pt_scene_export_bvh4q(pt_scene s, void* nodes4q) {
+    if (!s || !nodes4q) return fail(PT_EINVAL, "null argument");
+    if (!s->bvh.nodes4q.empty())
+        memcpy(nodes4q, s->bvh.nodes4q.data(), s->bvh.nodes4q.size() * sizeof(pt::Bvh4QNode));
     return PT_OK;
 }
 
@@ -521,9 +534,9 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
     if (ge != hipSuccess) return hip_fail(ge, "hipGetDevice");
     if (dev != scene->device) return fail(PT_EINVAL, "scene was uploaded on device %d, current device is %d", scene->device, dev);
     const int kind = (int)g.traversal - 1;   // -1: the scene's own choice
-    if (kind > pt::trace_kind(scene->dev))
+    if (kind > pt::trace_max_kind(scene->dev))
         return fail(PT_EINVAL, "traversal %d is not available for this scene (at most %d)", g.traversal,
-                    pt::trace_kind(scene->dev) + 1);
+                    pt::trace_max_kind(scene->dev) + 1);
 
     Frame f = make_frame(w, h, spp, B, mode, g, seed);
     if (is_sorted_mode(mode) && f.nslots > (1u << 27))
@@ -884,7 +897,7 @@ pt_status pt_batch_submit(pt_batch bt, const pt_job* job, uint32_t* job_id) {
     if (!bt || !job || !job_id) return fail(PT_EINVAL, "null argument");
     if (!job->scene || !job->scene->uploaded) return fail(PT_EINVAL, "job scene is not uploaded");
     if (job->scene->device != bt->device) return fail(PT_EINVAL, "job scene lives on another device");
-    if ((int)bt->group.traversal - 1 > pt::trace_kind(job->scene->dev))
+    if ((int)bt->group.traversal - 1 > pt::trace_max_kind(job->scene->dev))
         return fail(PT_EINVAL, "traversal %d is not available for this job's scene", bt->group.traversal);
     if (job->mode != PT_MODE_INCOHERENT && job->mode != PT_MODE_REUSE)
         return fail(PT_EUNSUPPORTED, "batches support the incoherent and reuse modes");
@@ -983,7 +996,7 @@ static hipError_t batch_launch_step(pt_batch bt, const pt::StepJob* dtab, int nj
     ta.waves_per_cu = bt->group.waves_per_cu;
     ta.leaf_gate = (bt->group.leaf_gate ? bt->group.leaf_gate : pt::kDefaultLeafGate) - 1;
     // one kernel for every job: the one asked for, else the narrowest kind any of their scenes needs
-    int kind = pt::kTraceWideQueue;
+    int kind = pt::kTraceWideQueueQ;
     for (auto& J : bt->jobs)
         if (J.used) kind = std::min(kind, pt::trace_kind(J.job.scene->dev));
     if (bt->group.traversal) kind = bt->group.traversal - 1;   // every job's scene allows it (checked at submit)

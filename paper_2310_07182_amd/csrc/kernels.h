@@ -13,6 +13,8 @@ namespace pt {
 struct DevScene {
     const float4* nodes;     // [nnodes][4]  child-pair nodes
     const float4* nodes4;    // [nnodes4][8] four-wide nodes of the same tree
+    const float4* nodes4q;   // [nnodes4][4] the four-wide nodes with quantized child boxes
+    uint32_t quant;          // the quantized nodes are usable (every step 2^e has e <= 60)
     uint32_t wide;           // traverse the four-wide nodes
     const float4* btris;     // [ntri][3]    BVH order; v0.w = original triangle id (int bits)
     const float4* otris;     // [ntri][3]    original order
@@ -45,6 +47,7 @@ constexpr int kTraceBlock = 64;    // one wave per workgroup
 constexpr int kStackLds = 16;      // LDS stack entries per lane
 constexpr bool kPreferWide = true; // traverse the four-wide nodes when the scene allows it
 constexpr bool kLeafQueue = true;  // four-wide traversal queues its triangle tests per wave
+constexpr bool kQuantized = true;  // and reads the quantized nodes
 constexpr int kStackOvf = kMaxDepth - kStackLds + 16; // global overflow entries per lane
 constexpr int kMaxTraceBlocks = 256 * 32;  // cap of the persistent grid (bounds the overflow area)
 constexpr int kDefaultWavesPerCu = 24;     // persistent grid when the caller leaves it to the library
@@ -104,8 +107,9 @@ hipError_t launch_trace(const DevScene& sc, const TraceArgs& a, bool stats, hipS
 // wide: every job's scene has four-wide nodes within the stack bound
 // traversal kernel of a scene: child-pair nodes, four-wide nodes, or four-wide nodes with the
 // per-wave queue of triangle tests (scenes of at most 2^26 triangles)
-constexpr int kTraceChildPair = 0, kTraceWide = 1, kTraceWideQueue = 2;
-int trace_kind(const DevScene& sc);   // the fastest kind the scene allows; every smaller kind works too
+constexpr int kTraceChildPair = 0, kTraceWide = 1, kTraceWideQueue = 2, kTraceWideQueueQ = 3;
+int trace_max_kind(const DevScene& sc);   // the widest kind the scene allows; every smaller kind works too
+int trace_kind(const DevScene& sc);       // the kind used when the caller leaves it to the library
 hipError_t launch_trace_multi(const StepJob* jobs, int njobs, const TraceArgs& a, int kind, hipStream_t st);
 hipError_t launch_raygen_multi(const StepJob* jobs, int njobs, uint32_t total_blocks, int TS, hipStream_t st);
 hipError_t launch_shade_multi(const StepJob* jobs, int njobs, uint32_t total_blocks, int TS, bool reuse,

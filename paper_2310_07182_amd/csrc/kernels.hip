@@ -600,6 +600,66 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
 // when no lane can walk on.  Owners re-read their key after every block to cull against
 // it.  Culling prunes only, and every queued triangle is tested, so the result is the
 // exact (t, prim id) minimum, as in k_trace.
+// Slab tests of the four children of a quantized node (p, exponents in g; child planes
+// in q0 = {lo x, hi x, lo y, hi y}, q1 = {lo z, hi z}, one byte per child).  Along an axis,
+// the distance to plane p + q * 2^e is t = q * a + b with a = 2^e * inv (exact) and
+// b = (p - o) * inv (two roundings).  b is moved by 2^-21 |b| (more than the 2.01 ulp its
+// roundings can be off, plus the rounding of the move) toward the near side for near planes
+// and the far side for far planes, so that the single rounding of the fused q * a + b is
+// the only error left, relative to t, which the far-distance widening of the child-pair
+// test covers.  Near and far planes are chosen by the sign of inv.  A direction component
+// of zero gives infinities or NaN along that axis, which drop the axis from the min and
+// max below (never a wrong cull).  The fused multiply-add is used on purpose: this test
+// only prunes, and every result stays the exact (t, prim id) minimum.
+constexpr float kQSlack = 0x1p-21f;
+// Rays with |1/d| above this along some axis (a direction component of zero or below 2^-64)
+// take the float boxes of the four-wide node of the same index instead: there the
+// quantized form would drop the axis instead of culling by it, and 2^e / d could overflow.
+// The node's steps are at most 2^60 (scenes that need more do not get quantized nodes), so
+// 2^e * inv stays finite below this bound.
+constexpr float kQMaxInv = 0x1p64f;
+
+__device__ __forceinline__ float qexp2(int32_t exps, int shift) {
+    const int e = (int)(int8_t)(uint8_t)((uint32_t)exps >> shift);
+    return __int_as_float((e + 127) << 23);
+}
+
+__device__ __forceinline__ float qplane(uint32_t q, int j, float a, float b) {
+    return fmaf((float)((q >> (8 * j)) & 0xFFu), a, b);
+}
+
+__device__ __forceinline__ void qslab4(float4 g, float4 q0, float4 q1, V3 o, V3 inv, float tcull, float& t0,
+                                       float& t1, float& t2, float& t3, bool& h0, bool& h1, bool& h2, bool& h3) {
+    const int32_t exps = __float_as_int(g.w);
+    const float ax = qexp2(exps, 0) * inv.x, ay = qexp2(exps, 8) * inv.y, az = qexp2(exps, 16) * inv.z;
+    const float bx = (g.x - o.x) * inv.x, by = (g.y - o.y) * inv.y, bz = (g.z - o.z) * inv.z;
+    const float sx = fabsf(bx) * kQSlack, sy = fabsf(by) * kQSlack, sz = fabsf(bz) * kQSlack;
+    const float nbx = bx - sx, fbx = bx + sx, nby = by - sy, fby = by + sy, nbz = bz - sz, fbz = bz + sz;
+    const bool px = inv.x >= 0.0f, py = inv.y >= 0.0f, pz = inv.z >= 0.0f;
+    const uint32_t nqx = __float_as_uint(px ? q0.x : q0.y), fqx = __float_as_uint(px ? q0.y : q0.x);
+    const uint32_t nqy = __float_as_uint(py ? q0.z : q0.w), fqy = __float_as_uint(py ? q0.w : q0.z);
+    const uint32_t nqz = __float_as_uint(pz ? q1.x : q1.y), fqz = __float_as_uint(pz ? q1.y : q1.x);
+    float tn[4];
+    bool hh[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float n = fmaxf(fmaxf(qplane(nqx, j, ax, nbx), qplane(nqy, j, ay, nby)),
+                              fmaxf(qplane(nqz, j, az, nbz), 0.0f));
+        const float f = fminf(fminf(qplane(fqx, j, ax, fbx), qplane(fqy, j, ay, fby)), qplane(fqz, j, az, fbz)) *
+                        kFarScale;
+        tn[j] = n;
+        hh[j] = n <= f && n <= tcull;
+    }
+    t0 = tn[0];
+    t1 = tn[1];
+    t2 = tn[2];
+    t3 = tn[3];
+    h0 = hh[0];
+    h1 = hh[1];
+    h2 = hh[2];
+    h3 = hh[3];
+}
+
 constexpr int kLeafQ = 512;                    // ring entries per wave
 constexpr uint32_t kQTriBits = 26;             // triangle index bits of an entry; the lane sits above
 constexpr uint32_t kQTriMask = (1u << kQTriBits) - 1u;
@@ -610,8 +670,8 @@ __device__ __forceinline__ unsigned long long hit_key(float t, uint32_t p) {
     return ((unsigned long long)__float_as_uint(t) << 32) | p;
 }
 
-template <bool STATS, bool MULTI>
-__global__ __launch_bounds__(kTraceBlock) void k_trace_q(DevScene sc, TraceArgs a, uint32_t gthreads,
+template <bool STATS, bool MULTI, bool QN>
+__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_trace_q(DevScene sc, TraceArgs a, uint32_t gthreads,
                                                          const StepJob* jobs, int njobs) {
     __shared__ int32_t stk[kStackLds][kTraceBlock];
     __shared__ uint32_t queue[kLeafQ];
@@ -636,7 +696,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_q(DevScene sc, TraceArgs 
     int32_t excl = -1, node = kDone;
     float tcull = INFINITY;
     int sp = 0, novf = 0;
-    const float4* nodes4 = sc.nodes4;
+    const float4* nodes4 = QN ? sc.nodes4q : sc.nodes4;
+    const float4* nodesf = sc.nodes4;   // float boxes: rays with a direction component below 2^-64
+    bool flat = false;
     const float4* btris = sc.btris;
     int32_t* oprim = a.out_prim;
     float* ot = a.out_t;
@@ -668,7 +730,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_q(DevScene sc, TraceArgs 
                         const StepJob& J = jobs[lo];
                         li = i - J.ray_start;
                         rays = J.q_in;
-                        nodes4 = J.sc.nodes4;
+                        nodes4 = QN ? J.sc.nodes4q : J.sc.nodes4;
+                        nodesf = J.sc.nodes4;
                         btris = J.sc.btris;
                         oprim = J.trace_prim;
                         ot = J.trace_t;
@@ -682,6 +745,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_q(DevScene sc, TraceArgs 
                     excl = __float_as_int(r0.w);
                     inv = mk3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
                     rp = prepare(o, d);
+                    flat = !(fabsf(inv.x) <= kQMaxInv && fabsf(inv.y) <= kQMaxInv && fabsf(inv.z) <= kQMaxInv);
                     bestk[lane] = key0;
                     tcull = a.shadow ? kShadowTmax * kCullScale : INFINITY;
                     sp = 0;
@@ -724,14 +788,24 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_q(DevScene sc, TraceArgs 
         qtail += total;
         // ---- one inner node: the nearest hit child next, the other hits pushed far to near
         if (have && node >= 0) {
-            const float4* nd = nodes4 + 8 * (size_t)node;
-            const float4 lx = nd[0], hx = nd[1], ly = nd[2], hy = nd[3], lz = nd[4], hz = nd[5], cc = nd[6];
-            if (STATS) ++nv;
             bool h0, h1, h2, h3;
-            float a0 = slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, o, inv, tcull, h0);
-            float a1 = slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, o, inv, tcull, h1);
-            float a2 = slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, o, inv, tcull, h2);
-            float a3 = slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, o, inv, tcull, h3);
+            float a0, a1, a2, a3;
+            // the codes are the same in both node arrays: read them from the array the lane
+            // walks before any branch (one 16-byte load, not one per path)
+            const float4 cc = QN ? nodes4[4 * (size_t)node + 1] : nodes4[8 * (size_t)node + 6];
+            if (QN && !flat) {
+                const float4* nd = nodes4 + 4 * (size_t)node;
+                const float4 g = nd[0], q0 = nd[2], q1 = nd[3];
+                qslab4(g, q0, q1, o, inv, tcull, a0, a1, a2, a3, h0, h1, h2, h3);
+            } else {
+                const float4* nd = (QN ? nodesf : nodes4) + 8 * (size_t)node;
+                const float4 lx = nd[0], hx = nd[1], ly = nd[2], hy = nd[3], lz = nd[4], hz = nd[5];
+                a0 = slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, o, inv, tcull, h0);
+                a1 = slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, o, inv, tcull, h1);
+                a2 = slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, o, inv, tcull, h2);
+                a3 = slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, o, inv, tcull, h3);
+            }
+            if (STATS) ++nv;
             int32_t k0 = __float_as_int(cc.x), k1 = __float_as_int(cc.y), k2 = __float_as_int(cc.z),
                     k3 = __float_as_int(cc.w);
             h0 = h0 && k0 != kEmpty;
@@ -1453,9 +1527,16 @@ int trace_grid_blocks(int waves_per_cu) {
     return g;
 }
 
+int trace_max_kind(const DevScene& sc) {
+    if (!sc.wide) return kTraceChildPair;
+    if (sc.ntri > kQTriMask + 1u) return kTraceWide;
+    return sc.quant ? kTraceWideQueueQ : kTraceWideQueue;
+}
+
 int trace_kind(const DevScene& sc) {
     if (!(kPreferWide && sc.wide)) return kTraceChildPair;
-    return (kLeafQueue && sc.ntri <= kQTriMask + 1u) ? kTraceWideQueue : kTraceWide;
+    if (!(kLeafQueue && sc.ntri <= kQTriMask + 1u)) return kTraceWide;
+    return (kQuantized && sc.quant) ? kTraceWideQueueQ : kTraceWideQueue;
 }
 
 hipError_t launch_trace(const DevScene& sc, const TraceArgs& a, bool stats, hipStream_t st) {
@@ -1463,13 +1544,19 @@ hipError_t launch_trace(const DevScene& sc, const TraceArgs& a, bool stats, hipS
     const uint32_t gthreads = (uint32_t)g * kTraceBlock;
     if (a.refill < 1 || a.refill > 64) return hipErrorInvalidValue;
     const StepJob* none = nullptr;
-    if (a.kind > trace_kind(sc)) return hipErrorInvalidValue;
+    if (a.kind > trace_max_kind(sc)) return hipErrorInvalidValue;
     switch (a.kind >= 0 ? a.kind : trace_kind(sc)) {
+    case kTraceWideQueueQ:
+        if (stats)
+            hipLaunchKernelGGL((k_trace_q<true, false, true>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+        else
+            hipLaunchKernelGGL((k_trace_q<false, false, true>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+        break;
     case kTraceWideQueue:
         if (stats)
-            hipLaunchKernelGGL((k_trace_q<true, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+            hipLaunchKernelGGL((k_trace_q<true, false, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
         else
-            hipLaunchKernelGGL((k_trace_q<false, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
+            hipLaunchKernelGGL((k_trace_q<false, false, false>), dim3(g), dim3(kTraceBlock), 0, st, sc, a, gthreads, none, 0);
         break;
     case kTraceWide:
         if (stats)
@@ -1491,8 +1578,10 @@ hipError_t launch_trace_multi(const StepJob* jobs, int njobs, const TraceArgs& a
     const uint32_t gthreads = (uint32_t)g * kTraceBlock;
     if (a.refill < 1 || a.refill > 64 || njobs < 1) return hipErrorInvalidValue;
     DevScene none{};
-    if (kind == kTraceWideQueue)
-        hipLaunchKernelGGL((k_trace_q<false, true>), dim3(g), dim3(kTraceBlock), 0, st, none, a, gthreads, jobs, njobs);
+    if (kind == kTraceWideQueueQ)
+        hipLaunchKernelGGL((k_trace_q<false, true, true>), dim3(g), dim3(kTraceBlock), 0, st, none, a, gthreads, jobs, njobs);
+    else if (kind == kTraceWideQueue)
+        hipLaunchKernelGGL((k_trace_q<false, true, false>), dim3(g), dim3(kTraceBlock), 0, st, none, a, gthreads, jobs, njobs);
     else if (kind == kTraceWide)
         hipLaunchKernelGGL((k_trace<false, true, true>), dim3(g), dim3(kTraceBlock), 0, st, none, a, gthreads, jobs, njobs);
     else

@@ -302,6 +302,47 @@ def test_bvh4_valid(L, fn):
     L.pt_scene_free(h)
 
 
+@pytest.mark.parametrize("fn,sample", [(scenes.tiny, None), (scenes.furnace, None), (scenes.mixed_small, 400),
+                                       (scenes.mid, 300)])
+def test_bvh4_quantized_boxes_enclose(L, fn, sample):
+    """Quantized four-wide nodes: same codes as the four-wide nodes, and in exact
+    arithmetic every child's quantized box p + q * 2^e encloses its float box; steps fit
+    in a byte and exponents stay at or above -100 (so 2^e * inv stays a normal float)."""
+    from fractions import Fraction
+    s = fn()
+    st, h, keep = _create(L, s)
+    assert st == 0
+    info, raw = _bvh4(L, h)
+    q = np.zeros((max(info.nnodes4, 1), 16), np.uint32)
+    assert L.pt_scene_export_bvh4q(h, q.ctypes.data) == 0
+    q = q[: info.nnodes4]
+    assert info.quant == 1
+    assert np.array_equal(q[:, 4:8], raw[:, 24:28].view(np.uint32))
+    boxes = raw[:, :24].reshape(-1, 6, 4).astype(np.float64)
+    EMPTY = np.iinfo(np.int32).min
+    codes = raw[:, 24:28].view(np.int32)
+    idx = np.arange(len(q)) if sample is None else np.random.default_rng(5).choice(len(q), sample, replace=False)
+    checked = 0
+    for ni in idx:
+        p = q[ni, :3].view(np.float32).astype(np.float64)
+        e = [int(np.int8(np.uint8((int(q[ni, 3]) >> (8 * a)) & 0xFF))) for a in range(3)]
+        assert all(-100 <= x <= 127 for x in e)
+        for c in range(4):
+            planes = [(int(q[ni, 8 + 2 * a]) >> (8 * c)) & 0xFF for a in range(3)] + \
+                     [(int(q[ni, 9 + 2 * a]) >> (8 * c)) & 0xFF for a in range(3)]
+            if int(codes[ni, c]) == EMPTY:
+                assert planes[:3] == [255] * 3 and planes[3:] == [0] * 3
+                continue
+            for a in range(3):
+                step = Fraction(2) ** e[a]
+                qlo = Fraction(p[a]) + planes[a] * step
+                qhi = Fraction(p[a]) + planes[3 + a] * step
+                assert qlo <= Fraction(boxes[ni, 2 * a, c]) and qhi >= Fraction(boxes[ni, 2 * a + 1, c])
+                checked += 1
+    assert checked > 0
+    L.pt_scene_free(h)
+
+
 def test_bvh4_empty_and_single_leaf(L):
     s = scenes.tiny()
     one = dict(s)

@@ -96,7 +96,8 @@ def test_batch_stepped_with_staggered_arrivals_equals_alone(env):
         _same(torch, refs[i], outs[i], spec)
 
 
-@pytest.mark.parametrize("use_graph,traversal", [(False, "auto"), (True, "auto"), (False, "pair"), (True, "wide")])
+@pytest.mark.parametrize("use_graph,traversal", [(False, "auto"), (True, "auto"), (False, "pair"), (True, "wide"),
+                                                (False, "queue")])
 def test_batch_static_run_equals_alone(env, use_graph, traversal):
     torch, api, sc = env
     refs = [_alone(torch, api, sc, spec) for spec in JOBS]

@@ -265,7 +265,7 @@ def test_workspace_too_small_is_enomem(api, torch_dev):
 
 
 # ------------------------------------------------------------------ every traversal kernel
-@pytest.mark.parametrize("traversal", ["pair", "wide", "queue"])
+@pytest.mark.parametrize("traversal", ["pair", "wide", "queue", "quant"])
 @pytest.mark.parametrize("mode,nee,refill,leaf_gate", [("incoherent", False, 0, 0), ("reuse", False, 1, 1),
                                                        ("sorted", False, 64, 64), ("reuse", True, 16, 33),
                                                        ("incoherent", True, 48, 8)])
@@ -286,13 +286,13 @@ def test_traversal_kind_out_of_range_is_einval(api, orc, torch_dev):
     from paper_2310_07182_amd import capi
     s, sc, osc = both(api, orc, "tiny")
     with pytest.raises(capi.PtError) as e:
-        api.render(sc, 16, 16, 1, 1, "reuse", (4, 4), 2, None, 1, traversal=4)
+        api.render(sc, 16, 16, 1, 1, "reuse", (4, 4), 2, None, 1, traversal=5)
     assert e.value.status == capi.PT_EINVAL
 
 
 # ------------------------------------------------------------------ full-size workload, sampled tiles
 @pytest.mark.parametrize("mode,traversal", [("reuse", "auto"), ("incoherent", "auto"), ("sorted", "auto"),
-                                            ("reuse", "pair"), ("sorted", "wide")])
+                                            ("reuse", "pair"), ("sorted", "wide"), ("incoherent", "queue")])
 def test_indoor_full_size_sampled_tiles(api, orc, torch_dev, mode, traversal):
     s, sc, osc = both(api, orc, "indoor")
     cfg = scenes.CONFIGS["indoor"]
