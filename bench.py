@@ -619,7 +619,7 @@ def main():
         "p99_frame_ms": round(head["frame_ms_p99"], 4),
         "roofline": {"bound": "alu", "achieved": round(achieved_ops, 3), "peak": round(VALU_PEAK_TOPS, 2),
                      "unit": "TFLOP/s", "frac": round(achieved_ops / VALU_PEAK_TOPS, 4), "traffic": measured_traffic(head["mode"], args.config),
-                     "kernel": kernel_label(scene) + ", secondary bounces",
+                     "kernel": kernel_label(sc) + ", secondary bounces",
                      "op": "32-bit VALU lane operation (compare/min/max/select counted like add/mul)",
                      "ops_per_ray": round(head["ops_per_ray"], 1),
                      "algorithmic_bytes_per_ray": round(head["bytes_per_ray"], 1),
