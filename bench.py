@@ -53,7 +53,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_trace_{config}_1080p.md")
 KERNEL_SOURCES = ("paper_2310_07182_amd/csrc/kernels.hip", "paper_2310_07182_amd/csrc/kernels.h",
-                  "paper_2310_07182_amd/build.py")
+                  "paper_2310_07182_amd/csrc/capi.hip", "paper_2310_07182_amd/build.py")
 
 
 def measured_traffic(mode, config):

@@ -18,8 +18,8 @@ time of the caller's unit of work (a frame, or a whole batch).
 from __future__ import annotations
 
 GROUPS = (((4, 4), 2), ((8, 8), 2), ((8, 8), 4), ((8, 8), 8), ((16, 8), 16), ((16, 16), 32))
-WAVES_PER_CU = (16, 24, 32)
-REFILLS = (32, 40, 48, 56)
+WAVES_PER_CU = (16, 20, 24)
+REFILLS = (8, 12, 16, 24, 32, 48)
 LEAF_GATES = (4, 6, 8, 12, 16)
 MAX_GROUP_FRACTION = 8      # K <= W*H / 8
 
@@ -63,7 +63,7 @@ def search_space(mode, groups=GROUPS, waves=WAVES_PER_CU, refills=REFILLS, leaf_
     return dims
 
 
-DEFAULT = dict(group=((8, 8), 8), waves_per_cu=24, refill=48, leaf_gate=8)
+DEFAULT = dict(group=((8, 8), 8), waves_per_cu=24, refill=16, leaf_gate=8)
 
 
 def _median_ms(run, reps):

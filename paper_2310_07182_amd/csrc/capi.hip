@@ -104,7 +104,7 @@ bool is_sorted_mode(int mode) {
            mode == PT_MODE_SORTED_AILA;
 }
 
-constexpr int kDefaultRefill = 48;
+constexpr int kDefaultRefill = 16;
 
 bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
