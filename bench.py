@@ -77,21 +77,29 @@ def measured_traffic(mode, config):
     return None
 
 
-def kernel_label(sc):
+def traversal_kind(sc, trav="auto"):
+    """The traversal kernel that runs: the one asked for, else the one the library picks."""
+    if trav != "auto":
+        return trav
     inf = sc.info()
-    if inf["wide"] and inf["quant"] and inf["ntri"] <= (1 << 26):
-        return "k_trace_q (closest hit over quantized four-wide nodes, per-wave triangle-test queue)"
     if inf["wide"] and inf["ntri"] <= (1 << 26):
-        return "k_trace_q (closest hit over four-wide nodes, per-wave triangle-test queue)"
-    return "k_trace (closest hit, " + ("four-wide" if inf["wide"] else "child-pair") + " nodes)"
+        return "quant" if inf["quant"] else "queue"
+    return "wide" if inf["wide"] else "pair"
 
 
-def node_costs(sc):
-    """(bytes, ops) of one node visit of the traversal kernel the library picks for the scene."""
-    inf = sc.info()
-    if inf["wide"] and inf["quant"] and inf["ntri"] <= (1 << 26):
+def kernel_label(sc, trav="auto"):
+    return {"quant": "k_trace_q (closest hit over quantized four-wide nodes, per-wave triangle-test queue)",
+            "queue": "k_trace_q (closest hit over four-wide nodes, per-wave triangle-test queue)",
+            "wide": "k_trace (closest hit over four-wide nodes)",
+            "pair": "k_trace (closest hit over child-pair nodes)"}[traversal_kind(sc, trav)]
+
+
+def node_costs(sc, trav="auto"):
+    """(bytes, ops) of one node visit of the traversal kernel that runs."""
+    k = traversal_kind(sc, trav)
+    if k == "quant":
         return NODE4Q_BYTES, OPS_PER_NODE4Q
-    if inf["wide"]:
+    if k in ("queue", "wide"):
         return NODE4_BYTES, OPS_PER_NODE4
     return NODE_BYTES, OPS_PER_NODE
 
@@ -100,10 +108,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bench_mode(api, sc, cfg, mode, steps, warmup, seed0, nee=False):
+def bench_mode(api, sc, cfg, mode, steps, warmup, seed0, nee=False, trav="auto"):
     import torch
-    node_bytes, ops_node = node_costs(sc)
-    rc = api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], mode, tuple(cfg["tile"]), cfg["k"], nee=nee)
+    node_bytes, ops_node = node_costs(sc, trav)
+    rc = api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], mode, tuple(cfg["tile"]), cfg["k"], nee=nee,
+                          traversal=trav)
     # untimed counting frame: nodes / triangles per ray and rays per bounce
     rs = api.Renderer(sc, rc, stats=True)
     rs.render(seed0)
@@ -487,6 +496,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="indoor")
     ap.add_argument("--modes", default="reuse,incoherent,sorted")
+    ap.add_argument("--traversal", default="auto", choices=["auto", "pair", "wide", "queue", "quant"],
+                    help="traversal kernel of the frame runs (pt_group.traversal); auto = the library's choice")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--profile", action="store_true",
@@ -560,7 +571,7 @@ def main():
     if args.profile:
         for i, mode in enumerate(args.modes.split(",")):
             r = api.Renderer(sc, api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], mode, tuple(cfg["tile"]),
-                                                  cfg["k"]))
+                                                  cfg["k"], traversal=args.traversal))
             for j in range(3):
                 r.render(2310071821 + 10 * i + j)
                 torch.cuda.synchronize()
@@ -575,7 +586,8 @@ def main():
     results = {}
     for i, mode in enumerate(args.modes.split(",")):
         log(f"[bench] mode {mode}: warmup {args.warmup}, steps {args.steps}")
-        results[mode] = bench_mode(api, sc, cfg, mode, args.steps, args.warmup, 2310071821 + 100000 * i, args.nee)
+        results[mode] = bench_mode(api, sc, cfg, mode, args.steps, args.warmup, 2310071821 + 100000 * i, args.nee,
+                                   args.traversal)
         log(f"[bench] {mode}: {json.dumps(results[mode])}")
     head = results.get("reuse") or next(iter(results.values()))
     log("[bench] memory ceilings")
@@ -607,7 +619,8 @@ def main():
         "data": "synthetic (seeded procedural scene standing in for the paper's archived scenes)",
         "config": {"workload": f"{args.config}: {cfg['w']}x{cfg['h']}, 1 spp, {cfg['bounces']} bounces, "
                                f"{scene.ntri} triangles, tile {cfg['tile'][0]}x{cfg['tile'][1]}, K={cfg['k']}",
-                   "mode": head["mode"], "parallelism": "single GPU", "nee": bool(args.nee)},
+                   "mode": head["mode"], "parallelism": "single GPU", "nee": bool(args.nee),
+                   "traversal": traversal_kind(sc, args.traversal)},
         "modes": {m: {"secondary_mrays_s": round(v["secondary_mrays_s"], 3),
                       "end_to_end_secondary_mrays_s": round(v["end_to_end_secondary_mrays_s"], 3),
                       "frame_ms_p50": round(v["frame_ms_p50"], 4), "frame_ms_p99": round(v["frame_ms_p99"], 4),
@@ -618,8 +631,8 @@ def main():
                   for m, v in results.items()},
         "p99_frame_ms": round(head["frame_ms_p99"], 4),
         "roofline": {"bound": "alu", "achieved": round(achieved_ops, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                     "unit": "TFLOP/s", "frac": round(achieved_ops / VALU_PEAK_TOPS, 4), "traffic": measured_traffic(head["mode"], args.config),
-                     "kernel": kernel_label(sc) + ", secondary bounces",
+                     "unit": "TFLOP/s", "frac": round(achieved_ops / VALU_PEAK_TOPS, 4), "traffic": measured_traffic(head["mode"], args.config) if args.traversal == "auto" else None,
+                     "kernel": kernel_label(sc, args.traversal) + ", secondary bounces",
                      "op": "32-bit VALU lane operation (compare/min/max/select counted like add/mul)",
                      "ops_per_ray": round(head["ops_per_ray"], 1),
                      "algorithmic_bytes_per_ray": round(head["bytes_per_ray"], 1),
