@@ -435,15 +435,15 @@ bool quantize_bvh4(const std::vector<Bvh4Node>& n4, std::vector<Bvh4QNode>& q) {
         o.px = lo[0];
         o.py = lo[1];
         o.pz = lo[2];
-        o.exps = (int32_t)(((uint32_t)(uint8_t)(int8_t)e[0]) | ((uint32_t)(uint8_t)(int8_t)e[1] << 8) |
-                           ((uint32_t)(uint8_t)(int8_t)e[2] << 16));
+        o.sx = std::ldexp(1.0f, e[0]);
+        o.sy = std::ldexp(1.0f, e[1]);
+        o.sz = std::ldexp(1.0f, e[2]);
         o.qlx = ql[0];
         o.qhx = qh[0];
         o.qly = ql[1];
         o.qhy = qh[1];
         o.qlz = ql[2];
         o.qhz = qh[2];
-        o.pad0 = o.pad1 = 0;
     }
     return ok;
 }

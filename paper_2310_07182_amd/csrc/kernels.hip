@@ -600,14 +600,14 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
 // when no lane can walk on.  Owners re-read their key after every block to cull against
 // it.  Culling prunes only, and every queued triangle is tested, so the result is the
 // exact (t, prim id) minimum, as in k_trace.
-// Slab tests of the four children of a quantized node (p, exponents in g; child planes
-// in q0 = {lo x, hi x, lo y, hi y}, q1 = {lo z, hi z}, one byte per child).  Along an axis,
-// the distance to plane p + q * 2^e is t = q * a + b with a = 2^e * inv (exact) and
-// b = (p - o) * inv (two roundings).  b is moved by 2^-21 |b| (more than the 2.01 ulp its
-// roundings can be off, plus the rounding of the move) toward the near side for near planes
-// and the far side for far planes, so that the single rounding of the fused q * a + b is
-// the only error left, relative to t, which the far-distance widening of the child-pair
-// test covers.  Near and far planes are chosen by the sign of inv.  A direction component
+// Slab tests of the four children of a quantized node (g = {p, step x}; child planes in
+// q0 = {lo x, hi x, lo y, hi y}, q1 = {lo z, hi z, step y, step z}, one byte per child).
+// Along an axis, the distance to plane p + q * 2^e is t = q * a + b with a = 2^e * inv
+// (exact) and b = (p - o) * inv (two roundings).  b is moved by 2^-21 |b| (more than the
+// 2.01 ulp its roundings can be off, plus the rounding of the move, one fused operation)
+// toward the near side for near planes and the far side for far planes, so that the single
+// rounding of the fused q * a + b is the only error left, relative to t, which the
+// far-distance widening of the child-pair test covers.  Near and far planes are chosen by the sign of inv.  A direction component
 // of zero gives infinities or NaN along that axis, which drop the axis from the min and
 // max below (never a wrong cull).  The fused multiply-add is used on purpose: this test
 // only prunes, and every result stays the exact (t, prim id) minimum.
@@ -619,22 +619,17 @@ constexpr float kQSlack = 0x1p-21f;
 // 2^e * inv stays finite below this bound.
 constexpr float kQMaxInv = 0x1p64f;
 
-__device__ __forceinline__ float qexp2(int32_t exps, int shift) {
-    const int e = (int)(int8_t)(uint8_t)((uint32_t)exps >> shift);
-    return __int_as_float((e + 127) << 23);
-}
-
 __device__ __forceinline__ float qplane(uint32_t q, int j, float a, float b) {
     return fmaf((float)((q >> (8 * j)) & 0xFFu), a, b);
 }
 
 __device__ __forceinline__ void qslab4(float4 g, float4 q0, float4 q1, V3 o, V3 inv, float tcull, float& t0,
                                        float& t1, float& t2, float& t3, bool& h0, bool& h1, bool& h2, bool& h3) {
-    const int32_t exps = __float_as_int(g.w);
-    const float ax = qexp2(exps, 0) * inv.x, ay = qexp2(exps, 8) * inv.y, az = qexp2(exps, 16) * inv.z;
+    const float ax = g.w * inv.x, ay = q1.z * inv.y, az = q1.w * inv.z;
     const float bx = (g.x - o.x) * inv.x, by = (g.y - o.y) * inv.y, bz = (g.z - o.z) * inv.z;
-    const float sx = fabsf(bx) * kQSlack, sy = fabsf(by) * kQSlack, sz = fabsf(bz) * kQSlack;
-    const float nbx = bx - sx, fbx = bx + sx, nby = by - sy, fby = by + sy, nbz = bz - sz, fbz = bz + sz;
+    const float nbx = fmaf(fabsf(bx), -kQSlack, bx), fbx = fmaf(fabsf(bx), kQSlack, bx);
+    const float nby = fmaf(fabsf(by), -kQSlack, by), fby = fmaf(fabsf(by), kQSlack, by);
+    const float nbz = fmaf(fabsf(bz), -kQSlack, bz), fbz = fmaf(fabsf(bz), kQSlack, bz);
     const bool px = inv.x >= 0.0f, py = inv.y >= 0.0f, pz = inv.z >= 0.0f;
     const uint32_t nqx = __float_as_uint(px ? q0.x : q0.y), fqx = __float_as_uint(px ? q0.y : q0.x);
     const uint32_t nqy = __float_as_uint(py ? q0.z : q0.w), fqy = __float_as_uint(py ? q0.w : q0.z);

@@ -37,16 +37,19 @@ struct Bvh4Node {
 };
 static_assert(sizeof(Bvh4Node) == 128, "node size");
 
+constexpr int kQMaxExp = 60;
+
 // Quantized four-wide node, 64 bytes: the child boxes of the four-wide node of the same
 // index as 8-bit steps of 2^e (one e per axis) above the node's lower corner p, rounded
 // outward so that, in exact arithmetic, p + q * 2^e encloses every child box (8-bit child
 // boxes relative to the parent, after Ylitie, Karras and Laine, HPG 2017).
 struct Bvh4QNode {
     float px, py, pz;          // grid origin: the lower corner of the node's box
-    int32_t exps;              // e_x | e_y << 8 | e_z << 16, each a signed byte, e >= -100
+    float sx;                  // step along x: 2^e_x, -100 <= e_x <= kQMaxExp
     int32_t c[4];              // child codes as in Bvh4Node
     uint32_t qlx, qhx, qly, qhy;   // byte j: child j's lower / upper plane in steps
-    uint32_t qlz, qhz, pad0, pad1; // an empty child has lower 255, upper 0
+    uint32_t qlz, qhz;             // an empty child has lower 255, upper 0
+    float sy, sz;              // steps along y and z
 };
 static_assert(sizeof(Bvh4QNode) == 64, "node size");
 
@@ -69,7 +72,6 @@ void collapse_bvh4(const std::vector<BvhNode>& n2, std::vector<Bvh4Node>& n4, ui
 
 // Quantizes the child boxes of the four-wide nodes (same order, same codes); returns false
 // when some node needs a step above 2^kQMaxExp (its nodes are then not to be used).
-constexpr int kQMaxExp = 60;
 bool quantize_bvh4(const std::vector<Bvh4Node>& n4, std::vector<Bvh4QNode>& q);
 
 // Binned-SAH build over the triangles (host, multi-threaded, deterministic output).

@@ -306,8 +306,8 @@ def test_bvh4_valid(L, fn):
                                        (scenes.mid, 300)])
 def test_bvh4_quantized_boxes_enclose(L, fn, sample):
     """Quantized four-wide nodes: same codes as the four-wide nodes, and in exact
-    arithmetic every child's quantized box p + q * 2^e encloses its float box; steps fit
-    in a byte and exponents stay at or above -100 (so 2^e * inv stays a normal float)."""
+    arithmetic every child's quantized box p + q * 2^e encloses its float box; the steps
+    are powers of two 2^e with -100 <= e <= 60 (so 2^e * inv stays a finite normal float)."""
     from fractions import Fraction
     s = fn()
     st, h, keep = _create(L, s)
@@ -325,8 +325,9 @@ def test_bvh4_quantized_boxes_enclose(L, fn, sample):
     checked = 0
     for ni in idx:
         p = q[ni, :3].view(np.float32).astype(np.float64)
-        e = [int(np.int8(np.uint8((int(q[ni, 3]) >> (8 * a)) & 0xFF))) for a in range(3)]
-        assert all(-100 <= x <= 127 for x in e)
+        steps = q[ni, [3, 14, 15]].view(np.float32).astype(np.float64)
+        e = [int(np.log2(x)) for x in steps]
+        assert all(-100 <= x <= 60 and 2.0 ** x == st for x, st in zip(e, steps))
         for c in range(4):
             planes = [(int(q[ni, 8 + 2 * a]) >> (8 * c)) & 0xFF for a in range(3)] + \
                      [(int(q[ni, 9 + 2 * a]) >> (8 * c)) & 0xFF for a in range(3)]
