@@ -569,6 +569,14 @@ def main():
         print(json.dumps(line), flush=True)
         return
     if args.profile:
+        # warm the GPU up (clocks, caches) with 20 untimed frames before the profiled sequence
+        rw = api.Renderer(sc, api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], "incoherent", tuple(cfg["tile"]),
+                                               cfg["k"], traversal=args.traversal))
+        for j in range(20):
+            rw.render(7 + j)
+        torch.cuda.synchronize()
+        del rw
+        log("[profile] 20 warm-up frames")
         for i, mode in enumerate(args.modes.split(",")):
             r = api.Renderer(sc, api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], mode, tuple(cfg["tile"]),
                                                   cfg["k"], traversal=args.traversal))
@@ -583,6 +591,14 @@ def main():
         torch.cuda.synchronize()
         log("[profile] copy of 1 GiB done")
         return
+    # the same untimed warm-up before every mode's own warm-up, so the first mode does not meet
+    # a GPU whose clocks are still ramping up
+    rw = api.Renderer(sc, api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], "incoherent", tuple(cfg["tile"]),
+                                           cfg["k"], traversal=args.traversal))
+    for j in range(20):
+        rw.render(7 + j)
+    torch.cuda.synchronize()
+    del rw
     results = {}
     for i, mode in enumerate(args.modes.split(",")):
         log(f"[bench] mode {mode}: warmup {args.warmup}, steps {args.steps}")

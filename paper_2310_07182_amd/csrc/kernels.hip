@@ -316,7 +316,11 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
         // ---- refill idle lanes with the next rays of the queue
         const unsigned long long idle = __ballot(!have);
         if (!exhausted && idle != 0 && (__popcll(idle) >= a.refill || idle == ~0ull)) {
-            const uint32_t need = (uint32_t)__popcll(idle);
+            // a launch with few rays spreads them over every wave (latency hiding) instead of
+            // filling the first waves' 64 lanes and leaving the others without work
+            const uint32_t share = n / gridDim.x + 1u;
+            const uint32_t nidle = (uint32_t)__popcll(idle);
+            const uint32_t need = nidle < share ? nidle : share;
             const uint32_t c = cq;
             uint32_t base = 0;
             if (lane == 0) base = atomicAdd(a.work + c * kCounterStride, need);
@@ -325,8 +329,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
                 if (++tries == kRayCounters) exhausted = true;
                 cq = (cq + 1u) % kRayCounters;
             }
-            if (!have) {
-                const uint64_t i64 = claimed_ray(base + (uint32_t)__popcll(idle & lt), c);
+            const uint32_t rank = (uint32_t)__popcll(idle & lt);
+            if (!have && rank < need) {
+                const uint64_t i64 = claimed_ray(base + rank, c);
                 const uint32_t i = (uint32_t)i64;
                 if (i64 < n) {
                     const float4* rays = a.rays;
@@ -656,6 +661,7 @@ __device__ __forceinline__ void qslab4(float4 g, float4 q0, float4 q1, V3 o, V3 
 }
 
 constexpr int kLeafQ = 512;                    // ring entries per wave
+constexpr uint32_t kFlushPerWalker = 4;        // queued tests per walking lane that trigger a partial block
 constexpr uint32_t kQTriBits = 26;             // triangle index bits of an entry; the lane sits above
 constexpr uint32_t kQTriMask = (1u << kQTriBits) - 1u;
 static_assert(kLeafQ >= 2 * kTraceBlock + kTraceBlock * kMaxLeaf, "one step appends at most 64 leaves");
@@ -701,7 +707,11 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
         // ---- refill idle lanes with the next rays of the queue
         const unsigned long long idle = __ballot(!have);
         if (!exhausted && idle != 0 && (__popcll(idle) >= a.refill || idle == ~0ull)) {
-            const uint32_t need = (uint32_t)__popcll(idle);
+            // a launch with few rays spreads them over every wave (latency hiding) instead of
+            // filling the first waves' 64 lanes and leaving the others without work
+            const uint32_t share = n / gridDim.x + 1u;
+            const uint32_t nidle = (uint32_t)__popcll(idle);
+            const uint32_t need = nidle < share ? nidle : share;
             const uint32_t c = cq;
             uint32_t base = 0;
             if (lane == 0) base = atomicAdd(a.work + c * kCounterStride, need);
@@ -710,8 +720,9 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
                 if (++tries == kRayCounters) exhausted = true;
                 cq = (cq + 1u) % kRayCounters;
             }
-            if (!have) {
-                const uint64_t i64 = claimed_ray(base + (uint32_t)__popcll(idle & lt), c);
+            const uint32_t rank = (uint32_t)__popcll(idle & lt);
+            if (!have && rank < need) {
+                const uint64_t i64 = claimed_ray(base + rank, c);
                 const uint32_t i = (uint32_t)i64;
                 if (i64 < n) {
                     const float4* rays = a.rays;
@@ -850,7 +861,11 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
         // ---- queued triangle tests: every whole block of 64, and a partial one when lanes wait on it
         const bool waiting = have && node == kDone && (int32_t)(last - qhead) >= 0;
         const int walking = __popcll(__ballot(have && node != kDone));
-        bool partial = qtail != qhead && (walking == 0 || __popcll(__ballot(waiting)) > a.leaf_gate);
+        // a partial block is tested when lanes wait on it, and when the queue holds kFlushPerWalker
+        // entries per walking lane: a wave with few walking rays would otherwise fill it slowly
+        // and walk on without culling against the hits it has queued
+        bool partial = qtail != qhead && (walking == 0 || __popcll(__ballot(waiting)) > a.leaf_gate ||
+                                          qtail - qhead >= kFlushPerWalker * (uint32_t)walking);
         if (qtail - qhead >= (uint32_t)kTraceBlock || partial) {
             const int perm = rp.kx | (rp.ky << 2) | (rp.kz << 4);
             __syncthreads();   // the entries written above are visible to every lane
