@@ -492,7 +492,7 @@ def bench_quality(api, sc, cfg, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="indoor")
     ap.add_argument("--modes", default="reuse,incoherent,sorted")
