@@ -73,6 +73,38 @@ def test_trace_parity_random_rays(api, orc, torch_dev, name, refill):
     assert np.array_equal(t[same].view(np.uint32), to[same].view(np.uint32))
 
 
+@pytest.mark.parametrize("name", ["tiny", "mixed_small"])
+def test_trace_parity_axis_aligned_rays(api, orc, torch_dev, name):
+    """Directions with one or two zero components (and components below 2^-64) take the
+    float boxes in the quantized traversal; results stay the exact closest hits."""
+    s, sc, osc = both(api, orc, name)
+    rng = np.random.default_rng(23)
+    tris = s["tris"].astype(np.float64)
+    lo, hi = tris.reshape(-1, 3).min(0), tris.reshape(-1, 3).max(0)
+    n = 12000
+    o = rng.uniform(lo, hi, (n, 3)).astype(np.float32)
+    d = rng.normal(size=(n, 3))
+    kind = np.arange(n) % 4
+    axis = rng.integers(0, 3, n)
+    d[kind == 0] = 0.0                                   # axis-aligned: two zero components
+    d[kind == 0, axis[kind == 0]] = rng.choice([-1.0, 1.0], (kind == 0).sum())
+    d[kind == 1, axis[kind == 1]] = 0.0                  # one zero component
+    d[kind == 2, axis[kind == 2]] = 1e-30                # one component below 2^-64
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    d[kind == 2, axis[kind == 2]] = np.float32(1e-30)
+    ex = np.full(n, -1, np.int32)
+    rays = orc.pack_rays(o, d, ex)
+    _say(f"[gpu] axis-aligned trace {name} n={n}")
+    prim, t = api.trace(sc, torch_dev.from_numpy(rays).cuda())
+    prim, t = prim.cpu().numpy(), t.cpu().numpy()
+    po, to, t2 = osc.trace(rays)
+    tie = (t2 - to) <= 1e-6 * to
+    assert np.all((prim == po) | tie)
+    same = prim == po
+    assert np.array_equal(t[same].view(np.uint32), to[same].view(np.uint32))
+    assert (po >= 0).sum() > n // 4
+
+
 def test_trace_empty_and_tiny_batches(api, orc, torch_dev):
     s, sc, osc = both(api, orc, "tiny")
     for n in (1, 63, 64, 65):
