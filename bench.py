@@ -114,11 +114,16 @@ def bench_mode(api, sc, cfg, mode, steps, warmup, seed0, nee=False, trav="auto")
     rc = api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], mode, tuple(cfg["tile"]), cfg["k"], nee=nee,
                           traversal=trav)
     # untimed counting frame: nodes / triangles per ray and rays per bounce
-    rs = api.Renderer(sc, rc, stats=True)
+    rs = api.Renderer(sc, rc, stats=True, touched=True)
     rs.render(seed0)
     torch.cuda.synchronize()
     stats = rs.stats.cpu().numpy().astype(np.float64)
     rays_stats = rs.ray_count.cpu().numpy().reshape(-1).astype(np.float64)
+    # compulsory bytes per bounce: the distinct nodes and triangles the bounce touched, plus
+    # each ray read and hit written once (a lower bound on the launch's memory traffic)
+    tn, tt = rs.touched_counts()
+    compulsory = [float(tn[b] * node_bytes + tt[b] * TRI_BYTES + rays_stats[b] * (RAY_BYTES + HIT_BYTES))
+                  for b in range(len(tn))]
     del rs
     timer = api.Timer(capacity=64 * (steps + warmup + 2))
     r = api.Renderer(sc, rc, timer=timer)
@@ -173,6 +178,8 @@ def bench_mode(api, sc, cfg, mode, steps, warmup, seed0, nee=False, trav="auto")
                 tris_per_ray=float(tris_per_ray), bytes_per_ray=float(bytes_per_ray),
                 avg_trace_launch_ms=float(avg_launch_ms), trace_launches=launches,
                 bytes_per_launch=float(bytes_per_launch), ops_per_ray=float(ops_per_ray),
+                compulsory_bytes_per_bounce=compulsory,
+                compulsory_bytes_per_launch=float(np.mean(compulsory[1:])) if len(compulsory) > 1 else 0.0,
                 ops_per_launch=float(ops_per_launch), ms_by_kind=kinds, **shadow)
 
 
@@ -641,6 +648,7 @@ def main():
                       "end_to_end_secondary_mrays_s": round(v["end_to_end_secondary_mrays_s"], 3),
                       "frame_ms_p50": round(v["frame_ms_p50"], 4), "frame_ms_p99": round(v["frame_ms_p99"], 4),
                       "rays_per_bounce": v["rays_per_bounce"], "nodes_per_ray": round(v["nodes_per_ray"], 2),
+                      "compulsory_bytes_per_bounce": [round(x) for x in v["compulsory_bytes_per_bounce"]],
                       "tris_per_ray": round(v["tris_per_ray"], 2),
                       **({"shadow_mrays_s": round(v["shadow_mrays_s"], 3),
                           "shadow_rays_per_frame": v["shadow_rays_per_frame"]} if args.nee else {})}
@@ -652,6 +660,8 @@ def main():
                      "op": "32-bit VALU lane operation (compare/min/max/select counted like add/mul)",
                      "ops_per_ray": round(head["ops_per_ray"], 1),
                      "algorithmic_bytes_per_ray": round(head["bytes_per_ray"], 1),
+                     "algorithmic_bytes_per_launch": round(head["bytes_per_launch"]),
+                     "compulsory_bytes_per_launch": round(head["compulsory_bytes_per_launch"]),
                      "algorithmic_GBps": round(achieved_gbs, 1), "hbm_peak_GBps": HBM_PEAK_GBS,
                      "working_set_level": level, "measured_ceiling_GBps": ceil[level]["read_GBps"],
                      "algorithmic_frac_of_measured_ceiling": round(achieved_gbs / ceil[level]["read_GBps"], 4)},

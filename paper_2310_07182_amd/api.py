@@ -160,7 +160,7 @@ class Renderer:
     """Holds the workspace and output tensors for repeated frames of one configuration."""
 
     def __init__(self, scene: Scene, cfg: RenderConfig, stats: bool = False, timer: Timer | None = None,
-                 rays: bool = False):
+                 rays: bool = False, touched: bool = False):
         self.scene = scene
         self.cfg = cfg
         dev = scene.device
@@ -180,6 +180,9 @@ class Renderer:
             self.ray_count = torch.empty((B + 1, cfg.spp), dtype=torch.int32, device=dev)
             self.shadow_count = torch.empty((B + 1, cfg.spp), dtype=torch.int32, device=dev) if cfg.nee else None
             self.stats = torch.empty((B + 1, 2), dtype=torch.int64, device=dev) if stats else None
+            inf = scene.info()
+            self.touched = (torch.zeros(inf["nnodes"] + inf["ntri"], dtype=torch.uint8, device=dev)
+                            if (stats and touched) else None)
             self.rays = torch.zeros((B + 1, cfg.spp, cfg.h, cfg.w, 8), dtype=torch.float32, device=dev) if rays else None
         self.timer = timer
         self.out = capi.Outputs()
@@ -191,6 +194,7 @@ class Renderer:
         self.out.rays = self.rays.data_ptr() if rays else None
         self.out.timer = timer.handle if timer is not None else None
         self.out.shadow_count = self.shadow_count.data_ptr() if cfg.nee else None
+        self.out.touched = self.touched.data_ptr() if self.touched is not None else None
 
     def render(self, seed: int = 1, camera: dict | None = None):
         cfg = self.cfg
@@ -211,7 +215,22 @@ class Renderer:
             r["rays"] = self.rays
         if self.shadow_count is not None:
             r["shadow_rays_per_bounce"] = self.shadow_count.sum(dim=1)
+        if self.touched is not None:
+            r["touched"] = self.touched
         return r
+
+    def touched_counts(self) -> tuple:
+        """Distinct nodes and triangles the traversal of each bounce b < 8 touched (sample 0) in
+        the frames rendered since the flags were cleared: two int arrays of length B + 1."""
+        assert self.touched is not None, "Renderer(..., stats=True, touched=True)"
+        nn = self.scene.info()["nnodes"]
+        B = self.cfg.bounces
+        t = self.touched.to(torch.int32)
+        bits = torch.tensor([1 << b for b in range(min(B + 1, 8))], dtype=torch.int32, device=t.device)
+        hit = (t[None, :] & bits[:, None]) != 0
+        nodes = hit[:, :nn].sum(dim=1).cpu().numpy()
+        tris = hit[:, nn:].sum(dim=1).cpu().numpy()
+        return nodes, tris
 
 
 def render(scene: Scene, w, h, spp=1, bounces=2, mode="incoherent", tile=(8, 8), k=8,

@@ -602,6 +602,11 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
             ta.out_t = out->hit_t + li * plane;
             ta.partial = out->ray_count ? partial + li * pt::kMaxTraceBlocks : nullptr;
             ta.stats = out->stats ? (unsigned long long*)(out->stats + 2 * (size_t)b) : nullptr;
+            if (out->stats && out->touched && b < 8 && s == 0) {
+                ta.touched = out->touched;
+                ta.touch_tri = (uint32_t)scene->bvh.nodes.size();
+                ta.touch_bit = 1u << b;
+            }
             ta.ovf = ovf;
             ta.by_pixel = 1;
             ta.refill = g.refill ? g.refill : kDefaultRefill;

@@ -74,6 +74,9 @@ struct TraceArgs {
     int shadow;                // shadow rays: blocked iff a triangle lies at 0 < t < kShadowTmax (units of d)
     int skip_empty;            // rays whose pixel word is kNoRay are skipped (not traced, no output)
     int kind;                  // traversal kernel (kTraceChildPair...), -1 = trace_kind of the scene
+    uint8_t* touched;          // optional (counting kernels): node flags, then triangle flags from touch_tri
+    uint32_t touch_tri;
+    uint32_t touch_bit;
 };
 
 // One job of a merged launch (batched rendering): the shade, raygen and trace launches of a

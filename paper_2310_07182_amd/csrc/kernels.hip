@@ -385,7 +385,10 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
                     // four children: nearest hit next, the other hits pushed far to near
                     const float4* nd = nodes4 + 8 * (size_t)node;
                     const float4 lx = nd[0], hx = nd[1], ly = nd[2], hy = nd[3], lz = nd[4], hz = nd[5], cc = nd[6];
-                    if (STATS) ++nv;
+                    if (STATS) {
+                    ++nv;
+                    if (a.touched) a.touched[node] |= (uint8_t)a.touch_bit;
+                }
                     bool h0, h1, h2, h3;
                     float a0 = slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, o, inv, tcull, h0);
                     float a1 = slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, o, inv, tcull, h1);
@@ -435,7 +438,10 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
                 } else {
                     const float4* nd = nodes + 4 * (size_t)node;
                     const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
-                    if (STATS) ++nv;
+                    if (STATS) {
+                    ++nv;
+                    if (a.touched) a.touched[node] |= (uint8_t)a.touch_bit;
+                }
                     const int32_t c0 = __float_as_int(n3.x), c1 = __float_as_int(n3.y);
                     bool h0, h1;
                     const float t0 = slab(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, o, inv, tcull, h0);
@@ -546,7 +552,10 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
                     const float4* tp = qtris + 3 * (size_t)qtri;
                     const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
                     const int32_t id = __float_as_int(p0.w);
-                    if (STATS) ++nt;
+                    if (STATS) {
+                        ++nt;
+                        if (a.touched) a.touched[a.touch_tri + qtri] |= (uint8_t)a.touch_bit;
+                    }
                     float th;
                     if (tri_test(q, p0, p1, p2, th) && id != qexcl) {
                         t = th;
@@ -811,7 +820,10 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
                 a2 = slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, o, inv, tcull, h2);
                 a3 = slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, o, inv, tcull, h3);
             }
-            if (STATS) ++nv;
+            if (STATS) {
+                    ++nv;
+                    if (a.touched) a.touched[node] |= (uint8_t)a.touch_bit;
+                }
             int32_t k0 = __float_as_int(cc.x), k1 = __float_as_int(cc.y), k2 = __float_as_int(cc.z),
                     k3 = __float_as_int(cc.w);
             h0 = h0 && k0 != kEmpty;
@@ -896,7 +908,10 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
                     const float4* tp = qtris + 3 * (size_t)(e & kQTriMask);
                     const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
                     const int32_t id = __float_as_int(p0.w);
-                    if (STATS) ++nt;
+                    if (STATS) {
+                        ++nt;
+                        if (a.touched) a.touched[a.touch_tri + (e & kQTriMask)] |= (uint8_t)a.touch_bit;
+                    }
                     float th;
                     if (tri_test(r, p0, p1, p2, th) && id != qexcl) atomicMin(&bestk[src], hit_key(th, (uint32_t)id));
                 }

@@ -105,6 +105,34 @@ def test_trace_parity_axis_aligned_rays(api, orc, torch_dev, name):
     assert (po >= 0).sum() > n // 4
 
 
+@pytest.mark.parametrize("traversal", ["quant", "pair"])
+def test_touched_flags_cover_hits(api, orc, torch_dev, traversal):
+    """The counting frame's touched flags: every bounce touches the root, every hit
+    triangle of a bounce is among the triangles it touched, and distinct counts never
+    exceed the visit counts."""
+    s, sc, osc = both(api, orc, "mixed_small")
+    B = 3
+    rc = api.RenderConfig(83, 61, 1, B, "reuse", (8, 8), 8, traversal=traversal)
+    r = api.Renderer(sc, rc, stats=True, touched=True)
+    _say(f"[gpu] touched flags traversal={traversal}")
+    r.render(59)
+    torch_dev.cuda.synchronize()
+    nodes, tris = r.touched_counts()
+    st = r.stats.cpu().numpy()
+    hp = r.hit_prim.cpu().numpy()
+    touched = r.touched.cpu().numpy()
+    nn = sc.info()["nnodes"]
+    _, order = sc.export_bvh()
+    for b in range(B + 1):
+        if (hp[b] != -2).sum() == 0:
+            continue
+        assert touched[0] & (1 << b)
+        assert 0 < nodes[b] <= st[b, 0] and tris[b] <= st[b, 1]
+        tri_set = set(order[np.nonzero(touched[nn:] & (1 << b))[0]].tolist())
+        hits = set(hp[b][hp[b] >= 0].tolist())
+        assert hits <= tri_set
+
+
 def test_trace_empty_and_tiny_batches(api, orc, torch_dev):
     s, sc, osc = both(api, orc, "tiny")
     for n in (1, 63, 64, 65):
