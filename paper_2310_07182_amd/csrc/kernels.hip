@@ -657,7 +657,7 @@ __device__ __forceinline__ void qslab4(float4 g, float4 q0, float4 q1, V3 o, V3 
         const float f = fminf(fminf(qplane(fqx, j, ax, fbx), qplane(fqy, j, ay, fby)), qplane(fqz, j, az, fbz)) *
                         kFarScale;
         tn[j] = n;
-        hh[j] = n <= f && n <= tcull;
+        hh[j] = n <= fminf(f, tcull);   // f is never NaN here (flat directions take the float boxes)
     }
     t0 = tn[0];
     t1 = tn[1];
