@@ -344,6 +344,50 @@ def test_bvh4_quantized_boxes_enclose(L, fn, sample):
     L.pt_scene_free(h)
 
 
+def _shifted(s, offset, scale=1.0):
+    out = dict(s)
+    out["tris"] = np.ascontiguousarray((s["tris"].astype(np.float64) * scale + np.asarray(offset)).astype(np.float32))
+    return out
+
+
+def test_bvh4_quantized_far_from_origin(L):
+    """A scene far from the origin (coordinates ~1e6, boxes of ~1 m): quantized boxes still
+    enclose the float boxes exactly."""
+    from fractions import Fraction
+    s = _shifted(scenes.tiny(), (1.0e6, -3.0e5, 2.0e4))
+    st, h, keep = _create(L, s)
+    assert st == 0
+    info, raw = _bvh4(L, h)
+    assert info.quant == 1
+    q = np.zeros((max(info.nnodes4, 1), 16), np.uint32)
+    assert L.pt_scene_export_bvh4q(h, q.ctypes.data) == 0
+    boxes = raw[:, :24].reshape(-1, 6, 4).astype(np.float64)
+    codes = raw[:, 24:28].view(np.int32)
+    for ni in range(info.nnodes4):
+        p = q[ni, :3].view(np.float32).astype(np.float64)
+        steps = q[ni, [3, 14, 15]].view(np.float32).astype(np.float64)
+        for c in range(4):
+            if int(codes[ni, c]) == np.iinfo(np.int32).min:
+                continue
+            for a in range(3):
+                ql = (int(q[ni, 8 + 2 * a]) >> (8 * c)) & 0xFF
+                qh = (int(q[ni, 9 + 2 * a]) >> (8 * c)) & 0xFF
+                assert Fraction(p[a]) + ql * Fraction(steps[a]) <= Fraction(boxes[ni, 2 * a, c])
+                assert Fraction(p[a]) + qh * Fraction(steps[a]) >= Fraction(boxes[ni, 2 * a + 1, c])
+    L.pt_scene_free(h)
+
+
+def test_bvh4_quantized_refused_for_huge_extents(L):
+    """Extents that need steps above 2^60 (here ~1e25) make the quantized nodes unusable:
+    the scene reports quant = 0 (the library then walks the float four-wide nodes)."""
+    s = _shifted(scenes.tiny(), (0.0, 0.0, 0.0), scale=1.0e24)
+    st, h, keep = _create(L, s)
+    assert st == 0
+    info, raw = _bvh4(L, h)
+    assert info.quant == 0
+    L.pt_scene_free(h)
+
+
 def test_bvh4_empty_and_single_leaf(L):
     s = scenes.tiny()
     one = dict(s)
