@@ -610,10 +610,13 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
 // by cross-lane shuffles), and folds each hit into the owner's (t, prim id) minimum,
 // kept in LDS as one 64-bit key (t's bits above the prim id: both are non-negative, so
 // the integer order is the lexicographic one) by an LDS atomic minimum.  A partial block
-// is tested when `leaf_gate` + 1 lanes have finished walking and wait on queued tests, or
-// when no lane can walk on.  Owners re-read their key after every block to cull against
-// it.  Culling prunes only, and every queued triangle is tested, so the result is the
-// exact (t, prim id) minimum, as in k_trace.
+// is tested when `leaf_gate` + 1 lanes have finished walking and wait on queued tests,
+// when the queue holds kFlushPerWalker entries per walking lane, or when no lane can walk
+// on.  Owners re-read their key after every block to cull against it.  Culling prunes
+// only, and every queued triangle is tested, so the result is the exact (t, prim id)
+// minimum, as in k_trace.  Rays are claimed from the spread counters as in k_trace, each
+// claim at most the launch's even share per wave.
+
 // Slab tests of the four children of a quantized node (g = {p, step x}; child planes in
 // q0 = {lo x, hi x, lo y, hi y}, q1 = {lo z, hi z, step y, step z}, one byte per child).
 // Along an axis, the distance to plane p + q * 2^e is t = q * a + b with a = 2^e * inv
