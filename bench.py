@@ -627,6 +627,8 @@ def main():
         log(f"[bench] cpu baseline, all cores: {cpu}")
     achieved_ops = head["ops_per_launch"] / (head["avg_trace_launch_ms"] * 1e-3) / 1e12
     achieved_gbs = head["bytes_per_launch"] / (head["avg_trace_launch_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(head["mode"], args.config) if args.traversal == "auto" else None
+    traffic_gbs = traffic / (head["avg_trace_launch_ms"] * 1e-3) / 1e9 if traffic else None
     line = {
         "metric": "secondary Mrays/s (reuse vs incoherent vs sorted) + p99 frame latency",
         "value": round(head["secondary_mrays_s"], 3),
@@ -655,7 +657,7 @@ def main():
                   for m, v in results.items()},
         "p99_frame_ms": round(head["frame_ms_p99"], 4),
         "roofline": {"bound": "alu", "achieved": round(achieved_ops, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                     "unit": "TFLOP/s", "frac": round(achieved_ops / VALU_PEAK_TOPS, 4), "traffic": measured_traffic(head["mode"], args.config) if args.traversal == "auto" else None,
+                     "unit": "TFLOP/s", "frac": round(achieved_ops / VALU_PEAK_TOPS, 4), "traffic": traffic,
                      "kernel": kernel_label(sc, args.traversal) + ", secondary bounces",
                      "op": "32-bit VALU lane operation (compare/min/max/select counted like add/mul)",
                      "ops_per_ray": round(head["ops_per_ray"], 1),
@@ -664,7 +666,10 @@ def main():
                      "compulsory_bytes_per_launch": round(head["compulsory_bytes_per_launch"]),
                      "algorithmic_GBps": round(achieved_gbs, 1), "hbm_peak_GBps": HBM_PEAK_GBS,
                      "working_set_level": level, "measured_ceiling_GBps": ceil[level]["read_GBps"],
-                     "algorithmic_frac_of_measured_ceiling": round(achieved_gbs / ceil[level]["read_GBps"], 4)},
+                     "algorithmic_frac_of_measured_ceiling": round(achieved_gbs / ceil[level]["read_GBps"], 4),
+                     "traffic_GBps": round(traffic_gbs, 1) if traffic_gbs else None,
+                     "traffic_frac_of_measured_hbm_ceiling":
+                         round(traffic_gbs / ceil["hbm"]["read_GBps"], 4) if traffic_gbs else None},
         "ceilings": ceil,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample",
                                                                        "single_core_value", "single_core_sample")},
