@@ -9,9 +9,8 @@ Headline (value): secondary Mrays/s in reuse mode = rays traced at bounces
 library's stream), the definition of the paper's Table 1.  The same figure for
 the incoherent and sorted modes, end-to-end rates and p50/p99 frame latency
 are reported beside it.  The roofline object describes the traversal kernel:
-algorithmic operations and bytes per launch (nodes visited x 56 B read of the
-quantized four-wide nodes, 128 B of the float four-wide nodes, 64 B of child-pair
-nodes, + triangles tested x 48 B + 32 B ray + 8 B hit, per ray, counted by the
+algorithmic operations and bytes per launch (nodes visited x 64 B of the quantized
+four-wide nodes, 128 B of the float four-wide nodes, 64 B of child-pair nodes, + triangles tested x 48 B + 32 B ray + 8 B hit, per ray, counted by the
 counting variant of the kernel in an untimed frame) divided by its average launch
 time.
 """
@@ -40,12 +39,12 @@ OPS_PER_NODE, OPS_PER_TRI = 58, 74
 # a four-wide node visit: four slab tests (4 x 26), the five compare-exchanges of the sorting
 # network on (distance, code) (5 x 5) and ~8 for the pushes and the choice of the next node
 OPS_PER_NODE4, NODE4_BYTES = 137, 128
-# a quantized four-wide node visit: per node the three steps 2^e (4 ops each), a = 2^e / d
-# (3 mul), b = (p - o) / d (3 sub, 3 mul), the moved b for near and far planes (3 mul, 6 add)
-# and the choice of near/far plane bytes by the ray's signs (3 cmp, 6 select) = 39; per child
-# 6 byte conversions, 6 fused multiply-adds, 3 max, 2 min, 1 mul, 2 cmp, 1 and = 21; then
-# the sorting network (25) and the pushes (8).  Bytes read: 56 of the 64-byte node.
-OPS_PER_NODE4Q, NODE4Q_BYTES = 156, 56
+# a quantized four-wide node visit: per node a = step / d (3 mul), b = (p - o) / d (3 sub,
+# 3 mul), b moved outward for near and far planes (6 fused multiply-adds) and the choice of
+# near/far plane bytes by the ray's signs (3 cmp, 6 select) = 24; per child 6 byte
+# conversions, 6 fused multiply-adds, 3 max, 2 min, 1 mul, the cull min and 1 cmp = 20; then
+# the sorting network (25) and the pushes (8).  Bytes read: the whole 64-byte node.
+OPS_PER_NODE4Q, NODE4Q_BYTES = 137, 64
 # MI355X vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit op per lane and cycle
 # (no packed FP32, an FMA counted once) = 39.3 T ops/s.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
