@@ -10,7 +10,11 @@ import os
 
 import numpy as np
 
-from .build import LIB, build
+from .build import LIB as _BUILT_LIB, build
+
+# PT_ORACLE_LIB names another build of the oracle (the mutation test loads
+# deliberately broken copies this way); default: the library oracle/build.py makes
+LIB = os.environ.get("PT_ORACLE_LIB") or _BUILT_LIB
 
 MODE = {"incoherent": 0, "sorted": 1, "reuse": 2, "sorted_origin": 3, "sorted_reis": 4, "sorted_aila": 5,
         "reuse_plain": 6, "reuse_world": 7}
@@ -48,6 +52,8 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB):
+            if LIB != _BUILT_LIB:
+                raise FileNotFoundError(LIB)
             build()
         L = C.CDLL(LIB)
         vp, u32, i32, f = C.c_void_p, C.c_uint32, C.c_int, C.c_float
@@ -137,7 +143,7 @@ class OracleScene:
         return prim, t
 
     def render(self, w, h, spp, bounces, mode="incoherent", tile=(8, 8), k=8, reuse_max_bounce=None,
-               seed=1, tile_mask=None, debug=False, camera=None, nee=False):
+               seed=1, tile_mask=None, debug=False, camera=None, nee=False, rays=False):
         cam = camera_struct(camera or self.scene["camera"])
         B = int(bounces)
         if reuse_max_bounce is None:
@@ -160,6 +166,10 @@ class OracleScene:
             rays = np.zeros((B + 1, spp, h, w, 8), np.float32)
             out.dbg_q, out.dbg_flags, out.dbg_keys, out.rays = _p(q), _p(fl), _p(keys), _p(rays)
             res.update(dbg_q=q[:B], dbg_flags=fl[:B], dbg_keys=keys[:B], rays=rays)
+        elif rays:
+            rr = np.zeros((B + 1, spp, h, w, 8), np.float32)
+            out.rays = _p(rr)
+            res.update(rays=rr)
         mask = None
         if tile_mask is not None:
             mask = np.ascontiguousarray(tile_mask, dtype=np.uint8)

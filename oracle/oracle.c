@@ -608,6 +608,8 @@ static v3 to_world(v3 q, v3 T, v3 B, v3 n)
  * GGX: Walter et al. 2007 normal sampling, Smith G, Schlick F.
  *   Pin: mean weight equals the quadrature of the reflectance integral.
  * Mirror: reflection about the normal; weight = albedo.
+ *   Pin: the next ray of every mirror hit of a frame equals d - 2 (d.n) n in
+ *   float64 world space; an open mirror floor returns albedo * L_env exactly.
  * ---------------------------------------------------------------------- */
 static v3 sample_lambert(float u2, float u3)
 {
@@ -669,7 +671,8 @@ int orc_sample_ggx(const float wi[3], float alpha, const float f0[3], float u2, 
  * screen order, the numbers are shuffled by the affine congruence
  * s(i) = (a*i + c) mod WH (a odd, so a bijection because WH is a power of
  * two), and pixels whose shuffled numbers share the quotient by K form a group.
- * Pin: bijection, exactly K members per full-tile group (test).
+ * Pin: bijection, exactly K members per full-tile group, every pixel's slot
+ * equal to the shuffle recomputed from the tile draw in the test.
  * ---------------------------------------------------------------------- */
 static void shuffle_params(int wh, uint64_t x0, uint64_t x1, uint32_t* a, uint32_t* c)
 {
@@ -1013,6 +1016,9 @@ int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp,
             }
 
             /* ---- generate: direction reuse inside interleaved groups ----
+             * A reused direction is weighted by the receiving pixel's own material
+             * (its own albedo for Lambert).  Pin: closed box of per-face albedos,
+             * L = E (1 + rho_own) exactly; open floor, L = rho_own * L_env exactly.
              * REUSE: tangent-space rules of Section 3.2 in groups interleaved by the
              * per-tile shuffle of Section 3.3.  REUSE_PLAIN: the same rules in groups of
              * K consecutive screen-order pixels (no shuffle: the ablation of Section 3.3).

@@ -92,6 +92,33 @@ def test_onb_random(orc):
         assert np.allclose(M @ M.T, np.eye(3), atol=4e-6)
 
 
+def test_offset_origin_published_steps(orc):
+    """Waechter & Binder (Ray Tracing Gems, 2019, ch. 6): away from the origin
+    (|p_i| >= 1/32) each coordinate moves by trunc(256 n_i) units in the last
+    place, away from zero when n_i points away from zero; near the origin it
+    moves by n_i / 65536 in floating point."""
+    p = np.array([1.5, -3.0, 100.0], np.float32)
+    n = np.array([0.6, 0.0, -0.8], np.float32)
+    q = orc.offset_origin(p, n)
+    dbits = q.view(np.int32).astype(np.int64) - p.view(np.int32).astype(np.int64)
+    assert dbits.tolist() == [153, 0, -204]            # trunc(256 * 0.6), 0, trunc(256 * -0.8)
+    p = np.array([-2.0, 7.25, -0.5], np.float32)
+    n = np.array([-0.36, 0.48, 0.8], np.float32)
+    q = orc.offset_origin(p, n)
+    dbits = q.view(np.int32).astype(np.int64) - p.view(np.int32).astype(np.int64)
+    # negative coordinates store a magnitude: -2.0 moves further from zero (its bit
+    # pattern grows by 92), -0.5 toward zero (its bit pattern shrinks by 204)
+    assert dbits.tolist() == [92, 122, -204]
+    p = np.array([0.01, -0.02, 0.0], np.float32)
+    n = np.array([0.0, 0.6, -0.8], np.float32)
+    q = orc.offset_origin(p, n)
+    expect = (p + n * np.float32(1.0 / 65536.0)).astype(np.float32)
+    assert np.array_equal(q.view(np.uint32), expect.view(np.uint32))
+    # the two regimes meet at |p| = 1/32
+    q = orc.offset_origin(np.array([1.0 / 32, -1.0 / 32, 0.03125], np.float32), np.array([1.0, 0.0, 0.0], np.float32))
+    assert q[0].view(np.int32) - np.float32(1.0 / 32).view(np.int32) == 256
+
+
 def test_offset_origin_side(orc):
     rng = np.random.default_rng(9)
     for scale in (1e-3, 1.0, 50.0, 4000.0):
@@ -415,6 +442,16 @@ def test_glossy_only_reuse_equals_incoherent(orc):
             assert np.array_equal(_bits(a[key]), _bits(b[key])), (key, tile, k)
 
 
+def _affine_slots(wh, x0, x1):
+    """The shuffle of Section 3.3 written out from its reading: multiplier
+    a = 2 (x0 mod wh/2) + 1 (odd), offset c = x1 mod wh, slot(i) = (a i + c) mod wh."""
+    if wh == 1:
+        return np.zeros(1, np.int64)
+    a = 2 * (x0 % (wh // 2)) + 1
+    c = x1 % wh
+    return np.array([(a * i + c) % wh for i in range(wh)], np.int64)
+
+
 def _pairwise_sum(vecs):
     v = [np.asarray(x, np.float32) for x in vecs]
     while len(v) > 1:
@@ -452,7 +489,7 @@ def test_reuse_rules_per_category(orc, tile, k, mode):
             # of counter (tile id, sample, bounce, stream 1) (Section 3.3)
             x = orc.philox((ty * (w // W) + tx, 0, 0, 1), (31, 0))
             if mode == "reuse":
-                assert np.array_equal(slot, orc.shuffle(W * H, int(x[0]), int(x[1])))
+                assert np.array_equal(slot, _affine_slots(W * H, int(x[0]), int(x[1])))
             else:
                 assert np.array_equal(slot, np.arange(W * H))
             for g in range(W * H // k):
@@ -519,7 +556,7 @@ def test_world_reuse_rules(orc):
             hpt = hp[sl].ravel()
             slot = (fl >> orc.F_SLOT_SH) & 0xFFFF
             x = orc.philox((ty * (w // W) + tx, 0, 0, 1), (33, 0))
-            assert np.array_equal(slot, orc.shuffle(W * H, int(x[0]), int(x[1])))
+            assert np.array_equal(slot, _affine_slots(W * H, int(x[0]), int(x[1])))
             act = np.where((fl & orc.F_ACTIVE) != 0)[0]
             if len(act) == 0:
                 continue
@@ -577,18 +614,28 @@ def test_group_composition_changes_across_samples(orc):
 
 
 def test_unbiased_diffuse_groups(orc):
-    """All-Lambert tiny room: diffuse groups reuse a cosine-distributed
-    direction with the receiving point's own pdf, so the expected image equals
-    plain path tracing (Section 3.2).  Tile-level z test over independent seeds."""
+    """All-Lambert tiny room: diffuse groups reuse a cosine-distributed direction
+    with the receiving point's own pdf, so the expected image equals plain path
+    tracing (Section 3.2).  32x32 pixels, 2048 samples per mode as 64 independent
+    batches of 32 (a new seed per batch, so each batch regroups): a tile-level z
+    test on the per-tile mean difference, and a per-pixel Welch test on the batch
+    means, at most 0.1% of pixels beyond |z| = 4.5."""
     s = scenes.tiny()
     sc = orc.OracleScene(s)
     w = h = 32
-    spp = 192
-    a = sc.render(w, h, spp, 2, mode="incoherent", tile=(4, 4), k=2, seed=101)["radiance"].astype(np.float64)
-    b = sc.render(w, h, spp, 2, mode="reuse", tile=(4, 4), k=8, seed=202)["radiance"].astype(np.float64)
-    D = (b - a).reshape(h // 4, 4, w // 4, 4, 3).mean(axis=(1, 3)).reshape(-1)
+    nb, spb = 64, 32
+    a = np.stack([sc.render(w, h, spb, 2, mode="incoherent", tile=(4, 4), k=2, seed=1000 + i)["radiance"]
+                  for i in range(nb)]).astype(np.float64)
+    b = np.stack([sc.render(w, h, spb, 2, mode="reuse", tile=(4, 4), k=8, seed=5000 + i)["radiance"]
+                  for i in range(nb)]).astype(np.float64)
+    ma, mb = a.mean(0), b.mean(0)
+    D = (mb - ma).reshape(h // 4, 4, w // 4, 4, 3).mean(axis=(1, 3)).reshape(-1)
     z = abs(D.mean()) / (D.std(ddof=1) / np.sqrt(D.size))
     assert z < 4.0, z
+    se = np.sqrt(a.var(0, ddof=1) / nb + b.var(0, ddof=1) / nb)
+    zp = np.abs(mb - ma) / np.maximum(se, 1e-12)
+    frac = float((zp > 4.5).any(axis=-1).mean())
+    assert frac <= 1e-3, frac
 
 
 def test_rays_per_bounce_counts(orc):
@@ -616,6 +663,152 @@ def test_tile_mask_matches_full_render(orc):
         pix[ty * H:(ty + 1) * H, tx * W:(tx + 1) * W] = True
     assert np.array_equal(full["hit_prim"][:, :, pix], part["hit_prim"][:, :, pix])
     assert np.array_equal(full["radiance"][pix].view(np.uint32), part["radiance"][pix].view(np.uint32))
+
+
+# ---------------------------------------------------------------- reflection law, own-material weights
+def _face_normals64(tris):
+    t = tris.astype(np.float64)
+    n = np.cross(t[:, 1] - t[:, 0], t[:, 2] - t[:, 0])
+    return n / np.linalg.norm(n, axis=1)[:, None]
+
+
+@pytest.mark.parametrize("scene_name,mode", [("mixed_small", "incoherent"), ("mixed_small", "reuse"),
+                                             ("checker", "reuse")])
+def test_mirror_exit_obeys_reflection_law(orc, scene_name, mode):
+    """A specular point (Section 3.2's specular class) sends the next ray along the
+    mirror reflection d - 2 (d.n) n of the incoming direction about the surface
+    normal, in world space, checked in float64 on every mirror hit of the frame."""
+    s = scenes.mixed_small() if scene_name == "mixed_small" else _checker_floor()
+    kinds = s["mats"]["kind"][s["tri_mat"]]
+    nrm = _face_normals64(s["tris"])
+    sc = orc.OracleScene(s)
+    B = 3
+    w, h = (160, 120) if scene_name == "mixed_small" else (64, 48)
+    r = sc.render(w, h, 1, B, mode=mode, tile=(8, 8), k=8, seed=29, rays=True)
+    checked = 0
+    for b in range(B):
+        hp = r["hit_prim"][b, 0].ravel()
+        nxt = r["hit_prim"][b + 1, 0].ravel()
+        rin = r["rays"][b, 0].reshape(-1, 8).astype(np.float64)
+        rout = r["rays"][b + 1, 0].reshape(-1, 8).astype(np.float64)
+        sel = np.where((hp >= 0) & (nxt != -2))[0]
+        sel = sel[kinds[hp[sel]] == scenes.MIRROR]
+        d = rin[sel, 4:7]
+        n = nrm[hp[sel]]
+        n = np.where((np.sum(n * d, axis=1) > 0)[:, None], -n, n)
+        refl = d - 2.0 * np.sum(d * n, axis=1)[:, None] * n
+        assert np.abs(rout[sel, 4:7] - refl).max(initial=0.0) < 2e-5, b
+        # the next ray leaves the hit point (offset along the normal by a few ulp)
+        hitp = rin[sel, 0:3] + r["hit_t"][b, 0].ravel()[sel][:, None].astype(np.float64) * d
+        assert np.abs(rout[sel, 0:3] - hitp).max(initial=0.0) < 1e-3, b
+        checked += len(sel)
+    assert checked > 50, checked
+
+
+def _box_per_face_albedo():
+    S = 4.0
+    faces = [
+        quad_((0, 0, 0), (S, 0, 0), (S, 0, S), (0, 0, S)),
+        quad_((0, S, 0), (0, S, S), (S, S, S), (S, S, 0)),
+        quad_((0, 0, 0), (0, 0, S), (0, S, S), (0, S, 0)),
+        quad_((S, 0, 0), (S, S, 0), (S, S, S), (S, 0, S)),
+        quad_((0, 0, 0), (0, S, 0), (S, S, 0), (S, 0, 0)),
+        quad_((0, 0, S), (S, 0, S), (S, S, S), (0, S, S)),
+    ]
+    alb = [(0.2, 0.5, 0.7), (0.9, 0.3, 0.4), (0.35, 0.65, 0.15), (0.6, 0.6, 0.25), (0.45, 0.1, 0.85), (0.75, 0.8, 0.55)]
+    mats = [scenes._mat(scenes.LAMBERT, a, 0.0, (1.0, 1.0, 1.0)) for a in alb]
+    cam = dict(pos=(1.0, 1.2, 1.1), look_at=(3.4, 3.1, 3.6), up=(0.0, 1.0, 0.0), vfov=100.0)
+    tris = sum(faces, [])
+    return _scene(tris, [f for f in range(6) for _ in range(2)], mats, (0.0, 0.0, 0.0), cam), np.array(alb, np.float32)
+
+
+def quad_(p0, p1, p2, p3):
+    return scenes.quad(p0, p1, p2, p3)
+
+
+@pytest.mark.parametrize("mode,tile,k", [("reuse", (8, 8), 64), ("reuse", (8, 8), 8), ("reuse_plain", (8, 8), 64),
+                                         ("reuse_world", (8, 8), 64), ("incoherent", (8, 8), 8)])
+def test_reused_direction_weighted_by_own_albedo_closed_box(orc, mode, tile, k):
+    """Sections 3.1 and 3.2: a pixel that takes another pixel's direction weighs it
+    by its own material.  Closed box, every face emitting E = 1 with its own RGB
+    albedo, one bounce: every path gathers E at the first hit and rho_own * E at the
+    second, so L = 1 + rho_own exactly, whichever direction the group shared."""
+    s, alb = _box_per_face_albedo()
+    sc = orc.OracleScene(s)
+    w, h = 48, 40
+    r = sc.render(w, h, 1, 1, mode=mode, tile=tile, k=k, seed=44, debug=True)
+    face = r["hit_prim"][0, 0] // 2
+    assert (r["hit_prim"][0, 0] >= 0).all()
+    one = np.float32(1.0)
+    expect = (one + alb[face] * one).astype(np.float32)
+    died = r["hit_prim"][1, 0] == -2          # direct reuse ends paths whose shared direction points inward
+    assert np.array_equal(r["radiance"][~died].view(np.uint32), expect[~died].view(np.uint32))
+    assert np.array_equal(r["radiance"][died], np.broadcast_to(one, r["radiance"][died].shape))
+    if mode != "incoherent":
+        # the frame holds reusing pixels whose representative sits on another face
+        fl = r["dbg_flags"][0, 0]
+        reused = (fl & orc.F_REUSED) != 0
+        W, H = tile
+        cross = 0
+        for ty in range(h // H):
+            for tx in range(w // W):
+                sl = (slice(ty * H, (ty + 1) * H), slice(tx * W, (tx + 1) * W))
+                f_t = face[sl].ravel()
+                rep = (fl[sl].ravel() & orc.F_REP) != 0
+                if rep.any() and len(np.unique(f_t)) > 1:
+                    cross += int((reused[sl].ravel() & (f_t != f_t[np.argmax(rep)])).sum())
+        assert cross > 20, cross
+
+
+def _checker_floor(n=24, cell=0.5):
+    """Floor y = 0 of n x n cells cycling through Lambert albedos, GGX and mirror, open sky."""
+    mats = [scenes._mat(scenes.LAMBERT, a) for a in
+            [(0.2, 0.5, 0.7), (0.9, 0.3, 0.4), (0.35, 0.65, 0.15), (0.6, 0.6, 0.25), (0.45, 0.1, 0.85)]]
+    mats += [scenes._mat(scenes.GGX, (0.8, 0.7, 0.6), 0.3), scenes._mat(scenes.MIRROR, (0.85, 0.9, 0.75))]
+    tris, ids = [], []
+    rng = np.random.default_rng(5)
+    for i in range(n):
+        for j in range(n):
+            x0, z0 = (i - n / 2) * cell, (j - n / 2) * cell
+            tris += scenes.quad((x0, 0, z0), (x0, 0, z0 + cell), (x0 + cell, 0, z0 + cell), (x0 + cell, 0, z0))
+            m = int(rng.integers(len(mats)))
+            ids += [m, m]
+    cam = dict(pos=(0.3, 4.0, 1.0), look_at=(-0.2, 0.0, -0.5), up=(0.0, 1.0, 0.0), vfov=50.0)
+    return _scene(tris, ids, mats, (0.7, 0.9, 1.1), cam)
+
+
+@pytest.mark.parametrize("mode,k", [("reuse", 8), ("reuse", 64), ("reuse_plain", 16), ("reuse_world", 64),
+                                    ("incoherent", 8)])
+def test_open_floor_one_bounce_weights(orc, mode, k):
+    """One bounce off a plane under a constant sky: every exit leaves the scene, so a
+    Lambert or mirror pixel ends with L = w_own * L_env exactly (w = its own albedo),
+    in diffuse and hybrid groups alike; a GGX pixel ends with its own sampled weight
+    times L_env or, when its sample died, 0."""
+    s = _checker_floor()
+    sc = orc.OracleScene(s)
+    w, h = 64, 48
+    r = sc.render(w, h, 1, 1, mode=mode, tile=(8, 8), k=k, seed=45, debug=True)
+    hp0 = r["hit_prim"][0, 0]
+    assert (hp0 >= 0).all()
+    mat = s["tri_mat"][hp0]
+    kind = s["mats"]["kind"][mat]
+    alb = s["mats"]["albedo"][mat].astype(np.float32)
+    env = s["env"].astype(np.float32)
+    lam_or_mirror = kind != scenes.GGX
+    assert (r["hit_prim"][1, 0][lam_or_mirror] == -1).all()
+    expect = (alb * env).astype(np.float32)
+    got = r["radiance"]
+    assert np.array_equal(got[lam_or_mirror].view(np.uint32), expect[lam_or_mirror].view(np.uint32))
+    gl = kind == scenes.GGX
+    dead = gl & (r["hit_prim"][1, 0] == -2)
+    assert (got[dead] == 0).all() and (got[gl & ~dead] > 0).all()
+    if mode != "incoherent":
+        fl = r["dbg_flags"][0, 0]
+        cat = (fl >> orc.F_CAT_SH) & 3
+        reused = (fl & orc.F_REUSED) != 0
+        assert (reused & (kind == scenes.LAMBERT)).sum() > 100
+        if mode != "reuse_world":
+            assert ((cat == 3) & (kind == scenes.LAMBERT) & reused).sum() > 20   # hybrid groups are covered
 
 
 # ---------------------------------------------------------------- next-event estimation
