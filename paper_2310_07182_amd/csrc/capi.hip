@@ -162,7 +162,7 @@ Frame make_frame(int w, int h, int spp, int B, pt_mode mode, pt_group g, uint64_
     f.H = g.tile_h;
     f.K = g.k;
     f.WH = f.W * f.H;
-    f.reuse_max = g.reuse_max_bounce;
+    f.reuse_max = g.reuse_max_bounce ? g.reuse_max_bounce : 0xFFFF;   // 0: the library default, every bounce
     super_tile(f.W, f.H, f.SW, f.SH, f.cols);
     f.TS = f.SW * f.SH;
     f.nstx = (w + f.SW - 1) / f.SW;

@@ -1,14 +1,16 @@
-"""Batched rendering on the GPU: every job's outputs are bit-identical to the
-same job rendered alone with pt_render, whether the batch is stepped with jobs
-joining at different times (continuous batching), run as a static schedule, or
-replayed as a captured hipGraph; admission refuses jobs beyond the slots or
-the arena."""
+"""Batched rendering on the GPU: every job's outputs match the CPU oracle's
+render of the same job (tests/parity.py bar: bit-exact ids, hit distances and
+radiance) and are bit-identical to the same job rendered alone with pt_render,
+whether the batch is stepped with jobs joining at different times (continuous
+batching), run as a static schedule, or replayed as a captured hipGraph;
+admission refuses jobs beyond the slots or the arena."""
 import sys
 
 import numpy as np
 import pytest
 
 from paper_2310_07182_amd import scenes
+from tests.parity import compare_render
 
 pytestmark = pytest.mark.gpu
 
@@ -19,13 +21,15 @@ def _say(*a):
 
 
 @pytest.fixture(scope="module")
-def env():
+def env(orc):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2310_07182_amd import api
-    sc = {name: api.Scene(getattr(scenes, name)()) for name in ("tiny", "mixed_small", "furnace")}
-    return torch, api, sc
+    src = {name: getattr(scenes, name)() for name in ("tiny", "mixed_small", "furnace")}
+    sc = {name: api.Scene(s) for name, s in src.items()}
+    osc = {name: orc.OracleScene(s) for name, s in src.items()}
+    return torch, api, sc, osc
 
 
 JOBS = [
@@ -53,6 +57,18 @@ def _same(torch, ref, out, tag):
         assert torch.equal(a.view(torch.int32), b.view(torch.int32)), (tag, key)
 
 
+_orc_cache = {}
+
+
+def _matches_oracle(osc, out, spec):
+    """The batched job against the oracle's render of the same job."""
+    name, w, h, spp, B, mode, seed = spec
+    if spec not in _orc_cache:
+        _orc_cache[spec] = osc[name].render(w, h, spp, B, mode=mode, tile=TILE, k=K, seed=seed)
+    g = dict(radiance=out.radiance, hit_prim=out.hit_prim, hit_t=out.hit_t)
+    return compare_render(g, _orc_cache[spec], TILE, mode, check_rays=False)
+
+
 def _new_batch(api, max_jobs, specs, sc, extra=0, traversal=0):
     b = api.Batch(max_jobs, 1, tile=TILE, k=K)
     need = api.Batch.base_bytes(max_jobs)
@@ -67,7 +83,7 @@ def _new_batch(api, max_jobs, specs, sc, extra=0, traversal=0):
 
 
 def test_batch_stepped_with_staggered_arrivals_equals_alone(env):
-    torch, api, sc = env
+    torch, api, sc, osc = env
     refs = [_alone(torch, api, sc, spec) for spec in JOBS]
     b, outs = _new_batch(api, 4, JOBS, sc)
     pending = list(range(len(JOBS)))
@@ -94,12 +110,13 @@ def test_batch_stepped_with_staggered_arrivals_equals_alone(env):
     _say(f"[gpu] stepped batch: {steps} steps")
     for i, spec in enumerate(JOBS):
         _same(torch, refs[i], outs[i], spec)
+        _say("  ", spec, _matches_oracle(osc, outs[i], spec))
 
 
 @pytest.mark.parametrize("use_graph,traversal", [(False, "auto"), (True, "auto"), (False, "pair"), (True, "wide"),
                                                 (False, "queue")])
 def test_batch_static_run_equals_alone(env, use_graph, traversal):
-    torch, api, sc = env
+    torch, api, sc, osc = env
     refs = [_alone(torch, api, sc, spec) for spec in JOBS]
     b, outs = _new_batch(api, len(JOBS), JOBS, sc, extra=1 << 20, traversal=traversal)
     for i, (name, w, h, spp, B, mode, seed) in enumerate(JOBS):
@@ -114,10 +131,11 @@ def test_batch_static_run_equals_alone(env, use_graph, traversal):
         torch.cuda.synchronize()
         for i, spec in enumerate(JOBS):
             _same(torch, refs[i], outs[i], (spec, rep))
+            _matches_oracle(osc, outs[i], spec)
 
 
 def test_batch_admission_limits(env):
-    torch, api, sc = env
+    torch, api, sc, osc = env
     spec = ("tiny", 64, 64, 1, 2, "reuse", 1)
     b, outs = _new_batch(api, 2, [spec, spec], sc)
     name, w, h, spp, B, mode, seed = spec

@@ -45,15 +45,15 @@ def test_landscape_full_size_sampled_tiles(land, mode):
     w, h, B, tile, k = cfg["w"], cfg["h"], cfg["bounces"], cfg["tile"], cfg["k"]
     seed = 2310071822
     _say(f"[gpu] landscape render {w}x{h} B={B} mode={mode}")
-    g = api.render(sc, w, h, 1, B, mode, tile, k, None, seed)
+    g = api.render(sc, w, h, 1, B, mode, tile, k, None, seed, rays=True)
     torch.cuda.synchronize()
     ntx, nty = (w + tile[0] - 1) // tile[0], (h + tile[1] - 1) // tile[1]
     rng = np.random.default_rng(321)
-    pick = rng.choice(ntx * nty, 16, replace=False)
+    pick = rng.choice(ntx * nty, (ntx * nty) // 100, replace=False)   # 1% of the tiles
     pick = np.concatenate([pick, [0, ntx - 1, ntx * nty - 1, ntx * (nty // 2) + ntx // 2]])
     mask = np.zeros(ntx * nty, np.uint8)
     mask[pick] = 1
-    o = osc.render(w, h, 1, B, mode=mode, tile=tile, k=k, seed=seed, tile_mask=mask)
+    o = osc.render(w, h, 1, B, mode=mode, tile=tile, k=k, seed=seed, tile_mask=mask, rays=True)
     pm = np.zeros((h, w), bool)
     for t in np.where(mask)[0]:
         ty, tx = divmod(int(t), ntx)

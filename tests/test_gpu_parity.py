@@ -43,7 +43,8 @@ def both(api, orc, name):
 def gpu_render(api, sc, w, h, spp, B, mode, tile, k, seed, rmax=None, camera=None, refill=0, leaf_gate=0):
     _say(f"[gpu] render {w}x{h} spp={spp} B={B} mode={mode} tile={tile} k={k} seed={seed} rmax={rmax} refill={refill} "
          f"leaf_gate={leaf_gate}")
-    r = api.render(sc, w, h, spp, B, mode, tile, k, rmax, seed, camera, refill=refill, leaf_gate=leaf_gate)
+    r = api.render(sc, w, h, spp, B, mode, tile, k, rmax, seed, camera, refill=refill, leaf_gate=leaf_gate,
+                   rays=True)
     import torch
     torch.cuda.synchronize()
     return r
@@ -150,7 +151,7 @@ def test_trace_empty_and_tiny_batches(api, orc, torch_dev):
 def test_render_parity_tiny(api, orc, torch_dev, mode, tile, k):
     s, sc, osc = both(api, orc, "tiny")
     g = gpu_render(api, sc, 64, 64, 1, 2, mode, tile, k, 2310071820)
-    o = osc.render(64, 64, 1, 2, mode=mode, tile=tile, k=k, seed=2310071820)
+    o = osc.render(64, 64, 1, 2, mode=mode, tile=tile, k=k, seed=2310071820, rays=True)
     res = compare_render(g, o, tile, mode)
     _say("  ", res)
     assert np.array_equal(g["rays_per_bounce"].cpu().numpy(), o["rays_per_bounce"].astype(np.int64))
@@ -170,7 +171,7 @@ def test_render_parity_tiny(api, orc, torch_dev, mode, tile, k):
 def test_render_parity_mixed(api, orc, torch_dev, mode, tile, k, w, h, spp, B):
     s, sc, osc = both(api, orc, "mixed_small")
     g = gpu_render(api, sc, w, h, spp, B, mode, tile, k, 99)
-    o = osc.render(w, h, spp, B, mode=mode, tile=tile, k=k, seed=99)
+    o = osc.render(w, h, spp, B, mode=mode, tile=tile, k=k, seed=99, rays=True)
     res = compare_render(g, o, tile, mode)
     _say("  ", res)
 
@@ -180,7 +181,7 @@ def test_render_parity_mixed(api, orc, torch_dev, mode, tile, k, w, h, spp, B):
 def test_render_parity_refill(api, orc, torch_dev, mode, refill):
     s, sc, osc = both(api, orc, "mixed_small")
     g = gpu_render(api, sc, 83, 61, 1, 3, mode, (8, 8), 8, 41, refill=refill)
-    o = osc.render(83, 61, 1, 3, mode=mode, tile=(8, 8), k=8, seed=41)
+    o = osc.render(83, 61, 1, 3, mode=mode, tile=(8, 8), k=8, seed=41, rays=True)
     compare_render(g, o, (8, 8), mode)
 
 
@@ -189,7 +190,7 @@ def test_render_parity_refill(api, orc, torch_dev, mode, refill):
 def test_render_parity_leaf_gate(api, orc, torch_dev, mode, leaf_gate, refill):
     s, sc, osc = both(api, orc, "mixed_small")
     g = gpu_render(api, sc, 83, 61, 1, 3, mode, (8, 8), 8, 43, refill=refill, leaf_gate=leaf_gate)
-    o = osc.render(83, 61, 1, 3, mode=mode, tile=(8, 8), k=8, seed=43)
+    o = osc.render(83, 61, 1, 3, mode=mode, tile=(8, 8), k=8, seed=43, rays=True)
     compare_render(g, o, (8, 8), mode)
 
 
@@ -204,7 +205,7 @@ def test_render_parity_leaf_gate(api, orc, torch_dev, mode, leaf_gate, refill):
 def test_render_parity_reuse_ablations(api, orc, torch_dev, mode, tile, k, w, h, spp, B):
     s, sc, osc = both(api, orc, "mixed_small")
     g = gpu_render(api, sc, w, h, spp, B, mode, tile, k, 123)
-    o = osc.render(w, h, spp, B, mode=mode, tile=tile, k=k, seed=123)
+    o = osc.render(w, h, spp, B, mode=mode, tile=tile, k=k, seed=123, rays=True)
     res = compare_render(g, o, tile, mode)
     _say("  ", res)
 
@@ -220,9 +221,9 @@ def test_render_parity_reuse_ablations(api, orc, torch_dev, mode, tile, k, w, h,
 def test_render_parity_nee(api, orc, torch_dev, name, mode, tile, k, w, h, spp, B):
     s, sc, osc = both(api, orc, name)
     _say(f"[gpu] nee render {name} {w}x{h} spp={spp} B={B} mode={mode}")
-    g = api.render(sc, w, h, spp, B, mode, tile, k, None, 321, nee=True)
+    g = api.render(sc, w, h, spp, B, mode, tile, k, None, 321, nee=True, rays=True)
     torch_dev.cuda.synchronize()
-    o = osc.render(w, h, spp, B, mode=mode, tile=tile, k=k, seed=321, nee=True)
+    o = osc.render(w, h, spp, B, mode=mode, tile=tile, k=k, seed=321, nee=True, rays=True)
     res = compare_render(g, o, tile, mode)
     _say("  ", res)
     assert np.array_equal(g["shadow_rays_per_bounce"].cpu().numpy(), o["shadow_rays"].astype(np.int64))
@@ -233,7 +234,15 @@ def test_render_parity_nee(api, orc, torch_dev, name, mode, tile, k, w, h, spp, 
 def test_reuse_max_bounce_one(api, orc, torch_dev):
     s, sc, osc = both(api, orc, "mixed_small")
     g = gpu_render(api, sc, 64, 48, 1, 3, "reuse", (8, 8), 8, 5, rmax=1)
-    o = osc.render(64, 48, 1, 3, mode="reuse", tile=(8, 8), k=8, seed=5, reuse_max_bounce=1)
+    o = osc.render(64, 48, 1, 3, mode="reuse", tile=(8, 8), k=8, seed=5, reuse_max_bounce=1, rays=True)
+    compare_render(g, o, (8, 8), "reuse")
+
+
+def test_reuse_max_bounce_zero_means_every_bounce(api, orc, torch_dev):
+    # a zero-initialised pt_group asks for the library default: reuse at every bounce
+    s, sc, osc = both(api, orc, "mixed_small")
+    g = gpu_render(api, sc, 64, 48, 1, 3, "reuse", (8, 8), 8, 6, rmax=0)
+    o = osc.render(64, 48, 1, 3, mode="reuse", tile=(8, 8), k=8, seed=6, reuse_max_bounce=3, rays=True)
     compare_render(g, o, (8, 8), "reuse")
 
 
@@ -257,7 +266,7 @@ def test_furnace_gpu(api, orc, torch_dev):
 def test_bounces_zero_and_empty_scene(api, orc, torch_dev):
     s, sc, osc = both(api, orc, "tiny")
     g = gpu_render(api, sc, 33, 17, 1, 0, "reuse", (4, 4), 2, 3)
-    o = osc.render(33, 17, 1, 0, mode="reuse", tile=(4, 4), k=2, seed=3)
+    o = osc.render(33, 17, 1, 0, mode="reuse", tile=(4, 4), k=2, seed=3, rays=True)
     compare_render(g, o, (4, 4), "reuse")
     mats = np.array([(0, (0.5, 0.5, 0.5), 0.0, (0, 0, 0))], dtype=scenes.MATERIAL_DTYPE)
     empty = dict(tris=np.zeros((0, 3, 3), np.float32), tri_mat=np.zeros(0, np.uint32), mats=mats,
@@ -292,7 +301,7 @@ def test_ray_keys_parity(api, orc, torch_dev, kind):
 def test_render_parity_other_sorted_modes(api, orc, torch_dev, mode):
     s, sc, osc = both(api, orc, "mixed_small")
     g = gpu_render(api, sc, 101, 67, 2, 4, mode, (8, 8), 8, 77)
-    o = osc.render(101, 67, 2, 4, mode=mode, tile=(8, 8), k=8, seed=77)
+    o = osc.render(101, 67, 2, 4, mode=mode, tile=(8, 8), k=8, seed=77, rays=True)
     compare_render(g, o, (8, 8), mode)
 
 
@@ -334,9 +343,9 @@ def test_render_parity_traversal_kinds(api, orc, torch_dev, traversal, mode, nee
     assert sc.info()["wide"] == 1
     _say(f"[gpu] traversal={traversal} mode={mode} nee={nee} refill={refill} leaf_gate={leaf_gate}")
     g = api.render(sc, 83, 61, 1, 3, mode, (8, 8), 8, None, 47, refill=refill, leaf_gate=leaf_gate, nee=nee,
-                   traversal=traversal)
+                   traversal=traversal, rays=True)
     torch_dev.cuda.synchronize()
-    o = osc.render(83, 61, 1, 3, mode=mode, tile=(8, 8), k=8, seed=47, nee=nee)
+    o = osc.render(83, 61, 1, 3, mode=mode, tile=(8, 8), k=8, seed=47, nee=nee, rays=True)
     compare_render(g, o, (8, 8), mode)
     if nee:
         assert np.array_equal(g["shadow_rays_per_bounce"].cpu().numpy(), o["shadow_rays"].astype(np.int64))
@@ -359,15 +368,15 @@ def test_indoor_full_size_sampled_tiles(api, orc, torch_dev, mode, traversal):
     w, h, B, tile, k = cfg["w"], cfg["h"], cfg["bounces"], cfg["tile"], cfg["k"]
     seed = 2310071821
     _say(f"[gpu] indoor traversal={traversal}")
-    g = api.render(sc, w, h, 1, B, mode, tile, k, None, seed, traversal=traversal)
+    g = api.render(sc, w, h, 1, B, mode, tile, k, None, seed, traversal=traversal, rays=True)
     torch_dev.cuda.synchronize()
     ntx, nty = (w + tile[0] - 1) // tile[0], (h + tile[1] - 1) // tile[1]
     rng = np.random.default_rng(123)
-    pick = rng.choice(ntx * nty, 24, replace=False)
+    pick = rng.choice(ntx * nty, (ntx * nty) // 100, replace=False)   # 1% of the tiles
     pick = np.concatenate([pick, [0, ntx - 1, ntx * nty - 1, ntx * (nty // 2) + ntx // 2]])
     mask = np.zeros(ntx * nty, np.uint8)
     mask[pick] = 1
-    o = osc.render(w, h, 1, B, mode=mode, tile=tile, k=k, seed=seed, tile_mask=mask)
+    o = osc.render(w, h, 1, B, mode=mode, tile=tile, k=k, seed=seed, tile_mask=mask, rays=True)
     pm = np.zeros((h, w), bool)
     for t in np.where(mask)[0]:
         ty, tx = divmod(int(t), ntx)
@@ -388,7 +397,7 @@ def test_indoor_full_size_sampled_tiles(api, orc, torch_dev, mode, traversal):
 def test_render_parity_edge_shapes(api, orc, torch_dev, w, h, tile, k, mode):
     s, sc, osc = both(api, orc, "mixed_small")
     g = gpu_render(api, sc, w, h, 2, 3, mode, tile, k, 55)
-    o = osc.render(w, h, 2, 3, mode=mode, tile=tile, k=k, seed=55)
+    o = osc.render(w, h, 2, 3, mode=mode, tile=tile, k=k, seed=55, rays=True)
     compare_render(g, o, tile, mode)
 
 
@@ -396,7 +405,7 @@ def test_render_parity_deep_paths(api, orc, torch_dev):
     # 16 bounces in the closed furnace: every path survives to the end
     s, sc, osc = both(api, orc, "furnace")
     g = gpu_render(api, sc, 24, 24, 3, 16, "reuse", (8, 8), 8, 9)
-    o = osc.render(24, 24, 3, 16, mode="reuse", tile=(8, 8), k=8, seed=9)
+    o = osc.render(24, 24, 3, 16, mode="reuse", tile=(8, 8), k=8, seed=9, rays=True)
     compare_render(g, o, (8, 8), "reuse")
     assert (g["hit_prim"].cpu().numpy() >= 0).all()
 
@@ -410,9 +419,9 @@ def test_indoor_4k_sampled_tiles(api, orc, torch_dev, mode):
     ntx, nty = w // 8, h // 8
     rng = np.random.default_rng(99)
     mask = np.zeros(ntx * nty, np.uint8)
-    mask[rng.choice(ntx * nty, 12, replace=False)] = 1
+    mask[rng.choice(ntx * nty, (ntx * nty) // 100, replace=False)] = 1   # 1% of the tiles
     mask[[0, ntx * nty - 1]] = 1
-    o = osc.render(w, h, 1, B, mode=mode, tile=tile, k=k, seed=77, tile_mask=mask)
+    o = osc.render(w, h, 1, B, mode=mode, tile=tile, k=k, seed=77, tile_mask=mask, rays=True)
     pm = np.zeros((h, w), bool)
     for t in np.where(mask)[0]:
         ty, tx = divmod(int(t), ntx)
