@@ -18,9 +18,21 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}", "-ff
          "-Wall", "-Wno-unused-function", "-pthread"]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+SAN_LIB = os.path.join(HERE, "libpt_san.so")
+# host sanitizers for the CPU tests of the host code (scene build, BVH, C-ABI checks, batch
+# bookkeeping): address and undefined behaviour on the host side of every source only
+SAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+            "-shared-libsan"]
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compiles libpt.so; with sanitize, libpt_san.so with host-side ASan and UBSan (load it with
+    the compiler's ASan runtime preloaded; for CPU runs of the host code)."""
+    out = SAN_LIB if sanitize else LIB
+    tmp = out + ".tmp"
+    flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-g"] + SAN_HOST if sanitize else FLAGS
+    cmd = [HIPCC] + flags + ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -32,8 +44,8 @@ def build(verbose: bool = False) -> str:
         lines = [ln for ln in r.stderr.splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
         if lines:
             sys.stderr.write("\n".join(lines) + "\n")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpt.so")
+# PT_LIB names another build of the same sources (the host-sanitizer build of the CPU tests)
+LIB_PATH = os.environ.get("PT_LIB") or os.path.join(HERE, "libpt.so")
 
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_EUNSUPPORTED, PT_EBUSY = 0, -1, -2, -3, -4, -5
 MODES = {"incoherent": 0, "sorted": 1, "reuse": 2, "sorted_origin": 3, "sorted_reis": 4, "sorted_aila": 5,

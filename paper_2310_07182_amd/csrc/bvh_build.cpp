@@ -403,7 +403,12 @@ bool quantize_bvh4(const std::vector<Bvh4Node>& n4, std::vector<Bvh4QNode>& q) {
                 // the smallest step 2^e that spans the node in at most 255 steps (upper bound of the extent)
                 const double ext = std::nextafter((double)hi[a] - (double)lo[a], INFINITY);
                 int ea = -100;
-                if (ext > 0.0) ea = std::max(-100, (int)std::ceil(std::log2(ext / 255.0)));
+                if (ext > 0.0) {
+                    // a flat extent makes ext a denormal whose 255th part is 0: log2 = -inf, which
+                    // must not reach the int conversion (clamped in double first)
+                    const double lg = std::ceil(std::log2(ext / 255.0));
+                    if (lg > -100.0) ea = (int)lg;
+                }
                 while (std::ceil(ext / std::ldexp(1.0, ea)) > 255.0) ++ea;
                 if (ea > kQMaxExp) {
                     ok = false;
