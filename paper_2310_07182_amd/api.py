@@ -256,6 +256,19 @@ def trace(scene: Scene, rays: torch.Tensor, refill: int = 0):
     return prim, t
 
 
+def trace_static(scene: Scene, rays: torch.Tensor, refill: int = 0, waves_per_cu: int = 0):
+    """pt_trace_static: as trace(), with the library's fixed scratch instead of a workspace."""
+    assert rays.dtype == torch.float32 and rays.is_contiguous() and rays.shape[-1] == 8
+    dev = scene.device
+    n = rays.shape[0]
+    prim = torch.empty(n, dtype=torch.int32, device=dev)
+    t = torch.empty(n, dtype=torch.float32, device=dev)
+    with torch.cuda.device(dev):
+        check(lib().pt_trace_static(scene.handle, rays.data_ptr(), n, int(refill), int(waves_per_cu), prim.data_ptr(),
+                                    t.data_ptr(), _stream_handle(dev)))
+    return prim, t
+
+
 def ray_keys(scene: Scene, rays: torch.Tensor, mode: str = "sorted") -> torch.Tensor:
     """Reordering keys of a sorted mode ("sorted" = TwoPoint, "sorted_origin", "sorted_reis",
     "sorted_aila"); int32 tensor holding the uint32 keys."""

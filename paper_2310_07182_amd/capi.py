@@ -83,6 +83,8 @@ PROTOTYPES = {
                         C.POINTER(Outputs), _vp]),
     "pt_trace_workspace_bytes": (_sz, []),
     "pt_trace": (_st, [_vp, _vp, _u32, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "pt_trace_static_scratch_bytes": (_sz, []),
+    "pt_trace_static": (_st, [_vp, _vp, _u32, _i32, _i32, _vp, _vp, _vp]),
     "pt_ray_keys": (_st, [_vp, _vp, _u32, C.c_int, _vp, _vp]),
     "pt_sort_workspace_bytes": (_sz, [_u32]),
     "pt_sort_pairs": (_st, [_vp, _vp, _u32, _vp, _sz, _vp]),

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -696,6 +697,92 @@ pt_status pt_trace(pt_scene scene, const float* rays, uint32_t n, int refill, in
     ta.leaf_gate = pt::kDefaultLeafGate - 1;
     ta.kind = -1;
     hipError_t e = pt::launch_zero(ta.work, pt::kWorkWords, st);
+    if (e != hipSuccess) return hip_fail(e, "launch (zero)");
+    e = pt::launch_trace(scene->dev, ta, false, st);
+    if (e != hipSuccess) return hip_fail(e, "launch (trace)");
+    return PT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of pt_trace_static: the launch's ray counters, then the traversal stack overflow
+// area of a persistent grid of at most kStaticTraceBlocks workgroups ([kStackOvf][grid lanes]
+// int32).  File-scope device memory, one copy per device, held until the process ends.  In
+// host code its name is not a device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device (static_scratch below).
+constexpr int kStaticTraceBlocks = 2048;   // 8 waves per CU on 256 CUs
+constexpr size_t kStaticWorkBytes = (size_t)pt::kWorkWords * 4;
+constexpr size_t kStaticScratchBytes =
+    kStaticWorkBytes + (size_t)kStaticTraceBlocks * pt::kTraceBlock * pt::kStackOvf * 4;
+static_assert(kStaticWorkBytes % 256 == 0, "the overflow area stays 256-byte aligned");
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+pt_status static_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(PT_EUNSUPPORTED, "device %d is beyond the %d this library serves", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(PT_EDEVICE, "hipGetSymbolAddress(scratch) returned a null address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pt_trace_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+pt_status pt_trace_static(pt_scene scene, const float* rays, uint32_t n, int refill, int waves_per_cu, int32_t* prim,
+                          float* t, void* stream) {
+    if (refill < 0 || refill > 64) return fail(PT_EINVAL, "refill must be in [0, 64] (got %d)", refill);
+    if (waves_per_cu < 0 || waves_per_cu > 32) return fail(PT_EINVAL, "waves_per_cu must be in [0, 32] (got %d)", waves_per_cu);
+    if (!scene || (n > 0 && (!rays || !prim || !t))) return fail(PT_EINVAL, "null argument");
+    if (!scene->uploaded) return fail(PT_EINVAL, "scene not uploaded");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != scene->device) return fail(PT_EINVAL, "scene was uploaded on device %d, current device is %d", scene->device, dev);
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    // the scratch holds the overflow stacks of kStaticTraceBlocks workgroups: a larger grid is refused
+    if (waves_per_cu > 0 && (long long)waves_per_cu * cus > kStaticTraceBlocks)
+        return fail(PT_EINVAL, "waves_per_cu %d x %d compute units exceeds the %d workgroups the static scratch (%zu bytes) holds",
+                    waves_per_cu, cus, kStaticTraceBlocks, kStaticScratchBytes);
+    void* sp = nullptr;
+    pt_status ps = static_scratch(&sp);
+    if (ps != PT_OK) return ps;
+    if (n == 0) return PT_OK;
+    hipStream_t st = (hipStream_t)stream;
+    pt::TraceArgs ta{};
+    ta.rays = (const float4*)rays;
+    ta.n = n;
+    ta.work = (uint32_t*)sp;
+    ta.out_prim = prim;
+    ta.out_t = t;
+    ta.ovf = (int32_t*)((char*)sp + kStaticWorkBytes);
+    ta.by_pixel = 0;
+    ta.refill = refill ? refill : kDefaultRefill;
+    ta.waves_per_cu = waves_per_cu ? waves_per_cu : kStaticTraceBlocks / (cus > 0 ? cus : 1);
+    ta.leaf_gate = pt::kDefaultLeafGate - 1;
+    ta.kind = -1;
+    ta.max_blocks = kStaticTraceBlocks;
+    e = pt::launch_zero(ta.work, pt::kWorkWords, st);   // a fill kernel, not a memset node
     if (e != hipSuccess) return hip_fail(e, "launch (zero)");
     e = pt::launch_trace(scene->dev, ta, false, st);
     if (e != hipSuccess) return hip_fail(e, "launch (trace)");

@@ -77,6 +77,8 @@ struct TraceArgs {
     uint8_t* touched;          // optional (counting kernels): node flags, then triangle flags from touch_tri
     uint32_t touch_tri;
     uint32_t touch_bit;
+    int max_blocks;            // > 0: the persistent grid has at most this many workgroups (the
+                               // overflow area ovf holds that many); 0 = no cap beyond kMaxTraceBlocks
 };
 
 // One job of a merged launch (batched rendering): the shade, raygen and trace launches of a

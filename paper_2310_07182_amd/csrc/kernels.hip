@@ -1568,7 +1568,9 @@ int trace_kind(const DevScene& sc) {
 }
 
 hipError_t launch_trace(const DevScene& sc, const TraceArgs& a, bool stats, hipStream_t st) {
-    const int g = trace_grid_blocks(a.waves_per_cu);
+    int g = trace_grid_blocks(a.waves_per_cu);
+    if (a.max_blocks > 0 && g > a.max_blocks) g = a.max_blocks & ~7;   // still a multiple of the 8 XCDs
+    if (g < 8) return hipErrorInvalidValue;
     const uint32_t gthreads = (uint32_t)g * kTraceBlock;
     if (a.refill < 1 || a.refill > 64) return hipErrorInvalidValue;
     const StepJob* none = nullptr;
