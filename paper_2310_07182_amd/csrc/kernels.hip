@@ -615,7 +615,12 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
 // on.  Owners re-read their key after every block to cull against it.  Culling prunes
 // only, and every queued triangle is tested, so the result is the exact (t, prim id)
 // minimum, as in k_trace.  Rays are claimed from the spread counters as in k_trace, each
-// claim at most the launch's even share per wave.
+// claim at most the launch's even share per wave.  Once the counters are used up (the
+// drain, where most lanes would idle while a few rays finish), a walking lane with pending
+// stack entries gives its top entry to a free lane, which walks that subtree with a copy of
+// the ray; its triangle tests fold into the owner's key, and the owner writes the hit once no
+// lane walks any part of its ray.  Which lane visits a subtree changes only the visiting
+// order, so the result stays the exact (t, prim id) minimum.
 
 // Slab tests of the four children of a quantized node (g = {p, step x}; child planes in
 // q0 = {lo x, hi x, lo y, hi y}, q1 = {lo z, hi z, step y, step z}, one byte per child).
@@ -679,6 +684,20 @@ constexpr uint32_t kQTriMask = (1u << kQTriBits) - 1u;
 static_assert(kLeafQ >= 2 * kTraceBlock + kTraceBlock * kMaxLeaf, "one step appends at most 64 leaves");
 static_assert((kLeafQ & (kLeafQ - 1)) == 0, "the ring wraps by masking");
 
+// Position of the r-th set bit (r counted from 0) of m, which has more than r set bits.
+__device__ __forceinline__ int nth_set_bit(unsigned long long m, uint32_t r) {
+    int base = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const uint32_t c = (uint32_t)__popcll(m & ((1ull << w) - 1ull));
+        const bool up = r >= c;
+        r = up ? r - c : r;
+        m = up ? m >> w : m;
+        base += up ? w : 0;
+    }
+    return base;
+}
+
 __device__ __forceinline__ unsigned long long hit_key(float t, uint32_t p) {
     return ((unsigned long long)__float_as_uint(t) << 32) | p;
 }
@@ -697,7 +716,9 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
     const unsigned long long key0 = a.shadow ? hit_key(kShadowTmax, 0u) : hit_key(INFINITY, (uint32_t)INT32_MAX);
     unsigned long long nv = 0, nt = 0;
     uint32_t traced = 0;
-    bool have = false;
+    bool have = false;               // the lane walks a ray (its own, or part of another lane's)
+    bool own = false;                // the lane holds a claimed ray whose hit it writes
+    int owner = lane;                // the lane whose ray this lane walks
     bool exhausted = false;          // wave-uniform: the queue of rays is used up
     uint32_t cq = blockIdx.x % kRayCounters;   // wave-uniform: the counter claimed from
     int tries = 0;
@@ -715,10 +736,14 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
     const float4* btris = sc.btris;
     int32_t* oprim = a.out_prim;
     float* ot = a.out_t;
-    for (;;) {
+    // One step of the wave.  Main phase (DRAIN false, while the queue lasts): idle lanes take
+    // new rays, every lane walks its own ray.  Drain (DRAIN true, the queue used up): free
+    // lanes take pending subtrees of the others (below).  Returns false when the drain ends.
+    auto step = [&](auto drain_tag) -> bool {
+        constexpr bool DRAIN = decltype(drain_tag)::value;
         // ---- refill idle lanes with the next rays of the queue
         const unsigned long long idle = __ballot(!have);
-        if (!exhausted && idle != 0 && (__popcll(idle) >= a.refill || idle == ~0ull)) {
+        if (!DRAIN && idle != 0 && (__popcll(idle) >= a.refill || idle == ~0ull)) {
             // a launch with few rays spreads them over every wave (latency hiding) instead of
             // filling the first waves' 64 lanes and leaving the others without work
             const uint32_t share = n / gridDim.x + 1u;
@@ -775,9 +800,80 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
                 }
             }
         }
+        // ---- once the queue is used up, free lanes take pending subtrees of the wave's other
+        // rays (the drain): a walking lane gives the top entry of its stack to a free lane,
+        // which walks that subtree with a copy of the ray and folds its hits into the owner's
+        // key; the owner writes the hit once no lane walks any part of its ray
+        if constexpr (DRAIN) {
+            const unsigned long long fm = idle;
+            const unsigned long long dm = __ballot(have && node != kDone && sp > 0);
+            if (fm != 0 && dm != 0) {
+                const uint32_t nf = (uint32_t)__popcll(fm), nd = (uint32_t)__popcll(dm);
+                const uint32_t np = nf < nd ? nf : nd;
+                const uint32_t rf = (uint32_t)__popcll(fm & lt), rd = (uint32_t)__popcll(dm & lt);
+                const bool helper = !have && rf < np;
+                const bool donor = ((dm >> lane) & 1ull) && rd < np;
+                const int d = nth_set_bit(dm, helper ? rf : 0u);
+                const int32_t give = donor ? stk[sp - 1][lane] : 0;
+                if (donor) --sp;
+                // the helper copies the donor's ray, field by field
+                float v;
+                v = __shfl(o.x, d); o.x = helper ? v : o.x;
+                v = __shfl(o.y, d); o.y = helper ? v : o.y;
+                v = __shfl(o.z, d); o.z = helper ? v : o.z;
+                v = __shfl(inv.x, d); inv.x = helper ? v : inv.x;
+                v = __shfl(inv.y, d); inv.y = helper ? v : inv.y;
+                v = __shfl(inv.z, d); inv.z = helper ? v : inv.z;
+                v = __shfl(rp.ox, d); rp.ox = helper ? v : rp.ox;
+                v = __shfl(rp.oy, d); rp.oy = helper ? v : rp.oy;
+                v = __shfl(rp.oz, d); rp.oz = helper ? v : rp.oz;
+                v = __shfl(rp.sx, d); rp.sx = helper ? v : rp.sx;
+                v = __shfl(rp.sy, d); rp.sy = helper ? v : rp.sy;
+                v = __shfl(rp.sz, d); rp.sz = helper ? v : rp.sz;
+                v = __shfl(tcull, d); tcull = helper ? v : tcull;
+                int u;
+                u = __shfl(rp.kx | (rp.ky << 2) | (rp.kz << 4) | ((int)flat << 6), d);
+                if (helper) {
+                    rp.kx = u & 3;
+                    rp.ky = (u >> 2) & 3;
+                    rp.kz = (u >> 4) & 3;
+                    flat = (u >> 6) != 0;
+                }
+                u = __shfl(excl, d); excl = helper ? u : excl;
+                u = __shfl(owner, d); owner = helper ? u : owner;
+                u = __shfl(give, d); node = helper ? u : node;
+                if constexpr (MULTI) {
+                    const float4* pp[3] = {nodes4, nodesf, btris};
+                    for (int j = 0; j < 3; ++j) {
+                        const uint64_t w = (uint64_t)(uintptr_t)pp[j];
+                        const uint32_t lo = (uint32_t)__shfl((uint32_t)w, d), hi = (uint32_t)__shfl((uint32_t)(w >> 32), d);
+                        pp[j] = helper ? (const float4*)(uintptr_t)(((uint64_t)hi << 32) | lo) : pp[j];
+                    }
+                    nodes4 = pp[0];
+                    nodesf = pp[1];
+                    btris = pp[2];
+                }
+                if (helper) {
+                    sp = 0;
+                    novf = 0;
+                    last = qhead - 1u;
+                    have = true;
+                }
+            }
+        }
         if (__ballot(have) == 0) {
-            if (exhausted) break;
-            continue;
+            if constexpr (DRAIN) {
+                // nothing walks: every owner's result is complete
+                if (own) {
+                    const unsigned long long k = bestk[lane];
+                    oprim[oi] = k == key0 ? -1 : (int32_t)(uint32_t)k;
+                    ot[oi] = __uint_as_float((uint32_t)(k >> 32));
+                    ++traced;
+                    own = false;
+                }
+                return false;
+            }
+            return true;
         }
         // ---- a lane on a leaf queues its triangles and takes the next node
         const bool on_leaf = have && node < 0 && node != kDone;
@@ -901,6 +997,8 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
                 r.ky = (qperm >> 2) & 3;
                 r.kz = (qperm >> 4) & 3;
                 const int32_t qexcl = __shfl(excl, src);
+                int qown = src;   // the key the hit folds into: the owner of the walking lane's ray
+                if constexpr (DRAIN) qown = __shfl(owner, src);
                 const float4* qtris = btris;
                 if constexpr (MULTI) {
                     const uint64_t bp = (uint64_t)(uintptr_t)btris;
@@ -916,7 +1014,7 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
                         if (a.touched) a.touched[a.touch_tri + (e & kQTriMask)] |= (uint8_t)a.touch_bit;
                     }
                     float th;
-                    if (tri_test(r, p0, p1, p2, th) && id != qexcl) atomicMin(&bestk[src], hit_key(th, (uint32_t)id));
+                    if (tri_test(r, p0, p1, p2, th) && id != qexcl) atomicMin(&bestk[qown], hit_key(th, (uint32_t)id));
                 }
                 const uint32_t left = qtail - qhead;
                 qhead += left < (uint32_t)kTraceBlock ? left : (uint32_t)kTraceBlock;
@@ -924,7 +1022,7 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
             } while (qtail - qhead >= (uint32_t)kTraceBlock);
             __syncthreads();   // the minima are complete; the ring slots are free again
             if (have) {
-                const unsigned long long k = bestk[lane];
+                const unsigned long long k = bestk[DRAIN ? owner : lane];
                 tcull = __uint_as_float((uint32_t)(k >> 32)) * kCullScale;
                 if (a.shadow && k != key0) {   // blocked: the shadow ray is answered
                     node = kDone;
@@ -933,15 +1031,45 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
                 }
             }
         }
-        // ---- finished rays whose tests are all done
-        if (have && node == kDone && (int32_t)(last - qhead) < 0) {
-            const unsigned long long k = bestk[lane];
-            const uint32_t kp = (uint32_t)k;
-            oprim[oi] = k == key0 ? -1 : (int32_t)kp;
-            ot[oi] = __uint_as_float((uint32_t)(k >> 32));
-            ++traced;
-            have = false;
+        // ---- walks that are finished and whose tests are all done; then the hits of owners
+        // whose ray no lane walks any more
+        if constexpr (!DRAIN) {
+            if (have && node == kDone && (int32_t)(last - qhead) < 0) {
+                const unsigned long long k = bestk[lane];
+                const uint32_t kp = (uint32_t)k;
+                oprim[oi] = k == key0 ? -1 : (int32_t)kp;
+                ot[oi] = __uint_as_float((uint32_t)(k >> 32));
+                ++traced;
+                have = false;
+            }
+        } else {
+            if (have && node == kDone && (int32_t)(last - qhead) < 0) have = false;
+            // owners some lane still walks for (wave-uniform)
+            unsigned long long walked = __ballot(have && owner == lane);
+            if (__ballot(own && !have) != 0) {
+                unsigned long long hl = __ballot(have && owner != lane);
+                while (hl != 0) {
+                    const int h = __ffsll((long long)hl) - 1;
+                    hl &= hl - 1ull;
+                    walked |= 1ull << __builtin_amdgcn_readlane(owner, h);
+                }
+            }
+            if (own && !have && ((walked >> lane) & 1ull) == 0) {
+                const unsigned long long k = bestk[lane];
+                const uint32_t kp = (uint32_t)k;
+                oprim[oi] = k == key0 ? -1 : (int32_t)kp;
+                ot[oi] = __uint_as_float((uint32_t)(k >> 32));
+                ++traced;
+                own = false;
+            }
         }
+        return true;
+    };
+    while (!exhausted) step(std::false_type{});
+    // the drain: every lane that walks owns its ray
+    own = have;
+    owner = lane;
+    while (step(std::true_type{})) {
     }
     unsigned int tsum = traced;
     for (int off = 32; off > 0; off >>= 1) tsum += __shfl_down(tsum, off);
