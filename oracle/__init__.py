@@ -64,7 +64,7 @@ def lib():
         L.orc_trace.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp]
         L.orc_trace_brute.argtypes = [vp, vp, u32, vp, vp]
         L.orc_render.restype = i32
-        L.orc_render.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, i32, i32, i32, C.c_uint64, vp, i32, vp]
+        L.orc_render.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, i32, i32, i32, i32, C.c_uint64, vp, i32, vp]
         L.orc_philox4x64_10.argtypes = [vp, vp, vp]
         L.orc_sincos2pi.argtypes = [vp, u32, vp, vp]
         L.orc_onb.argtypes = [vp, vp, vp]
@@ -143,7 +143,7 @@ class OracleScene:
         return prim, t
 
     def render(self, w, h, spp, bounces, mode="incoherent", tile=(8, 8), k=8, reuse_max_bounce=None,
-               seed=1, tile_mask=None, debug=False, camera=None, nee=False, rays=False):
+               seed=1, tile_mask=None, debug=False, camera=None, nee=False, rays=False, frame_groups=False):
         cam = camera_struct(camera or self.scene["camera"])
         B = int(bounces)
         if reuse_max_bounce is None:
@@ -177,7 +177,8 @@ class OracleScene:
             nty = (h + tile[1] - 1) // tile[1]
             assert mask.size == ntx * nty
         rc = lib().orc_render(self.h, C.byref(cam), w, h, spp, B, MODE[mode], tile[0], tile[1], k,
-                              int(reuse_max_bounce), C.c_uint64(seed), _p(mask), int(bool(nee)), C.byref(out))
+                              int(reuse_max_bounce), int(bool(frame_groups)), C.c_uint64(seed), _p(mask),
+                              int(bool(nee)), C.byref(out))
         if rc != 0:
             raise ValueError(f"orc_render failed with {rc}")
         return res

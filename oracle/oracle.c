@@ -863,7 +863,7 @@ static void nee_sample(const orc_scene* s, const opath* p, const orc_material* m
 }
 
 int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp, int B,
-               int mode, int W, int H, int K, int reuse_max_bounce, uint64_t seed,
+               int mode, int W, int H, int K, int reuse_max_bounce, int frame_groups, uint64_t seed,
                const uint8_t* tile_mask, int nee, orc_outputs* out)
 {
     if (w <= 0 || h <= 0 || spp <= 0 || B < 0 || W <= 0 || H <= 0 || K <= 0) return -1;
@@ -1032,8 +1032,12 @@ int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp,
                     for (int tx = 0; tx < ntx; ++tx) {
                         int tile = ty * ntx + tx;
                         if (tile_mask && !tile_mask[tile]) continue;
+                        /* Section 3.3: the group composition varies per tile and per frame.
+                         * frame_groups = 0 draws a new shuffle at every bounce (b); 1 keeps
+                         * the frame's first draw (bounce index 0) at every bounce, so the
+                         * members that shared a direction at one hit group again at the next. */
                         uint64_t r[4];
-                        draw(seed, (uint64_t)tile, smp, b, 1, r);
+                        draw(seed, (uint64_t)tile, smp, frame_groups ? 0 : b, 1, r);
                         uint32_t a = 1, c = 0;
                         if (mode != ORC_MODE_REUSE_PLAIN) shuffle_params(WH, r[0], r[1], &a, &c);
                         for (int sl = 0; sl < WH; ++sl) member[sl] = 0;

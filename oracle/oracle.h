@@ -78,7 +78,7 @@ void orc_trace_brute(const orc_scene* s, const float* rays, uint32_t n, int32_t*
 /* nee: next-event estimation toward the emissive triangles at Lambert scattering points
  * (not with ORC_MODE_REUSE_WORLD) */
 int orc_render(const orc_scene* s, const orc_camera* cam, int w, int h, int spp, int bounces,
-               int mode, int tile_w, int tile_h, int k, int reuse_max_bounce, uint64_t seed,
+               int mode, int tile_w, int tile_h, int k, int reuse_max_bounce, int frame_groups, uint64_t seed,
                const uint8_t* tile_mask, int nee, orc_outputs* out);
 
 /* individual steps, exported for the pins */

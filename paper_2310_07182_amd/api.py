@@ -36,7 +36,7 @@ TRAVERSALS = {"auto": 0, "pair": 1, "wide": 2, "queue": 3, "quant": 4}
 
 
 def group_struct(tile=(8, 8), k=8, reuse_max_bounce=0xFFFF, refill=0, waves_per_cu=0, leaf_gate=0,
-                 nee=False, traversal=0) -> capi.Group:
+                 nee=False, traversal=0, frame_groups=False) -> capi.Group:
     g = capi.Group()
     g.tile_w, g.tile_h = int(tile[0]), int(tile[1])
     g.k = int(k)
@@ -46,6 +46,7 @@ def group_struct(tile=(8, 8), k=8, reuse_max_bounce=0xFFFF, refill=0, waves_per_
     g.leaf_gate = int(leaf_gate)
     g.nee = int(bool(nee))
     g.traversal = TRAVERSALS[traversal] if isinstance(traversal, str) else int(traversal)
+    g.frame_groups = int(bool(frame_groups))
     return g
 
 
@@ -154,6 +155,7 @@ class RenderConfig:
     leaf_gate: int = 0
     nee: bool = False
     traversal: int | str = 0
+    frame_groups: bool = False
 
 
 class Renderer:
@@ -167,7 +169,7 @@ class Renderer:
         B = cfg.bounces
         rmax = B if cfg.reuse_max_bounce is None else cfg.reuse_max_bounce
         self.group = group_struct(cfg.tile, cfg.k, rmax, cfg.refill, cfg.waves_per_cu, cfg.leaf_gate, cfg.nee,
-                                  cfg.traversal)
+                                  cfg.traversal, cfg.frame_groups)
         self.mode = capi.MODES[cfg.mode]
         ws = lib().pt_render_workspace_bytes(cfg.w, cfg.h, cfg.spp, B, self.mode, self.group)
         if ws == 0:
@@ -235,9 +237,9 @@ class Renderer:
 
 def render(scene: Scene, w, h, spp=1, bounces=2, mode="incoherent", tile=(8, 8), k=8,
            reuse_max_bounce=None, seed=1, camera=None, stats=False, rays=False, refill=0, leaf_gate=0,
-           nee=False, traversal=0) -> dict:
+           nee=False, traversal=0, frame_groups=False) -> dict:
     r = Renderer(scene, RenderConfig(w, h, spp, bounces, mode, tuple(tile), k, reuse_max_bounce, refill, 0, leaf_gate,
-                                     nee, traversal), stats=stats, rays=rays)
+                                     nee, traversal, frame_groups), stats=stats, rays=rays)
     r.render(seed, camera)
     return r.results()
 
@@ -342,9 +344,10 @@ class Batch:
     """Jobs in flight over device-resident scenes; merged launches per step (pt_batch_*)."""
 
     def __init__(self, max_jobs: int, arena_bytes: int, tile=(8, 8), k=8, reuse_max_bounce=0xFFFF, refill=0,
-                 waves_per_cu=0, leaf_gate=0, device="cuda:0", traversal=0):
+                 waves_per_cu=0, leaf_gate=0, device="cuda:0", traversal=0, frame_groups=False):
         self.device = _require_cuda(device)
-        self.group = group_struct(tile, k, reuse_max_bounce, refill, waves_per_cu, leaf_gate, traversal=traversal)
+        self.group = group_struct(tile, k, reuse_max_bounce, refill, waves_per_cu, leaf_gate, traversal=traversal,
+                                  frame_groups=frame_groups)
         base = lib().pt_batch_base_bytes(int(max_jobs))
         if base == 0:
             raise capi.PtError(capi.PT_EINVAL, "bad max_jobs")

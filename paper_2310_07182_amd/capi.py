@@ -38,7 +38,8 @@ class Camera(C.Structure):
 class Group(C.Structure):
     _fields_ = [("tile_w", C.c_uint16), ("tile_h", C.c_uint16), ("k", C.c_uint16),
                 ("reuse_max_bounce", C.c_uint16), ("refill", C.c_uint16), ("waves_per_cu", C.c_uint16),
-                ("leaf_gate", C.c_uint16), ("nee", C.c_uint16), ("traversal", C.c_uint16)]
+                ("leaf_gate", C.c_uint16), ("nee", C.c_uint16), ("traversal", C.c_uint16),
+                ("frame_groups", C.c_uint16)]
 
 
 class SceneDesc(C.Structure):

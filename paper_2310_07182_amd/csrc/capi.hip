@@ -132,6 +132,7 @@ pt_status check_group(pt_group g, int bounces) {
     if (g.leaf_gate > 64) return fail(PT_EINVAL, "leaf_gate must be in [0, 64] (got %d)", g.leaf_gate);
     if (g.nee > 1) return fail(PT_EINVAL, "nee must be 0 or 1 (got %d)", g.nee);
     if (g.traversal > 4) return fail(PT_EINVAL, "traversal must be in [0, 4] (got %d)", g.traversal);
+    if (g.frame_groups > 1) return fail(PT_EINVAL, "frame_groups must be 0 or 1 (got %d)", g.frame_groups);
     return PT_OK;
 }
 
@@ -172,6 +173,7 @@ Frame make_frame(int w, int h, int spp, int B, pt_mode mode, pt_group g, uint64_
     f.nslots = (uint32_t)f.nstx * (uint32_t)f.nsty * (uint32_t)f.TS;
     f.seed = seed;
     f.nee = g.nee;
+    f.frame_groups = g.frame_groups;
     return f;
 }
 

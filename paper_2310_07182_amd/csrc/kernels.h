@@ -37,6 +37,7 @@ struct Frame {
     float cpos[3], cfwd[3], cright[3], cup[3];
     float th, thx;
     int nee;                  // next-event estimation at Lambert points
+    int frame_groups;         // one tile shuffle per sample (drawn at bounce 0), not one per bounce
 };
 
 // Ray queue record: {ox, oy, oz, excluded prim} {dx, dy, dz, pixel}; pixel = kNoRay: no ray.

@@ -1291,7 +1291,7 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
         uint32_t slot = 0;
         {
             const uint32_t tile = (uint32_t)(spx.y / f.H) * (uint32_t)f.ntx + (uint32_t)(spx.x / f.W);
-            const U64x4 rnd = philox(tile, (uint64_t)s, (uint64_t)b, 1, f.seed);
+            const U64x4 rnd = philox(tile, (uint64_t)s, f.frame_groups ? 0u : (uint64_t)b, 1, f.seed);
             uint32_t ma = 1, mc = 0;
             if (f.WH > 1 && f.mode != PT_MODE_REUSE_PLAIN) {
                 ma = 2u * (uint32_t)(rnd.v[0] & (uint64_t)(f.WH / 2 - 1)) + 1u;

@@ -176,6 +176,24 @@ def test_render_parity_mixed(api, orc, torch_dev, mode, tile, k, w, h, spp, B):
     _say("  ", res)
 
 
+@pytest.mark.parametrize("mode,tile,k,w,h,spp,B", [
+    ("reuse", (8, 8), 8, 101, 67, 2, 4),
+    ("reuse", (4, 4), 2, 96, 72, 1, 3),
+    ("reuse", (16, 16), 32, 100, 70, 1, 3),
+    ("reuse_world", (8, 8), 8, 77, 41, 1, 3),
+])
+def test_render_parity_frame_groups(api, orc, torch_dev, mode, tile, k, w, h, spp, B):
+    """One interleaved grouping per frame, kept at every bounce (pt_group.frame_groups)."""
+    s, sc, osc = both(api, orc, "mixed_small")
+    _say(f"[gpu] render frame_groups {w}x{h} spp={spp} B={B} mode={mode} tile={tile} k={k}")
+    g = api.render(sc, w, h, spp, B, mode, tile, k, None, 77, rays=True, frame_groups=True)
+    torch_dev.cuda.synchronize()
+    o = osc.render(w, h, spp, B, mode=mode, tile=tile, k=k, seed=77, rays=True, frame_groups=True)
+    res = compare_render(g, o, tile, mode)
+    _say("  ", res)
+    assert np.array_equal(g["rays_per_bounce"].cpu().numpy(), o["rays_per_bounce"].astype(np.int64))
+
+
 @pytest.mark.parametrize("mode,refill", [("incoherent", 1), ("sorted", 64), ("reuse", 8), ("reuse", 64),
                                          ("sorted", 1), ("incoherent", 40)])
 def test_render_parity_refill(api, orc, torch_dev, mode, refill):

@@ -123,6 +123,14 @@ MUTATIONS = [
      "W1 = 0xBB67AE8584CAA73Bull;",
      "W1 = 0xBB67AE8584CAA73Dull;",
      "philox"),
+    ("frame_groups_ignored",
+     "draw(seed, (uint64_t)tile, smp, frame_groups ? 0 : b, 1, r);",
+     "draw(seed, (uint64_t)tile, smp, b, 1, r);",
+     "composition"),
+    ("groups_never_redrawn",
+     "draw(seed, (uint64_t)tile, smp, frame_groups ? 0 : b, 1, r);",
+     "draw(seed, (uint64_t)tile, smp, 0, 1, r);",
+     "composition"),
     ("nee_light_count_dropped",
      "float k = g * ((float)s->nemit * (float)(1.0 / (2.0 * 3.14159265358979323846)));",
      "float k = g * (float)(1.0 / (2.0 * 3.14159265358979323846));",

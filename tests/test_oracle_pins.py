@@ -459,6 +459,48 @@ def _pairwise_sum(vecs):
     return v[0]
 
 
+@pytest.mark.parametrize("frame_groups", [False, True])
+def test_group_composition_per_bounce_or_per_frame(orc, frame_groups):
+    """Section 3.3: the group composition varies per tile and per frame.  At every reuse
+    bounce b the slots of the active pixels are the affine shuffle of the tile draw with
+    counter (tile, sample, b, stream 1), or (tile, sample, 0, 1) at every bounce of the
+    sample when the frame keeps one grouping; the slots are recomputed here from that draw."""
+    s = scenes.mixed_small()
+    sc = orc.OracleScene(s)
+    W, H, k, w, h, B, spp, seed = 8, 8, 8, 64, 48, 3, 2, 37
+    r = sc.render(w, h, spp, B, mode="reuse", tile=(W, H), k=k, seed=seed, debug=True, frame_groups=frame_groups)
+    differs = 0
+    for smp in range(spp):
+        for b in range(B):
+            fl = r["dbg_flags"][b, smp]
+            for ty in range(h // H):
+                for tx in range(w // W):
+                    f = fl[ty * H:(ty + 1) * H, tx * W:(tx + 1) * W].ravel()
+                    act = (f & orc.F_ACTIVE) != 0
+                    slot = (f >> orc.F_SLOT_SH) & 0xFFFF
+                    x = orc.philox((ty * (w // W) + tx, smp, 0 if frame_groups else b, 1), (seed, 0))
+                    assert np.array_equal(slot[act], _affine_slots(W * H, int(x[0]), int(x[1]))[act])
+                    if b > 0:
+                        x0 = orc.philox((ty * (w // W) + tx, smp, 0, 1), (seed, 0))
+                        differs += int(not np.array_equal(slot[act], _affine_slots(W * H, int(x0[0]), int(x0[1]))[act]))
+    assert (differs == 0) == frame_groups
+
+
+def test_frame_groups_equal_at_first_bounce_only(orc):
+    """With reuse at the first shading point only (reuse_max_bounce = 1), keeping the
+    frame's grouping changes nothing: both draw the tile shuffle at bounce index 0.  With
+    reuse at every bounce the two groupings give different images."""
+    sc = orc.OracleScene(scenes.mixed_small())
+    a = sc.render(72, 40, 1, 3, mode="reuse", tile=(8, 8), k=8, reuse_max_bounce=1, seed=5)
+    b = sc.render(72, 40, 1, 3, mode="reuse", tile=(8, 8), k=8, reuse_max_bounce=1, seed=5, frame_groups=True)
+    for key in ("radiance", "hit_prim", "hit_t"):
+        assert np.array_equal(a[key].view(np.uint32), b[key].view(np.uint32))
+    c = sc.render(72, 40, 1, 3, mode="reuse", tile=(8, 8), k=8, seed=5)
+    d = sc.render(72, 40, 1, 3, mode="reuse", tile=(8, 8), k=8, seed=5, frame_groups=True)
+    assert np.array_equal(c["hit_prim"][:2], d["hit_prim"][:2])
+    assert not np.array_equal(c["hit_prim"][2:], d["hit_prim"][2:])
+
+
 @pytest.mark.parametrize("tile,k,mode", [((4, 4), 4, "reuse"), ((8, 8), 8, "reuse"), ((8, 8), 8, "reuse_plain"),
                                          ((4, 4), 2, "reuse_plain")])
 def test_reuse_rules_per_category(orc, tile, k, mode):
