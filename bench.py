@@ -29,7 +29,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-NODE_BYTES, TRI_BYTES, RAY_BYTES, HIT_BYTES = 64, 48, 32, 8
+# algorithmic bytes per unit of traversal work: a node as the kernel reads it, a triangle as
+# 36 bytes of vertices + its 4-byte id (the kernel's float4 layout reads 48), the ray and the hit
+NODE_BYTES, TRI_BYTES, RAY_BYTES, HIT_BYTES = 64, 40, 32, 8
 # 32-bit VALU lane operations per unit of traversal work (counted from the kernel source):
 # a node visit = two slab tests (6 sub, 6 mul, 10 min/max, 1 mul, 2 cmp, 1 and = 26 each)
 # plus the near/far choice (~6); a triangle test = 9 sub, 12 mul, 9 sub of the shear and
@@ -80,7 +82,7 @@ def traversal_kind(sc, trav="auto"):
     """The traversal kernel that runs: the one asked for, else the one the library picks."""
     if trav != "auto":
         return trav
-    inf = sc.info()
+    inf = sc if isinstance(sc, dict) else sc.info()
     if inf["wide"] and inf["ntri"] <= (1 << 26):
         return "quant" if inf["quant"] else "queue"
     return "wide" if inf["wide"] else "pair"
@@ -107,11 +109,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bench_mode(api, sc, cfg, mode, steps, warmup, seed0, nee=False, trav="auto"):
+def bench_mode(api, sc, cfg, mode, steps, warmup, seed0, nee=False, trav="auto", tile=None, k=None,
+               frame_groups=False, reuse_max_bounce=None, latency_frames=0):
+    """Timed frames of one mode: W untimed frames, then exactly `steps` timed frames (the
+    value), then `latency_frames` more for the frame-latency percentiles."""
     import torch
     node_bytes, ops_node = node_costs(sc, trav)
-    rc = api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], mode, tuple(cfg["tile"]), cfg["k"], nee=nee,
-                          traversal=trav)
+    tile = tuple(cfg["tile"]) if tile is None else tuple(tile)
+    k = cfg["k"] if k is None else k
+    rc = api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], mode, tile, k, nee=nee, traversal=trav,
+                          frame_groups=frame_groups, reuse_max_bounce=reuse_max_bounce)
     # untimed counting frame: nodes / triangles per ray and rays per bounce
     rs = api.Renderer(sc, rc, stats=True, touched=True)
     rs.render(seed0)
@@ -143,6 +150,20 @@ def bench_mode(api, sc, cfg, mode, steps, warmup, seed0, nee=False, trav="auto")
     wall = time.perf_counter() - t0
     frame_ms = np.array([a.elapsed_time(b) for a, b in ev])
     ms, kind, bounce = timer.read()
+    # more frames, after the timed region, for the latency percentiles only
+    lat_ms = list(frame_ms)
+    if latency_frames > 0:
+        r2 = api.Renderer(sc, rc)
+        evl = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(latency_frames)]
+        for i in range(latency_frames):
+            evl[i][0].record(st)
+            r2.render(seed0 + 50000 + i)
+            evl[i][1].record(st)
+        torch.cuda.synchronize()
+        lat_ms += [a.elapsed_time(b) for a, b in evl]
+        del r2
+    lat_ms = np.array(lat_ms)
     # rays of the last frame (identical statistics every frame; counted on the device)
     rays = r.ray_count.cpu().numpy().reshape(-1).astype(np.float64)
     B = cfg["bounces"]
@@ -162,16 +183,24 @@ def bench_mode(api, sc, cfg, mode, steps, warmup, seed0, nee=False, trav="auto")
     bytes_per_launch = bytes_per_ray * sec_rays / B
     ops_per_ray = nodes_per_ray * ops_node + tris_per_ray * OPS_PER_TRI
     ops_per_launch = ops_per_ray * sec_rays / B
-    kinds = {int(k): float(ms[kind == k].sum() / steps) for k in np.unique(kind)}
+    kinds = {int(kk): float(ms[kind == kk].sum() / steps) for kk in np.unique(kind)}
+    # per bounce: mean traversal and shade launch time; per frame: the secondary trace rate
+    trace_us = [float(ms[trace & (bounce == bb)].mean() * 1e3) for bb in range(B + 1)]
+    shade_us = [float(ms[(kind == 2) & (bounce == bb)].mean() * 1e3) for bb in range(B + 1)]
+    per_frame_sec = ms[sec].reshape(steps, -1).sum(axis=1)
+    frame_rates = sec_rays / (per_frame_sec * 1e-3) / 1e6
     shadow = {}
     if nee:
         srays = r.shadow_count.cpu().numpy().astype(np.float64).sum()
         sms = ms[kind == 7].sum() / steps
         shadow = dict(shadow_rays_per_frame=int(srays), shadow_trace_ms_per_frame=float(sms),
                       shadow_mrays_s=float(srays / (sms * 1e-3) / 1e6) if sms > 0 else 0.0)
-    return dict(mode=mode, secondary_mrays_s=mrays, end_to_end_secondary_mrays_s=e2e,
-                frame_ms_mean=float(frame_ms.mean()), frame_ms_p50=float(np.percentile(frame_ms, 50)),
-                frame_ms_p99=float(np.percentile(frame_ms, 99)), wall_s=wall,
+    return dict(mode=mode, tile=list(tile), k=k, frame_groups=bool(frame_groups), reuse_max_bounce=reuse_max_bounce,
+                secondary_mrays_s=mrays, end_to_end_secondary_mrays_s=e2e,
+                secondary_mrays_s_frame_sd=float(frame_rates.std()),
+                trace_us_per_bounce=trace_us, shade_us_per_bounce=shade_us,
+                frame_ms_mean=float(frame_ms.mean()), frame_ms_p50=float(np.percentile(lat_ms, 50)),
+                frame_ms_p99=float(np.percentile(lat_ms, 99)), latency_frames=int(len(lat_ms)), wall_s=wall,
                 trace_ms_per_frame=float(per_frame_trace_ms), secondary_trace_ms_per_frame=float(per_frame_sec_ms),
                 rays_per_bounce=[int(v) for v in rays], nodes_per_ray=float(nodes_per_ray),
                 tris_per_ray=float(tris_per_ray), bytes_per_ray=float(bytes_per_ray),
@@ -495,12 +524,215 @@ def bench_quality(api, sc, cfg, args):
     return out
 
 
+def _csv_rows(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_profile(config, prof_dir, out_path, modes, bounces, counters):
+    """Writes the text summary of a profiled `bench.py --config CONFIG --profile` run: the
+    kernel-trace table, traversal launch times per mode and bounce, the counters per launch
+    and the machine-readable lines the bench reads.  prof_dir holds pf_CONFIG_kt (kernel
+    trace, stats and log) and pf_CONFIG_pmcI (one counter run each, in `counters` order)."""
+    import glob
+    import hashlib
+    B1 = bounces + 1
+    nm = len(modes)
+    trace_name = "k_trace_q<false, false, true>"
+
+    def trace_rows(rows, key="Kernel_Name"):
+        return [r for r in rows if trace_name in r[key]]
+
+    def mapping(n_dispatch):
+        # 20 warm-up frames, then per mode 3 frames of B+1 launches; frames 1 and 2 are profiled
+        assert n_dispatch == (20 + 3 * nm) * B1, (n_dispatch, (20 + 3 * nm) * B1)
+        out = {}
+        for i, m in enumerate(modes):
+            for fr in (1, 2):
+                for b in range(B1):
+                    out.setdefault((m, b), []).append((20 + 3 * i + fr) * B1 + b)
+        return out
+
+    kt_dir = os.path.join(prof_dir, f"pf_{config}_kt")
+    kt = _csv_rows(glob.glob(os.path.join(kt_dir, "*kernel_trace.csv"))[0])
+    stats = _csv_rows(glob.glob(os.path.join(kt_dir, "*kernel_stats.csv"))[0])
+    tr = trace_rows(kt)
+    tr.sort(key=lambda r: int(r["Dispatch_Id"]))
+    mp = mapping(len(tr))
+    dur = {k: np.mean([(int(tr[i]["End_Timestamp"]) - int(tr[i]["Start_Timestamp"])) / 1e3 for i in v])
+           for k, v in mp.items()}
+    counts = {}
+    with open(os.path.join(prof_dir, f"pf_{config}_kt.log")) as f:
+        for line in f:
+            if "[profile] counts " in line:
+                c = json.loads(line.split("[profile] counts ", 1)[1])
+                counts[c["mode"]] = c
+    # counters: per run, per (mode, bounce) mean over the profiled frames; copy calibration
+    ctr = {}
+    calib = {}
+    for j, names in enumerate(counters, start=1):
+        rows = _csv_rows(glob.glob(os.path.join(prof_dir, f"pf_{config}_pmc{j}", "*counter_collection.csv"))[0])
+        per = {}
+        for r in rows:
+            per.setdefault((int(r["Dispatch_Id"]), r["Kernel_Name"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+        disp = sorted(per.items(), key=lambda kv: kv[0][0])
+        tdisp = [v for (d, name), v in disp if trace_name in name]
+        m2 = mapping(len(tdisp))
+        for nme in names.split():
+            for k, idx in m2.items():
+                ctr.setdefault(nme, {})[k] = float(np.mean([tdisp[i].get(nme, np.nan) for i in idx]))
+            if nme in ("FETCH_SIZE", "WRITE_SIZE"):
+                calib[nme] = max(v.get(nme, 0.0) for (d, name), v in disp if "copyBuffer" in name)
+    gib_kib = float(1 << 20)
+    fac = {k: gib_kib / v for k, v in calib.items() if v > 0}
+    digest = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            digest.update(f.read())
+    sha = digest.hexdigest()
+    L = []
+    L.append(f"# {trace_name.split('<')[0]} (closest-hit traversal over quantized four-wide nodes, per-wave triangle-test "
+             f"queue), {config} 1920x1080, 1 spp, {bounces} bounces")
+    L.append("")
+    L.append("Workload: the seeded scene; one counting frame per mode (a separate counting instantiation of the "
+             "kernel), 20 warm-up frames, then per mode one warm-up and two profiled frames "
+             f"({B1} traversal launches each: bounce 0 = primary rays, 1..{bounces} = secondary), then a 1 GiB "
+             "device-to-device copy that calibrates the byte counters.")
+    L.append("")
+    L.append("Commands (from the repository root, `export TMPDIR=/tmp` first), then this summary:")
+    L.append("")
+    L.append("```")
+    L.append(f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/pf_{config}_kt -o kt -- "
+             f"python -u bench.py --config {config} --profile > gpurun_out/pf_{config}_kt.log 2>&1")
+    for j, names in enumerate(counters, start=1):
+        L.append(f"timeout -s KILL 300 rocprofv3 --pmc {names} --output-format csv -d gpurun_out/pf_{config}_pmc{j} "
+                 f"-o pmc -- python -u bench.py --config {config} --profile")
+    L.append(f"python bench.py --summarize-profile gpurun_out --config {config}")
+    L.append("```")
+    L.append("")
+    L.append("## Kernel trace summary (rocprofv3 --stats, all kernels of the run)")
+    L.append("")
+    L.append("| kernel | calls | total ms | avg us | min us | max us |")
+    L.append("|---|---|---|---|---|---|")
+    for r in stats[:14]:
+        nm_ = r["Name"].replace("pt::(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+        L.append(f"| {nm_} | {r['Calls']} | {int(r['TotalDurationNs']) / 1e6:.3f} | {float(r['AverageNs']) / 1e3:.1f} | "
+                 f"{int(r['MinNs']) / 1e3:.1f} | {int(r['MaxNs']) / 1e3:.1f} |")
+    L.append("")
+    L.append("## Traversal launch duration per mode and bounce (kernel trace, mean of the two profiled frames, us)")
+    L.append("")
+    L.append("| mode | " + " | ".join(f"b{b}" for b in range(B1)) + f" | mean b1..b{bounces} |")
+    L.append("|---|" + "---|" * (B1 + 1))
+    mean_sec = {}
+    for m in modes:
+        mean_sec[m] = float(np.mean([dur[(m, b)] for b in range(1, B1)]))
+        L.append(f"| {m} | " + " | ".join(f"{dur[(m, b)]:.1f}" for b in range(B1)) + f" | {mean_sec[m]:.1f} |")
+    L.append("")
+    if fac:
+        L.append("Byte calibration from the 1 GiB copy: " + ", ".join(
+            f"{k} reads {calib[k]:.0f} KiB for 1,048,576 KiB (factor {fac[k]:.4f})" for k in sorted(fac)) +
+            ". MB below = KiB x factor x 1024 / 1e6. FETCH_SIZE counts L2 misses served by the fabric (MALL hits "
+            "included), an upper bound on HBM reads.")
+        L.append("")
+    cols = []
+
+    def g(nme, k):
+        return ctr.get(nme, {}).get(k, float("nan"))
+
+    L.append("## Counters per traversal launch (mean of the two profiled frames)")
+    L.append("")
+    table = []
+    traffic, lane_ops = {}, {}
+    for m in modes:
+        tb, lo = [], []
+        for b in range(B1):
+            k = (m, b)
+            rd = g("FETCH_SIZE", k) * fac.get("FETCH_SIZE", float("nan")) * 1024
+            wr = g("WRITE_SIZE", k) * fac.get("WRITE_SIZE", float("nan")) * 1024
+            util = g("SQ_THREAD_CYCLES_VALU", k) / (64.0 * g("SQ_ACTIVE_INST_VALU", k))
+            gui = g("GRBM_GUI_ACTIVE", k) / 8.0
+            row = {"fabric read MB": rd / 1e6, "write MB": wr / 1e6,
+                   "L2 hit": g("TCC_HIT_sum", k) / (g("TCC_HIT_sum", k) + g("TCC_MISS_sum", k)),
+                   "VALU Minstr": g("SQ_INSTS_VALU", k) / 1e6, "VALU lane util": util,
+                   "VALU issue": g("SQ_INSTS_VALU", k) * 4.0 / 1024.0 / gui,
+                   "SALU Minstr": g("SQ_INSTS_SALU", k) / 1e6,
+                   "TA busy": g("TA_TA_BUSY_sum", k) / 256.0 / gui, "TD busy": g("TD_TD_BUSY_sum", k) / 256.0 / gui,
+                   "L1 lines / mem instr": g("TCP_TOTAL_CACHE_ACCESSES_sum", k) / g("SQ_INSTS_VMEM", k)}
+            table.append((m, b, row))
+            if b >= 1:
+                tb.append(rd + wr)
+                lo.append(g("SQ_INSTS_VALU", k) * 64.0 * util)
+        traffic[m] = float(np.mean(tb))
+        lane_ops[m] = float(np.mean(lo))
+    # columns the counter runs of this workload cover
+    cols = [c for c in table[0][2] if not all(np.isnan(r[c]) for _, _, r in table)]
+    L.append("| mode | bounce | " + " | ".join(cols) + " |")
+    L.append("|---|---|" + "---|" * len(cols))
+    for m, b, row in table:
+        L.append(f"| {m} | {b} | " + " | ".join(f"{row[c]:.3f}" if row[c] < 10 else f"{row[c]:.1f}" for c in cols) + " |")
+    L.append("")
+    L.append("VALU lane util = SQ_THREAD_CYCLES_VALU / (64 x SQ_ACTIVE_INST_VALU), the fraction of the 64 lanes active "
+             "per VALU instruction. VALU issue = VALU instructions x 4 cycles / 1024 SIMDs / (GRBM_GUI_ACTIVE / 8). "
+             "TA / TD busy = busy cycles summed over the 256 CUs / 256 / the same cycles. L1 lines / mem instr = "
+             "TCP_TOTAL_CACHE_ACCESSES / SQ_INSTS_VMEM. Counters come from separate runs of the same sequence.")
+    L.append("")
+    L.append("## Roofline per secondary traversal launch (mean over bounces 1..%d)" % bounces)
+    L.append("")
+    L.append("Algorithmic bytes per ray = nodes x node bytes + triangles x 40 B + 32 B ray + 8 B hit, nodes and "
+             "triangles per secondary ray from the counting frame; frac = algorithmic bytes per launch / mean launch "
+             "time / 8 TB/s. Executed lane-ops = SQ_INSTS_VALU x 64 x lane util (all VALU work, overhead included), "
+             "against 256 CUs x 64 lanes x 2.4 GHz = 39.3 T lane-op/s.")
+    L.append("")
+    L.append("| mode | nodes / ray | tris / ray | alg. bytes / ray | rays / launch | alg. bytes / launch | mean launch us | "
+             "alg. GB/s | frac of 8 TB/s | counted traffic / launch | traffic GB/s | executed lane-ops / launch | "
+             "executed frac of VALU |")
+    L.append("|---|---|---|---|---|---|---|---|---|---|---|---|---|")
+    for m in modes:
+        c = counts.get(m)
+        t = mean_sec[m] * 1e-6
+        if c:
+            abl = c["bytes_per_ray"] * c["rays_per_launch"]
+            L.append(f"| {m} | {c['nodes_per_ray']:.2f} | {c['tris_per_ray']:.2f} | {c['bytes_per_ray']:.1f} | "
+                     f"{c['rays_per_launch']:.0f} | {abl:.4g} | {mean_sec[m]:.1f} | {abl / t / 1e9:.0f} | "
+                     f"{abl / t / 1e9 / HBM_PEAK_GBS:.3f} | {traffic[m]:.4g} | {traffic[m] / t / 1e9:.0f} | "
+                     f"{lane_ops[m]:.4g} | {lane_ops[m] / t / 1e12 / VALU_PEAK_TOPS:.3f} |".replace("nan", "-"))
+    L.append("")
+    L.append("Machine-readable lines read by bench.py (source digest of kernels.hip, kernels.h, capi.hip and build.py "
+             "when the counters were taken):")
+    L.append("")
+    L.append("```")
+    L.append("traffic_bytes_per_launch " + " ".join(f"{m}={traffic[m]:.6g}" for m in modes) + f" source_sha256={sha}")
+    if not any(np.isnan(v) for v in lane_ops.values()):
+        L.append("valu_lane_ops_per_launch " + " ".join(f"{m}={lane_ops[m]:.6g}" for m in modes) +
+                 f" source_sha256={sha}")
+    L.append("mean_launch_us " + " ".join(f"{m}={mean_sec[m]:.1f}" for m in modes) + f" source_sha256={sha}")
+    L.append("```")
+    with open(out_path, "w") as f:
+        f.write("\n".join(L) + "\n")
+    return out_path
+
+
+PROFILE_COUNTERS = {
+    "indoor": ("FETCH_SIZE", "WRITE_SIZE",
+               "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
+               "SQ_WAIT_INST_ANY",
+               "TCC_HIT_sum TCC_MISS_sum TCP_TOTAL_CACHE_ACCESSES_sum TCP_TCC_READ_REQ_sum GRBM_GUI_ACTIVE",
+               "SQ_THREAD_CYCLES_VALU SQ_ACTIVE_INST_VALU",
+               "TA_TA_BUSY_sum TD_TD_BUSY_sum TCP_TOTAL_CACHE_ACCESSES_sum SQ_INSTS_VMEM GRBM_GUI_ACTIVE"),
+    "landscape": ("FETCH_SIZE", "WRITE_SIZE", "SQ_THREAD_CYCLES_VALU SQ_ACTIVE_INST_VALU"),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="indoor")
+    ap.add_argument("--config", default="all",
+                    help="all (indoor, then landscape: the default run) or one of the scene configs")
+    ap.add_argument("--latency-frames", type=int, default=200,
+                    help="frames rendered after the timed ones, for the p50/p99 frame latency")
     ap.add_argument("--modes", default="reuse,incoherent,sorted")
     ap.add_argument("--traversal", default="auto", choices=["auto", "pair", "wide", "queue", "quant"],
                     help="traversal kernel of the frame runs (pt_group.traversal); auto = the library's choice")
@@ -527,6 +759,8 @@ def main():
                     help="PSNR against a many-frame reference and the (W,H) x K speed sweep")
     ap.add_argument("--quality-frames", type=int, default=128)
     ap.add_argument("--quality-ref", type=int, default=4096)
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="write profiles/k_trace_CONFIG_1080p.md from the rocprofv3 runs of --profile under DIR")
     ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-part", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-parts", type=int, default=1, help=argparse.SUPPRESS)
@@ -535,6 +769,14 @@ def main():
     args = ap.parse_args()
     if args.cpu_worker:
         cpu_worker(args)
+        return
+    if args.summarize_profile:
+        from paper_2310_07182_amd import scenes
+        name = "indoor" if args.config == "all" else args.config
+        out = PROFILE_SUMMARY.format(config=name)
+        summarize_profile(name, args.summarize_profile, out, args.modes.split(","),
+                          scenes.CONFIGS[name]["bounces"], PROFILE_COUNTERS[name])
+        print(out)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {args.gpus}); "
@@ -557,6 +799,12 @@ def main():
             line["serving"], line["serving_setup"] = bench_serve(api, serve, scs, args)
         print(json.dumps(line), flush=True)
         return
+    if not (args.quality or args.profile):
+        line = bench_frames(api, scenes, args, torch)
+        print(json.dumps(line), flush=True)
+        return
+    if args.config == "all":
+        args.config = "indoor"
     cfg = dict(scenes.CONFIGS[args.config])
     t0 = time.perf_counter()
     scene = cfg["scene"]()
@@ -583,6 +831,22 @@ def main():
         torch.cuda.synchronize()
         del rw
         log("[profile] 20 warm-up frames")
+        # counting frame per mode (a separate, counting instantiation of the traversal kernel):
+        # nodes and triangles per secondary ray and rays per launch, the algorithmic bytes of the summary
+        node_bytes, _ = node_costs(sc, args.traversal)
+        for i, mode in enumerate(args.modes.split(",")):
+            rs = api.Renderer(sc, api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], mode, tuple(cfg["tile"]),
+                                                   cfg["k"], traversal=args.traversal), stats=True)
+            rs.render(2310071821 + 10 * i)
+            torch.cuda.synchronize()
+            st = rs.stats.cpu().numpy().astype(np.float64)
+            rc_ = rs.ray_count.cpu().numpy().reshape(-1).astype(np.float64)
+            npr, tpr = st[1:, 0].sum() / rc_[1:].sum(), st[1:, 1].sum() / rc_[1:].sum()
+            bpr = npr * node_bytes + tpr * TRI_BYTES + RAY_BYTES + HIT_BYTES
+            log("[profile] counts " + json.dumps({"mode": mode, "nodes_per_ray": npr, "tris_per_ray": tpr,
+                                                  "node_bytes": node_bytes, "bytes_per_ray": bpr,
+                                                  "rays_per_launch": rc_[1:].sum() / cfg["bounces"]}))
+            del rs
         for i, mode in enumerate(args.modes.split(",")):
             r = api.Renderer(sc, api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], mode, tuple(cfg["tile"]),
                                                   cfg["k"], traversal=args.traversal))
@@ -597,6 +861,116 @@ def main():
         torch.cuda.synchronize()
         log("[profile] copy of 1 GiB done")
         return
+
+
+# Rows of the default run: (label, mode, tile, K, frame_groups, reuse_max_bounce); None = the
+# config's own tile / K / every bounce.  The first row is the headline.
+INDOOR_POINTS = (("reuse", "reuse", None, None, False, None),
+                 ("incoherent", "incoherent", None, None, False, None),
+                 ("sorted", "sorted", None, None, False, None),
+                 ("reuse_frame_groups", "reuse", None, None, True, None),
+                 ("reuse_first_bounce", "reuse", None, None, False, 1),
+                 ("reuse_4x4_k2", "reuse", (4, 4), 2, False, None))
+LANDSCAPE_POINTS = (("reuse", "reuse", None, None, False, None),
+                    ("incoherent", "incoherent", None, None, False, None),
+                    ("sorted", "sorted", None, None, False, None),
+                    ("reuse_frame_groups", "reuse", None, None, True, None))
+
+
+def profile_figures(mode, config):
+    """Per secondary traversal launch, from the committed rocprofv3 summary of this kernel and
+    workload: counted traffic (FETCH_SIZE + WRITE_SIZE, calibrated bytes) and executed VALU
+    lane operations (SQ_THREAD_CYCLES_VALU-based); None for figures taken from other sources."""
+    import hashlib
+    path = PROFILE_SUMMARY.format(config=config)
+    out = {}
+    if not os.path.exists(path):
+        return out
+    digest = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            digest.update(f.read())
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) < 2 or parts[0] not in ("traffic_bytes_per_launch", "valu_lane_ops_per_launch",
+                                                  "mean_launch_us"):
+                continue
+            fields = dict(kv.split("=", 1) for kv in parts[1:])
+            if fields.get("source_sha256") == digest.hexdigest() and mode in fields:
+                out[parts[0]] = float(fields[mode])
+    return out
+
+
+def roofline(head, sc, trav, ceil, config, level):
+    """The traversal kernel's roofline over the secondary bounces of the headline mode.
+    Primary bound: algorithmic bytes (nodes x node bytes + triangles x 40 B + 32 B ray + 8 B
+    hit per traced ray, node and triangle counts from the counting frame) per launch over the
+    mean launch time, against the 8 TB/s HBM peak.  Second bound: the VALU, algorithmic lane
+    operations per launch over the launch time against 256 CUs x 64 lanes x 2.4 GHz."""
+    t = head["avg_trace_launch_ms"] * 1e-3
+    gbs = head["bytes_per_launch"] / t / 1e9
+    ops = head["ops_per_launch"] / t / 1e12
+    prof = profile_figures(head["mode"], config) if trav == "auto" else {}
+    traffic = prof.get("traffic_bytes_per_launch")
+    counted_ops = prof.get("valu_lane_ops_per_launch")
+    rays_per_launch = head["bytes_per_launch"] / head["bytes_per_ray"]
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": round(traffic) if traffic else None,
+            "kernel": kernel_label(sc, trav) + ", secondary bounces",
+            "unit_of_work": "one traced secondary ray",
+            "bytes_per_ray_formula": f"nodes x {node_costs(sc, trav)[0]} B + triangles x {TRI_BYTES} B + "
+                                     f"{RAY_BYTES} B ray + {HIT_BYTES} B hit",
+            "nodes_per_ray": round(head["nodes_per_ray"], 2), "tris_per_ray": round(head["tris_per_ray"], 2),
+            "algorithmic_bytes_per_ray": round(head["bytes_per_ray"], 1),
+            "rays_per_launch": round(rays_per_launch),
+            "algorithmic_bytes_per_launch": round(head["bytes_per_launch"]),
+            "mean_launch_us": round(head["avg_trace_launch_ms"] * 1e3, 1),
+            "compulsory_bytes_per_launch": round(head["compulsory_bytes_per_launch"]),
+            "traffic_over_compulsory": round(traffic / head["compulsory_bytes_per_launch"], 2) if traffic else None,
+            "traffic_GBps": round(traffic / t / 1e9, 1) if traffic else None,
+            "working_set_level": level, "measured_ceiling_GBps": ceil[level]["read_GBps"] if ceil else None,
+            "algorithmic_frac_of_measured_ceiling": round(gbs / ceil[level]["read_GBps"], 4) if ceil else None,
+            "valu": {"achieved": round(ops, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "T lane-op/s",
+                     "frac": round(ops / VALU_PEAK_TOPS, 4), "ops_per_ray": round(head["ops_per_ray"], 1),
+                     "op": "32-bit VALU lane operation (compare/min/max/select counted like add/mul), "
+                           "hand-counted per node visit and triangle test",
+                     "executed_lane_ops_per_launch": round(counted_ops) if counted_ops else None,
+                     "executed_frac": round(counted_ops / t / 1e12 / VALU_PEAK_TOPS, 4) if counted_ops else None}}
+
+
+def _mode_summary(v, nee=False):
+    return {"mode": v["mode"], "tile": v["tile"], "k": v["k"], "frame_groups": v["frame_groups"],
+            "reuse_max_bounce": v["reuse_max_bounce"],
+            "secondary_mrays_s": round(v["secondary_mrays_s"], 3),
+            "secondary_mrays_s_frame_sd": round(v["secondary_mrays_s_frame_sd"], 2),
+            "end_to_end_secondary_mrays_s": round(v["end_to_end_secondary_mrays_s"], 3),
+            "frame_ms_p50": round(v["frame_ms_p50"], 4), "frame_ms_p99": round(v["frame_ms_p99"], 4),
+            "latency_frames": v["latency_frames"],
+            "trace_us_per_bounce": [round(x, 1) for x in v["trace_us_per_bounce"]],
+            "shade_us_per_bounce": [round(x, 1) for x in v["shade_us_per_bounce"]],
+            "ms_by_kind": {TIMER_KIND_NAMES.get(kk, str(kk)): round(x, 4) for kk, x in v["ms_by_kind"].items()},
+            "rays_per_bounce": v["rays_per_bounce"], "nodes_per_ray": round(v["nodes_per_ray"], 2),
+            "tris_per_ray": round(v["tris_per_ray"], 2),
+            "compulsory_bytes_per_bounce": [round(x) for x in v["compulsory_bytes_per_bounce"]],
+            **({"shadow_mrays_s": round(v["shadow_mrays_s"], 3),
+                "shadow_rays_per_frame": v["shadow_rays_per_frame"]} if nee else {})}
+
+
+TIMER_KIND_NAMES = {0: "trace", 1: "raygen", 2: "shade", 3: "key", 4: "sort", 5: "gather", 6: "other",
+                    7: "shadow_trace", 8: "shadow_accumulate"}
+
+
+def bench_config(api, scenes, name, points, args, torch):
+    cfg = dict(scenes.CONFIGS[name])
+    t0 = time.perf_counter()
+    scene = cfg["scene"]()
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sc = api.Scene(scene, device="cuda:0")
+    build_s = time.perf_counter() - t0
+    log(f"[bench] {name}: {scene.ntri} triangles, generated in {gen_s:.1f} s, BVH+upload {build_s:.1f} s, "
+        f"info {sc.info()}")
     # the same untimed warm-up before every mode's own warm-up, so the first mode does not meet
     # a GPU whose clocks are still ramping up
     rw = api.Renderer(sc, api.RenderConfig(cfg["w"], cfg["h"], 1, cfg["bounces"], "incoherent", tuple(cfg["tile"]),
@@ -606,28 +980,53 @@ def main():
     torch.cuda.synchronize()
     del rw
     results = {}
-    for i, mode in enumerate(args.modes.split(",")):
-        log(f"[bench] mode {mode}: warmup {args.warmup}, steps {args.steps}")
-        results[mode] = bench_mode(api, sc, cfg, mode, args.steps, args.warmup, 2310071821 + 100000 * i, args.nee,
-                                   args.traversal)
-        log(f"[bench] {mode}: {json.dumps(results[mode])}")
-    head = results.get("reuse") or next(iter(results.values()))
+    for i, (label, mode, tile, k, fg, rmax) in enumerate(points):
+        log(f"[bench] {name} {label}: warmup {args.warmup}, steps {args.steps}, then {args.latency_frames} latency frames")
+        results[label] = bench_mode(api, sc, cfg, mode, args.steps, args.warmup, 2310071821 + 100000 * i, args.nee,
+                                    args.traversal, tile, k, fg, rmax, args.latency_frames)
+        log(f"[bench] {name} {label}: {json.dumps(results[label])}")
+    level = "mall" if sc.arena.numel() <= MALL_BYTES else "hbm"
+    info = dict(scene=scene, sc=sc, sc_info=sc.info(), cfg=cfg, level=level, ntri=int(scene.ntri),
+                gen_s=gen_s, build_s=build_s)
+    return results, info
+
+
+def bench_frames(api, scenes, args, torch):
+    """The default run: every configured workload, its modes and extra points, the memory
+    ceilings, the roofline of the traversal kernel and the CPU oracle baseline."""
+    if args.config == "all":
+        plan = [("indoor", INDOOR_POINTS), ("landscape", LANDSCAPE_POINTS)]
+    else:
+        plan = [(args.config, tuple((m, m, None, None, False, None) for m in args.modes.split(",")))]
+    out = {}
+    for name, points in plan:
+        res, info = bench_config(api, scenes, name, points, args, torch)
+        out[name] = (res, info)
+        if name != plan[0][0]:
+            # large scenes leave the device before the next one is built
+            del info["sc"], info["scene"]
+            torch.cuda.empty_cache()
     log("[bench] memory ceilings")
     ceil = measure_ceilings(api)
     log(f"[bench] ceilings: {ceil}")
-    level = "mall" if sc.arena.numel() <= MALL_BYTES else "hbm"
+    name0 = plan[0][0]
+    res0, info0 = out[name0]
+    head = next(iter(res0.values()))
+    cfg0 = info0["cfg"]
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle, bounded sample)")
-        single = cpu_baseline(scene, cfg, args.config, args.cpu_budget)
+        single = cpu_baseline(info0["scene"], cfg0, name0, args.cpu_budget)
         log(f"[bench] cpu baseline, one core: {single}")
         log("[bench] cpu baseline on every host core")
-        cpu = cpu_baseline_all_cores(cfg, args.config, single)
+        cpu = cpu_baseline_all_cores(cfg0, name0, single)
         log(f"[bench] cpu baseline, all cores: {cpu}")
-    achieved_ops = head["ops_per_launch"] / (head["avg_trace_launch_ms"] * 1e-3) / 1e12
-    achieved_gbs = head["bytes_per_launch"] / (head["avg_trace_launch_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic(head["mode"], args.config) if args.traversal == "auto" else None
-    traffic_gbs = traffic / (head["avg_trace_launch_ms"] * 1e-3) / 1e9 if traffic else None
+
+    def workload(name, info):
+        c = info["cfg"]
+        return (f"{name}: {c['w']}x{c['h']}, 1 spp, {c['bounces']} bounces, {info['ntri']} triangles, "
+                f"tile {c['tile'][0]}x{c['tile'][1]}, K={c['k']}")
+
     line = {
         "metric": "secondary Mrays/s (reuse vs incoherent vs sorted) + p99 frame latency",
         "value": round(head["secondary_mrays_s"], 3),
@@ -640,40 +1039,29 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded procedural scene standing in for the paper's archived scenes)",
-        "config": {"workload": f"{args.config}: {cfg['w']}x{cfg['h']}, 1 spp, {cfg['bounces']} bounces, "
-                               f"{scene.ntri} triangles, tile {cfg['tile'][0]}x{cfg['tile'][1]}, K={cfg['k']}",
-                   "mode": head["mode"], "parallelism": "single GPU", "nee": bool(args.nee),
-                   "traversal": traversal_kind(sc, args.traversal)},
-        "modes": {m: {"secondary_mrays_s": round(v["secondary_mrays_s"], 3),
-                      "end_to_end_secondary_mrays_s": round(v["end_to_end_secondary_mrays_s"], 3),
-                      "frame_ms_p50": round(v["frame_ms_p50"], 4), "frame_ms_p99": round(v["frame_ms_p99"], 4),
-                      "rays_per_bounce": v["rays_per_bounce"], "nodes_per_ray": round(v["nodes_per_ray"], 2),
-                      "compulsory_bytes_per_bounce": [round(x) for x in v["compulsory_bytes_per_bounce"]],
-                      "tris_per_ray": round(v["tris_per_ray"], 2),
-                      **({"shadow_mrays_s": round(v["shadow_mrays_s"], 3),
-                          "shadow_rays_per_frame": v["shadow_rays_per_frame"]} if args.nee else {})}
-                  for m, v in results.items()},
+        "data": "synthetic (seeded procedural scenes standing in for the paper's archived scenes)",
+        "config": {"workload": workload(name0, info0), "mode": head["mode"], "parallelism": "single GPU",
+                   "nee": bool(args.nee), "traversal": traversal_kind(info0["sc_info"], args.traversal),
+                   "metric_definition": "rays traced at bounces 1..B / summed traversal-kernel time of those "
+                                        "bounces (HIP events on the library's stream), per frame of exactly "
+                                        "`steps` timed frames; p50/p99 over those frames and "
+                                        f"{args.latency_frames} more after them"},
+        "modes": {lab: _mode_summary(v, args.nee) for lab, v in res0.items()},
         "p99_frame_ms": round(head["frame_ms_p99"], 4),
-        "roofline": {"bound": "alu", "achieved": round(achieved_ops, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                     "unit": "TFLOP/s", "frac": round(achieved_ops / VALU_PEAK_TOPS, 4), "traffic": traffic,
-                     "kernel": kernel_label(sc, args.traversal) + ", secondary bounces",
-                     "op": "32-bit VALU lane operation (compare/min/max/select counted like add/mul)",
-                     "ops_per_ray": round(head["ops_per_ray"], 1),
-                     "algorithmic_bytes_per_ray": round(head["bytes_per_ray"], 1),
-                     "algorithmic_bytes_per_launch": round(head["bytes_per_launch"]),
-                     "compulsory_bytes_per_launch": round(head["compulsory_bytes_per_launch"]),
-                     "algorithmic_GBps": round(achieved_gbs, 1), "hbm_peak_GBps": HBM_PEAK_GBS,
-                     "working_set_level": level, "measured_ceiling_GBps": ceil[level]["read_GBps"],
-                     "algorithmic_frac_of_measured_ceiling": round(achieved_gbs / ceil[level]["read_GBps"], 4),
-                     "traffic_GBps": round(traffic_gbs, 1) if traffic_gbs else None,
-                     "traffic_frac_of_measured_hbm_ceiling":
-                         round(traffic_gbs / ceil["hbm"]["read_GBps"], 4) if traffic_gbs else None},
-        "ceilings": ceil,
-        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample",
-                                                                       "single_core_value", "single_core_sample")},
+        "roofline": roofline(head, info0["sc_info"], args.traversal, ceil, name0, info0["level"]),
     }
-    print(json.dumps(line), flush=True)
+    for name, (res, info) in out.items():
+        if name == name0:
+            continue
+        h = next(iter(res.values()))
+        line[name] = {"workload": workload(name, info), "value": round(h["secondary_mrays_s"], 3),
+                      "p99_frame_ms": round(h["frame_ms_p99"], 4),
+                      "modes": {lab: _mode_summary(v, args.nee) for lab, v in res.items()},
+                      "roofline": roofline(h, info["sc_info"], args.traversal, ceil, name, info["level"])}
+    line["ceilings"] = ceil
+    line["cpu_baseline"] = None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample",
+                                                                         "single_core_value", "single_core_sample")}
+    return line
 
 
 if __name__ == "__main__":
