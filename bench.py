@@ -161,7 +161,8 @@ def bench_mode(api, sc, cfg, mode, steps, warmup, seed0, nee=False, trav="auto",
             r2.render(seed0 + 50000 + i)
             evl[i][1].record(st)
         torch.cuda.synchronize()
-        lat_ms += [a.elapsed_time(b) for a, b in evl]
+        # percentiles over these frames alone: the timed frames carry the timer's events
+        lat_ms = [a.elapsed_time(b) for a, b in evl]
         del r2
     lat_ms = np.array(lat_ms)
     # rays of the last frame (identical statistics every frame; counted on the device)
@@ -446,6 +447,30 @@ def _ldr(x):
     return x.clamp(0.0, 1.0).pow(1.0 / 2.2)
 
 
+def psnr_db(img, ref):
+    """PSNR in dB of an image against a reference, both display values in [0, 1] (numpy
+    arrays of one shape): 10 log10(1 / mean squared difference over every pixel and channel)."""
+    mse = float(np.mean((np.asarray(img, np.float64) - np.asarray(ref, np.float64)) ** 2))
+    return 10.0 * np.log10(1.0 / mse) if mse > 0 else float("inf")
+
+
+def tile_variance_ratio(err, tile):
+    """Structured noise at the period of the reuse tiles: the variance of the error averaged
+    over each W x H tile, times W*H, over the variance of the per-pixel error (channels
+    averaged first; whole tiles only).  Independent pixel errors give 1; errors shared by
+    groups of K pixels inside each tile give K, the correlation that the paper reports as
+    visible noise for large groups (Sec. 5.3), which a per-pixel PSNR does not see."""
+    e = np.asarray(err, np.float64)
+    if e.ndim == 3:
+        e = e.mean(axis=2)
+    W, H = tile
+    h, w = (e.shape[0] // H) * H, (e.shape[1] // W) * W
+    e = e[:h, :w]
+    e = e - e.mean()
+    tm = e.reshape(h // H, H, w // W, W).mean(axis=(1, 3))
+    return float(tm.var() * (W * H) / e.var())
+
+
 def bench_quality(api, sc, cfg, args):
     """Image quality and the tile/group sweep (the protocols of the paper's Table 2 and
     Table 3): PSNR after `--quality-frames` frames (1 spp each, a new seed per frame, so
@@ -482,9 +507,13 @@ def bench_quality(api, sc, cfg, args):
     ref = _ldr(average("incoherent", (8, 8), 8, args.quality_ref, 7_000_000))
     log(f"[quality] reference: {args.quality_ref} frames in {time.perf_counter() - t0:.1f} s")
 
+    ref_np = ref.cpu().numpy()
+
     def psnr(img):
-        mse = float(((_ldr(img) - ref) ** 2).mean())
-        return 10.0 * np.log10(1.0 / mse) if mse > 0 else float("inf")
+        return psnr_db(_ldr(img).cpu().numpy(), ref_np)
+
+    def structure(img, tile):
+        return tile_variance_ratio(_ldr(img).cpu().numpy() - ref_np, tile)
 
     out = {"reference_frames": args.quality_ref, "frames": args.quality_frames,
            "display": "clamp to [0,1], gamma 1/2.2, PSNR over all pixels and channels",
@@ -521,6 +550,20 @@ def bench_quality(api, sc, cfg, args):
                          "secondary_mrays_s": round(v, 1)})
         log(f"[quality] {mode} + NEE: {nee_rows[-1]}")
     out["nee"] = nee_rows
+    # structured noise (Sec. 5.3: K = 32 in 8x8 tiles leaves visible noise after many frames):
+    # the tile variance ratio of the error after 128 and after `--quality-long` frames
+    srows = []
+    for mode, tile, k in (("incoherent", (8, 8), 8), ("reuse", (8, 8), 8), ("reuse", (8, 8), 32),
+                          ("reuse", (8, 8), 64), ("reuse", (16, 16), 32), ("reuse_plain", (8, 8), 8),
+                          ("reuse_world", (8, 8), 8)):
+        row = {"mode": mode, "tile": list(tile), "k": k}
+        for frames in (args.quality_frames, args.quality_long):
+            img = average(mode, tile, k, frames, 1)
+            row[f"psnr_db_{frames}"] = round(psnr(img), 3)
+            row[f"tile_variance_ratio_{frames}"] = round(structure(img, tile), 3)
+        srows.append(row)
+        log(f"[quality] structure {mode} {tile} K={k}: {row}")
+    out["structure"] = srows
     return out
 
 
@@ -759,6 +802,8 @@ def main():
                     help="PSNR against a many-frame reference and the (W,H) x K speed sweep")
     ap.add_argument("--quality-frames", type=int, default=128)
     ap.add_argument("--quality-ref", type=int, default=4096)
+    ap.add_argument("--quality-long", type=int, default=2048,
+                    help="frames of the long runs of the structured-noise rows")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="write profiles/k_trace_CONFIG_1080p.md from the rocprofv3 runs of --profile under DIR")
     ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
@@ -957,7 +1002,7 @@ def _mode_summary(v, nee=False):
                 "shadow_rays_per_frame": v["shadow_rays_per_frame"]} if nee else {})}
 
 
-TIMER_KIND_NAMES = {0: "trace", 1: "raygen", 2: "shade", 3: "key", 4: "sort", 5: "gather", 6: "other",
+TIMER_KIND_NAMES = {0: "trace", 1: "raygen", 2: "shade", 3: "key", 4: "sort", 6: "other",
                     7: "shadow_trace", 8: "shadow_accumulate"}
 
 
@@ -1044,8 +1089,9 @@ def bench_frames(api, scenes, args, torch):
                    "nee": bool(args.nee), "traversal": traversal_kind(info0["sc_info"], args.traversal),
                    "metric_definition": "rays traced at bounces 1..B / summed traversal-kernel time of those "
                                         "bounces (HIP events on the library's stream), per frame of exactly "
-                                        "`steps` timed frames; p50/p99 over those frames and "
-                                        f"{args.latency_frames} more after them"},
+                                        "`steps` timed frames; p50/p99 frame latency over "
+                                        f"{args.latency_frames} frames rendered after them without "
+                                        "the per-kernel timer"},
         "modes": {lab: _mode_summary(v, args.nee) for lab, v in res0.items()},
         "p99_frame_ms": round(head["frame_ms_p99"], 4),
         "roofline": roofline(head, info0["sc_info"], args.traversal, ceil, name0, info0["level"]),

@@ -16,7 +16,8 @@ LIB_PATH = os.environ.get("PT_LIB") or os.path.join(HERE, "libpt.so")
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_EUNSUPPORTED, PT_EBUSY = 0, -1, -2, -3, -4, -5
 MODES = {"incoherent": 0, "sorted": 1, "reuse": 2, "sorted_origin": 3, "sorted_reis": 4, "sorted_aila": 5,
          "reuse_plain": 6, "reuse_world": 7}
-TIMER_KINDS = {0: "trace", 1: "raygen", 2: "shade", 3: "key", 4: "sort", 5: "gather", 6: "other"}
+TIMER_KINDS = {0: "trace", 1: "raygen", 2: "shade", 3: "key", 4: "sort", 6: "other", 7: "shadow_trace",
+               8: "shadow_accumulate"}
 
 
 class PtError(RuntimeError):

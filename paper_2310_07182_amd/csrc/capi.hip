@@ -171,6 +171,8 @@ Frame make_frame(int w, int h, int spp, int B, pt_mode mode, pt_group g, uint64_
     f.nsty = (h + f.SH - 1) / f.SH;
     f.ntx = (w + f.W - 1) / f.W;
     f.nslots = (uint32_t)f.nstx * (uint32_t)f.nsty * (uint32_t)f.TS;
+    // compacted queues: 8 regions (shade workgroup blk writes region blk mod 8)
+    f.region = (uint32_t)(((uint32_t)f.nstx * (uint32_t)f.nsty + 7u) / 8u) * (uint32_t)f.TS;
     f.seed = seed;
     f.nee = g.nee;
     f.frame_groups = g.frame_groups;
@@ -198,14 +200,14 @@ void set_camera(Frame& f, const pt_camera* cam, int w, int h) {
 }
 
 struct Layout {
-    size_t q0, q1, state, work, partial, keys, vals, qs, sortws, ovf, total;
+    size_t q0, q1, state, work, partial, sortws, ovf, total;
     size_t shray, shc, sprim, st, swork, spartial;   // next-event estimation
 };
 
 Layout layout(const Frame& f) {
     Layout L{};
     size_t o = 0;
-    const size_t qb = (size_t)f.nslots * 32;
+    const size_t qb = (size_t)8 * f.region * 32;   // a ray queue: the slots, or the 8 regions of a compacted one
     const size_t launches = (size_t)(f.B + 1) * (size_t)f.spp;
     L.q0 = o;
     o = align256(o + qb);
@@ -218,14 +220,8 @@ Layout layout(const Frame& f) {
     L.partial = o;
     o = align256(o + launches * pt::kMaxTraceBlocks * 4);
     if (is_sorted_mode(f.mode)) {
-        L.keys = o;
-        o = align256(o + (size_t)f.nslots * 4);
-        L.vals = o;
-        o = align256(o + (size_t)f.nslots * 4);
-        L.qs = o;
-        o = align256(o + qb);
         L.sortws = o;
-        o = align256(o + pt::sort_workspace_bytes(f.nslots));
+        o = align256(o + pt::sort_compacted_workspace_bytes(f.nslots));
     }
     if (f.nee) {
         L.shray = o;
@@ -574,32 +570,30 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
         if (e != hipSuccess) return hip_fail(e, "launch (raygen)");
         for (int b = 0; b <= B; ++b) {
             const size_t li = (size_t)b * spp + s;
-            const float4* tq = q[b & 1];
             const uint32_t n = f.nslots;
+            // bounces after the first trace a compacted queue: the live rays the previous shade
+            // wrote into 8 regions, counted in the fill words of this launch's work area
+            const uint32_t* fill = b >= 1 ? work + li * pt::kWorkWords + pt::kFillWord : nullptr;
+            const uint32_t* perm = nullptr;
             if (is_sorted_mode(mode) && b >= 1) {
-                uint32_t* keys = (uint32_t*)(ws + L.keys);
-                uint32_t* vals = (uint32_t*)(ws + L.vals);
-                float4* qs = (float4*)(ws + L.qs);
                 {
                     TimerScope ts(out->timer, st, 3, b);
-                    e = pt::launch_keys(scene->dev, q[b & 1], f.nslots, keys, vals, (int)mode, st);
+                    e = pt::launch_keys_compacted(scene->dev, q[b & 1], fill, f.region, f.nslots, (int)mode,
+                                                  ws + L.sortws, st);
                 }
                 if (e != hipSuccess) return hip_fail(e, "launch (keys)");
                 {
                     TimerScope ts(out->timer, st, 4, b);
-                    e = pt::radix_sort_pairs(keys, vals, f.nslots, ws + L.sortws, st);
+                    e = pt::launch_sort_compacted(fill, f.nslots, ws + L.sortws, &perm, st);
                 }
                 if (e != hipSuccess) return hip_fail(e, "launch (sort)");
-                {
-                    TimerScope ts(out->timer, st, 5, b);
-                    e = pt::launch_gather(q[b & 1], vals, f.nslots, qs, st);
-                }
-                if (e != hipSuccess) return hip_fail(e, "launch (gather)");
-                tq = qs;   // dead rays (key 0xFFFFFFFF) sort last and are skipped by the trace
             }
             pt::TraceArgs ta{};
-            ta.rays = tq;
+            ta.rays = q[b & 1];
             ta.n = n;
+            ta.fill = fill;
+            ta.region = f.region;
+            ta.perm = perm;   // sorted: the rays are read in key order
             ta.work = work + li * pt::kWorkWords;
             ta.out_prim = out->hit_prim + li * plane;
             ta.out_t = out->hit_t + li * plane;
@@ -625,8 +619,10 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
             float4* shc = f.nee ? (float4*)(ws + L.shc) : nullptr;
             {
                 TimerScope ts(out->timer, st, 2, b);
+                // the next rays go compacted into the regions counted by the next launch's fill words
+                uint32_t* fill_next = b < B ? work + ((size_t)(b + 1) * spp + s) * pt::kWorkWords + pt::kFillWord : nullptr;
                 e = pt::launch_shade(scene->dev, f, b, s, q[b & 1], q[(b + 1) & 1], state, out->hit_prim, out->hit_t,
-                                     out->radiance, (float4*)out->rays, shray, shc, st);
+                                     out->radiance, (float4*)out->rays, shray, shc, fill_next, st);
             }
             if (e != hipSuccess) return hip_fail(e, "launch (shade)");
             if (f.nee && b < B) {

@@ -38,6 +38,8 @@ struct Frame {
     float th, thx;
     int nee;                  // next-event estimation at Lambert points
     int frame_groups;         // one tile shuffle per sample (drawn at bounce 0), not one per bounce
+    uint32_t region;          // compacted queues: ray slots per region (8 regions, workgroup blk
+                              // writes region blk mod 8): ceil(workgroups / 8) x TS
 };
 
 // Ray queue record: {ox, oy, oz, excluded prim} {dx, dy, dz, pixel}; pixel = kNoRay: no ray.
@@ -57,6 +59,9 @@ constexpr int kDefaultWavesPerCu = 24;     // persistent grid when the caller le
 constexpr int kRayCounters = 8;
 constexpr int kCounterStride = 64;
 constexpr int kWorkWords = kRayCounters * kCounterStride;
+// A compacted launch keeps region c's ray count kFillWord words after counter c: another
+// 128-byte line, so the loads of the counts do not meet the claims' atomics on one line.
+constexpr int kFillWord = 32;
 constexpr int kDefaultLeafGate = 8;        // pt_group.leaf_gate when the caller leaves it to the library
 
 struct TraceArgs {
@@ -78,6 +83,12 @@ struct TraceArgs {
     uint8_t* touched;          // optional (counting kernels): node flags, then triangle flags from touch_tri
     uint32_t touch_tri;
     uint32_t touch_bit;
+    const uint32_t* fill;      // compacted launch: region c holds fill[c * kCounterStride] rays from
+                               // slot c * region on (launch_shade's layout); the claims follow the
+                               // regions and n is their sum.  null: n rays at [0, n)
+    uint32_t region;
+    const uint32_t* perm;      // with fill: ray i of the launch is rays[perm[i]], i < sum of fill
+                               // (the sorted modes' order); null: ray i is rays[i]
     int max_blocks;            // > 0: the persistent grid has at most this many workgroups (the
                                // overflow area ovf holds that many); 0 = no cap beyond kMaxTraceBlocks
 };
@@ -126,9 +137,12 @@ hipError_t launch_probe_read(const void* buf, size_t bytes, int passes, uint32_t
 hipError_t launch_probe_chase(const uint32_t* buf, uint32_t nlines, int steps, uint32_t* sink, hipStream_t st);
 hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t st);
 hipError_t launch_raygen(const Frame& f, int s, float4* q, float4* state, float4* rays_out, hipStream_t st);
+// fill: null = the next rays at their slots (dead slots hold kNoRay records); else the live
+// rays compacted into 8 regions of f.region slots, region r's count in fill[r * kCounterStride]
+// (zero before the launch), dead rays not written
 hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const float4* q_in, float4* q_out,
                         float4* state, int32_t* hit_prim, float* hit_t, float* radiance, float4* rays_out,
-                        float4* shadow_rays, float4* shadow_light, hipStream_t st);
+                        float4* shadow_rays, float4* shadow_light, uint32_t* fill, hipStream_t st);
 // next-event estimation: adds shadow_light[p].rgb to the radiance of path p when its shadow
 // ray exists (pixel word != kNoRay) and shadow_prim[p] == -1 (nothing in between)
 hipError_t launch_nee_accumulate(const float4* shadow_rays, const float4* shadow_light, const int32_t* shadow_prim,
@@ -138,9 +152,18 @@ hipError_t launch_keys(const DevScene& sc, const float4* q, uint32_t n, uint32_t
 // ray_count[i] = sum of partial[i * stride + j] for j < parts, i < launches
 hipError_t launch_count_finalize(const uint32_t* partial, int stride, int parts, int launches, uint32_t* ray_count,
                                  hipStream_t st);
-hipError_t launch_gather(const float4* q, const uint32_t* idx, uint32_t n, float4* out, hipStream_t st);
+// sorted modes over a compacted queue (launch_shade's regions, counts in fill): the 30-bit keys of
+// the live rays with their queue slots and the digit histograms (launch_keys_compacted), then a
+// stable radix sort in 4 passes of 8-bit digits (launch_sort_compacted), whose *perm gives the
+// queue slots in key order for the traversal (TraceArgs.perm); ws: sort_compacted_workspace_bytes
+size_t sort_compacted_workspace_bytes(uint32_t nslots);
+hipError_t launch_keys_compacted(const DevScene& sc, const float4* q, const uint32_t* fill, uint32_t region,
+                                 uint32_t nslots, int kind, void* ws, hipStream_t st);
+hipError_t launch_sort_compacted(const uint32_t* fill, uint32_t nslots, void* ws, const uint32_t** perm,
+                                 hipStream_t st);
 
-// stable LSD radix sort (4 passes of 8 bits)
+// stable LSD radix sort of n (key, value) pairs by 32-bit keys (4 passes of 8-bit digits, one
+// decoupled look-back pass each), in place
 size_t sort_workspace_bytes(uint32_t n);
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t n, void* ws, hipStream_t st);
 

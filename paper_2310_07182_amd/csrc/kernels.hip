@@ -285,6 +285,26 @@ __device__ __forceinline__ uint64_t claimed_ray(uint32_t v, uint32_t c) {
     return ((((uint64_t)(v >> 6)) * kRayCounters + c) << 6) | (v & 63u);
 }
 
+// The v-th ray counter c hands out, as an index into the launch's rays, or kNoClaim.  Plain
+// and permuted launches: the 64-ray chunks of [0, n) numbered c mod 8.  Compacted launches
+// (fill, no permutation): the first nc = fill[c] slots of region c.  The index is monotone
+// in v, so the first v without a ray ends the counter.
+constexpr uint64_t kNoClaim = ~0ull;
+__device__ __forceinline__ uint64_t claim_index(const TraceArgs& a, uint32_t v, uint32_t c, uint32_t n, uint32_t nc) {
+    if (a.fill && !a.perm) return v < nc ? (uint64_t)c * a.region + v : kNoClaim;
+    const uint64_t i = claimed_ray(v, c);
+    return i < n ? i : kNoClaim;
+}
+
+// rays of the launch: a.n, or the sum of the region counts of a compacted launch
+__device__ __forceinline__ uint32_t launch_rays(const TraceArgs& a) {
+    if (!a.fill) return a.n;
+    uint32_t n = 0;
+#pragma unroll
+    for (int c = 0; c < kRayCounters; ++c) n += a.fill[c * kCounterStride];
+    return n;
+}
+
 template <bool STATS, bool MULTI, bool WIDE>
 __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a, uint32_t gthreads,
                                                        const StepJob* jobs, int njobs) {
@@ -292,7 +312,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
     __shared__ PairT pairs[kTraceBlock * kMaxLeaf];   // lane | (triangle in leaf) << 6
     const int lane = threadIdx.x;
     const uint32_t gtid = blockIdx.x * kTraceBlock + lane;
-    const uint32_t n = a.n;
+    const uint32_t n = launch_rays(a);
+    uint32_t ncq = a.fill ? a.fill[(blockIdx.x % kRayCounters) * kCounterStride] : 0u;   // rays of counter cq
     const unsigned long long lt = (1ull << lane) - 1ull;
     unsigned long long nv = 0, nt = 0;
     uint32_t traced = 0;
@@ -322,20 +343,22 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
             const uint32_t nidle = (uint32_t)__popcll(idle);
             const uint32_t need = nidle < share ? nidle : share;
             const uint32_t c = cq;
+            const uint32_t nc = ncq;
             uint32_t base = 0;
             if (lane == 0) base = atomicAdd(a.work + c * kCounterStride, need);
             base = __shfl(base, 0);
-            if (claimed_ray(base + need, c) >= n) {   // this counter has no rays left
+            if (claim_index(a, base + need, c, n, nc) == kNoClaim) {   // this counter has no rays left
                 if (++tries == kRayCounters) exhausted = true;
                 cq = (cq + 1u) % kRayCounters;
+                ncq = a.fill ? a.fill[cq * kCounterStride] : 0u;
             }
             const uint32_t rank = (uint32_t)__popcll(idle & lt);
             if (!have && rank < need) {
-                const uint64_t i64 = claimed_ray(base + rank, c);
+                const uint64_t i64 = claim_index(a, base + rank, c, n, nc);
                 const uint32_t i = (uint32_t)i64;
-                if (i64 < n) {
+                if (i64 != kNoClaim) {
                     const float4* rays = a.rays;
-                    uint32_t li = i;
+                    uint32_t li = a.perm ? a.perm[i] : i;   // sorted launches read the rays through the sort's permutation
                     if constexpr (MULTI) {
                         int lo = 0, hi = njobs - 1;
                         while (lo < hi) {
@@ -710,7 +733,8 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
     __shared__ unsigned long long bestk[kTraceBlock];
     const int lane = threadIdx.x;
     const uint32_t gtid = blockIdx.x * kTraceBlock + lane;
-    const uint32_t n = a.n;
+    const uint32_t n = launch_rays(a);
+    uint32_t ncq = a.fill ? a.fill[(blockIdx.x % kRayCounters) * kCounterStride] : 0u;   // rays of counter cq
     const unsigned long long lt = (1ull << lane) - 1ull;
     // a shadow ray keeps hits at t < kShadowTmax; prim ids are below INT32_MAX
     const unsigned long long key0 = a.shadow ? hit_key(kShadowTmax, 0u) : hit_key(INFINITY, (uint32_t)INT32_MAX);
@@ -750,20 +774,22 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
             const uint32_t nidle = (uint32_t)__popcll(idle);
             const uint32_t need = nidle < share ? nidle : share;
             const uint32_t c = cq;
+            const uint32_t nc = ncq;
             uint32_t base = 0;
             if (lane == 0) base = atomicAdd(a.work + c * kCounterStride, need);
             base = __shfl(base, 0);
-            if (claimed_ray(base + need, c) >= n) {   // this counter has no rays left
+            if (claim_index(a, base + need, c, n, nc) == kNoClaim) {   // this counter has no rays left
                 if (++tries == kRayCounters) exhausted = true;
                 cq = (cq + 1u) % kRayCounters;
+                ncq = a.fill ? a.fill[cq * kCounterStride] : 0u;
             }
             const uint32_t rank = (uint32_t)__popcll(idle & lt);
             if (!have && rank < need) {
-                const uint64_t i64 = claimed_ray(base + rank, c);
+                const uint64_t i64 = claim_index(a, base + rank, c, n, nc);
                 const uint32_t i = (uint32_t)i64;
-                if (i64 < n) {
+                if (i64 != kNoClaim) {
                     const float4* rays = a.rays;
-                    uint32_t li = i;
+                    uint32_t li = a.perm ? a.perm[i] : i;   // sorted launches read the rays through the sort's permutation
                     if constexpr (MULTI) {
                         int lo = 0, hi = njobs - 1;
                         while (lo < hi) {
@@ -1162,7 +1188,8 @@ __global__ __launch_bounds__(1024) void k_raygen_multi(const StepJob* jobs, int 
 __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, int b, int s, uint32_t blk,
                                            const float4* __restrict__ q_in, float4* __restrict__ q_out,
                                            float4* state, int32_t* hit_prim, float* hit_t, float* radiance,
-                                           float4* rays_out, float4* shadow_rays, float4* shadow_light, float* lds) {
+                                           float4* rays_out, float4* shadow_rays, float4* shadow_light, float* lds,
+                                           uint32_t* fill) {
     // group exchange in LDS, TS entries each: own tangent exit, tree sums, info bits, min active slot
     const int TS = f.TS;
     float* sq0 = lds;
@@ -1343,6 +1370,37 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
         use_ok = use_world ? dot3(repq, n) > 0.0f : use_ok;
         newpos = blk * (uint32_t)TS + (uint32_t)e;
     }
+    if (fill && b < f.B) {
+        // the compacted queue: the live rays of workgroup blk go, in their queue order (group by
+        // group in reuse modes), to the next free places of region blk mod 8 (one counter per
+        // region, one atomic per workgroup); the traversal's counter c hands out region c
+        int* cf = (int*)(lds + (f.mode == PT_MODE_REUSE || f.mode == PT_MODE_REUSE_PLAIN || world ? 8 * TS : 0));
+        int* cw = cf + TS;
+        const bool live = active && use_ok;
+        const int epos = (int)(newpos - blk * (uint32_t)TS);
+        __syncthreads();
+        cf[epos] = live ? 1 : 0;
+        __syncthreads();
+        const bool fl = cf[l] != 0;
+        const unsigned long long bm = __ballot(fl);
+        const int wv = l >> 6, ln = l & 63;
+        const int pre = __popcll(bm & ((1ull << ln) - 1ull));
+        if (ln == 0) cw[wv] = __popcll(bm);
+        __syncthreads();
+        if (l == 0) {
+            int tot = 0;
+            for (int w = 0; w < (TS + 63) / 64; ++w) {
+                const int c = cw[w];
+                cw[16 + w] = tot;
+                tot += c;
+            }
+            cw[32] = tot > 0 ? (int)atomicAdd(fill + (blk & 7u) * (uint32_t)kCounterStride, (uint32_t)tot) : 0;
+        }
+        __syncthreads();
+        cf[l] = cw[32] + cw[16 + wv] + pre;   // place of queue position l among the region's rays
+        __syncthreads();
+        newpos = live ? (blk & 7u) * f.region + (uint32_t)cf[epos] : p;
+    }
     if (b < f.B) {
         float4 o0 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1)), o1 = make_float4(0.f, 0.f, 0.f, __uint_as_float(kNoRay));
         if (active && use_ok) {
@@ -1358,8 +1416,10 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
         } else if (active) {
             died = true;
         }
-        q_out[2 * (size_t)newpos] = o0;
-        q_out[2 * (size_t)newpos + 1] = o1;
+        if (!fill || (active && use_ok)) {   // a compacted queue holds live rays only
+            q_out[2 * (size_t)newpos] = o0;
+            q_out[2 * (size_t)newpos + 1] = o1;
+        }
     }
     if (died) {
         alive = false;
@@ -1384,10 +1444,10 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
 __global__ __launch_bounds__(1024) void k_shade(DevScene sc, Frame f, int b, int s, const float4* __restrict__ q_in,
                                                 float4* __restrict__ q_out, float4* state, int32_t* hit_prim,
                                                 float* hit_t, float* radiance, float4* rays_out, float4* shadow_rays,
-                                                float4* shadow_light) {
+                                                float4* shadow_light, uint32_t* fill) {
     extern __shared__ float lds[];
     shade_body(sc, f, b, s, blockIdx.x, q_in, q_out, state, hit_prim, hit_t, radiance, rays_out, shadow_rays,
-               shadow_light, lds);
+               shadow_light, lds, fill);
 }
 
 // adds the light of unblocked shadow rays to their paths (one thread per path slot)
@@ -1409,7 +1469,7 @@ __global__ __launch_bounds__(1024) void k_shade_multi(const StepJob* jobs, int n
     const int j = job_of_block(jobs, njobs, blockIdx.x);
     const StepJob& J = jobs[j];
     shade_body(J.sc, J.f, J.b, J.s, blockIdx.x - J.block_start, J.q_in, J.q_out, J.state, J.hit_prim, J.hit_t,
-               J.radiance, nullptr, nullptr, nullptr, lds);
+               J.radiance, nullptr, nullptr, nullptr, lds, nullptr);
 }
 
 // ------------------------------------------------------------------ two-point key, gather
@@ -1423,63 +1483,348 @@ __device__ __forceinline__ uint32_t qbits(float x, float lo, float ext, int nb) 
     return (uint32_t)f;
 }
 
-// 30-bit reordering keys of the sorted modes (bits interleaved most significant first)
+// 30-bit reordering key of a live ray for a sorted mode (bits interleaved most significant first)
+__device__ __forceinline__ uint32_t ray_key(const DevScene& sc, float4 r0, float4 r1, int kind) {
+    const float ex = sc.hi[0] - sc.lo[0], ey = sc.hi[1] - sc.lo[1], ez = sc.hi[2] - sc.lo[2];
+    uint32_t key = 0;
+    if (kind == PT_MODE_SORTED_ORIGIN) {
+        const uint32_t qc[3] = {qbits(r0.x, sc.lo[0], ex, 10), qbits(r0.y, sc.lo[1], ey, 10),
+                                qbits(r0.z, sc.lo[2], ez, 10)};
+#pragma unroll
+        for (int bit = 9; bit >= 0; --bit)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) key = (key << 1) | ((qc[c] >> bit) & 1u);
+    } else if (kind == PT_MODE_SORTED_REIS) {
+        const uint32_t qo[3] = {qbits(r0.x, sc.lo[0], ex, 6), qbits(r0.y, sc.lo[1], ey, 6),
+                                qbits(r0.z, sc.lo[2], ez, 6)};
+        const uint32_t qd[3] = {qbits(r1.x, -1.0f, 2.0f, 4), qbits(r1.y, -1.0f, 2.0f, 4),
+                                qbits(r1.z, -1.0f, 2.0f, 4)};
+#pragma unroll
+        for (int bit = 5; bit >= 0; --bit)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) key = (key << 1) | ((qo[c] >> bit) & 1u);
+#pragma unroll
+        for (int bit = 3; bit >= 0; --bit)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) key = (key << 1) | ((qd[c] >> bit) & 1u);
+    } else {
+        uint32_t qc[6];
+        if (kind == PT_MODE_SORTED_AILA) {
+            qc[3] = qbits(r1.x, -1.0f, 2.0f, 5);
+            qc[4] = qbits(r1.y, -1.0f, 2.0f, 5);
+            qc[5] = qbits(r1.z, -1.0f, 2.0f, 5);
+        } else {   // TwoPoint: the point at a fixed length of 0.25 x the largest extent
+            float mx = ex;
+            if (ey > mx) mx = ey;
+            if (ez > mx) mx = ez;
+            const float len = 0.25f * mx;
+            qc[3] = qbits(r0.x + len * r1.x, sc.lo[0], ex, 5);
+            qc[4] = qbits(r0.y + len * r1.y, sc.lo[1], ey, 5);
+            qc[5] = qbits(r0.z + len * r1.z, sc.lo[2], ez, 5);
+        }
+        qc[0] = qbits(r0.x, sc.lo[0], ex, 5);
+        qc[1] = qbits(r0.y, sc.lo[1], ey, 5);
+        qc[2] = qbits(r0.z, sc.lo[2], ez, 5);
+#pragma unroll
+        for (int bit = 4; bit >= 0; --bit)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) key = (key << 1) | ((qc[c] >> bit) & 1u);
+    }
+    return key;
+}
+
+// keys of n rays in a plain queue (dead rays, pixel word kNoRay, get 0xFFFFFFFF)
 __global__ __launch_bounds__(256) void k_keys(DevScene sc, const float4* q, uint32_t n, uint32_t* keys,
                                               uint32_t* vals, int kind) {
     const uint32_t j = blockIdx.x * 256u + threadIdx.x;
     if (j < n) {
         const float4 r0 = q[2 * (size_t)j], r1 = q[2 * (size_t)j + 1];
         const bool live = __float_as_uint(r1.w) != kNoRay;
-        uint32_t key = 0xFFFFFFFFu;
-        if (live) {
-            const float ex = sc.hi[0] - sc.lo[0], ey = sc.hi[1] - sc.lo[1], ez = sc.hi[2] - sc.lo[2];
-            key = 0;
-            if (kind == PT_MODE_SORTED_ORIGIN) {
-                const uint32_t qc[3] = {qbits(r0.x, sc.lo[0], ex, 10), qbits(r0.y, sc.lo[1], ey, 10),
-                                        qbits(r0.z, sc.lo[2], ez, 10)};
+        keys[j] = live ? ray_key(sc, r0, r1, kind) : 0xFFFFFFFFu;
+        if (vals) vals[j] = j;
+    }
+}
+
+// ------------------------------------------------------------------ stable radix sort, one pass per digit
+// Each pass (Merrill and Garland's decoupled look-back, as in single-pass "onesweep" radix
+// sorts): a workgroup takes the next tile id from a counter (ids follow the order workgroups
+// start in, so every lower tile belongs to a workgroup that is already running), counts the
+// tile's digits, publishes the counts, and adds the counts of the lower tiles by walking back
+// until it meets one that has published its inclusive prefix (tile 0 publishes that at once).
+// Keys are ranked stably in the tile (by index), staged in LDS in digit order and written out
+// in runs.  The global start of each digit comes from histograms of all passes taken before
+// the first pass.
+constexpr int kOsThreads = 256;
+constexpr int kOsItems = 16;
+constexpr uint32_t kOsTile = (uint32_t)kOsThreads * kOsItems;
+constexpr uint32_t kLbAgg = 1u << 30, kLbInc = 2u << 30, kLbCount = (1u << 30) - 1u;
+constexpr int kLbWindow = 16;   // lower tiles whose words one look-back step loads at once
+
+// exclusive scan over the 256 threads of a workgroup; *total = sum
+__device__ __forceinline__ uint32_t scan256(uint32_t v, uint32_t* wsum, uint32_t* total) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t x = v;
 #pragma unroll
-                for (int bit = 9; bit >= 0; --bit)
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) key = (key << 1) | ((qc[c] >> bit) & 1u);
-            } else if (kind == PT_MODE_SORTED_REIS) {
-                const uint32_t qo[3] = {qbits(r0.x, sc.lo[0], ex, 6), qbits(r0.y, sc.lo[1], ey, 6),
-                                        qbits(r0.z, sc.lo[2], ez, 6)};
-                const uint32_t qd[3] = {qbits(r1.x, -1.0f, 2.0f, 4), qbits(r1.y, -1.0f, 2.0f, 4),
-                                        qbits(r1.z, -1.0f, 2.0f, 4)};
+    for (int w = 0; w < kOsThreads / 64; ++w) {
+        before += w < wave ? wsum[w] : 0u;
+        all += wsum[w];
+    }
+    __syncthreads();
+    if (total) *total = all;
+    return before + x - v;
+}
+
+// rays of a compacted launch (the region counts of fill), or n when fill is null
+__device__ __forceinline__ uint32_t fill_total(const uint32_t* fill, uint32_t n) {
+    if (!fill) return n;
+    uint32_t t = 0;
 #pragma unroll
-                for (int bit = 5; bit >= 0; --bit)
+    for (int c = 0; c < kRayCounters; ++c) t += fill[c * kCounterStride];
+    return t;
+}
+
+// Keys of the live rays of a compacted queue (sorted modes): ray i (i < the launch's rays, in
+// region order) gets its key and its queue slot; the digit histograms of all `passes` passes
+// of d bits each are added to hist[pass][2^d].  Also clears the look-back words of the passes.
+// 1024 threads x kKeysPerThread rays per workgroup, the rays' loads issued together.
+constexpr int kKeysPerThread = 8;
+template <int D>
+__global__ __launch_bounds__(1024) void k_keys_compacted(DevScene sc, const float4* q, const uint32_t* fill,
+                                                         uint32_t region, uint32_t* keys, uint32_t* vals, int kind,
+                                                         int passes, uint32_t* hist, uint32_t* lookback,
+                                                         uint32_t lookback_words) {
+    constexpr uint32_t R = 1u << D;
+    __shared__ uint32_t h[4 * R];   // passes <= 4
+    for (uint32_t d = threadIdx.x; d < 4 * R; d += 1024) h[d] = 0;
+    for (size_t w = (size_t)blockIdx.x * 1024 + threadIdx.x; w < lookback_words; w += (size_t)gridDim.x * 1024)
+        lookback[w] = 0;
+    __syncthreads();
+    uint32_t cnt[kRayCounters], total = 0;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) key = (key << 1) | ((qo[c] >> bit) & 1u);
+    for (int c = 0; c < kRayCounters; ++c) {
+        cnt[c] = fill[c * kCounterStride];
+        total += cnt[c];
+    }
+    uint32_t pos[kKeysPerThread];
+    float4 r0[kKeysPerThread], r1[kKeysPerThread];
 #pragma unroll
-                for (int bit = 3; bit >= 0; --bit)
+    for (int e = 0; e < kKeysPerThread; ++e) {
+        const uint32_t i = (blockIdx.x * kKeysPerThread + (uint32_t)e) * 1024u + threadIdx.x;
+        uint32_t c = 0, v = i;
+        while (c + 1 < (uint32_t)kRayCounters && v >= cnt[c]) {
+            v -= cnt[c];
+            ++c;
+        }
+        pos[e] = c * region + v;
+        const bool ok = i < total;
+        r0[e] = ok ? q[2 * (size_t)pos[e]] : make_float4(0.f, 0.f, 0.f, 0.f);
+        r1[e] = ok ? q[2 * (size_t)pos[e] + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) key = (key << 1) | ((qd[c] >> bit) & 1u);
-            } else {
-                uint32_t qc[6];
-                if (kind == PT_MODE_SORTED_AILA) {
-                    qc[3] = qbits(r1.x, -1.0f, 2.0f, 5);
-                    qc[4] = qbits(r1.y, -1.0f, 2.0f, 5);
-                    qc[5] = qbits(r1.z, -1.0f, 2.0f, 5);
-                } else {   // TwoPoint: the point at a fixed length of 0.25 x the largest extent
-                    float mx = ex;
-                    if (ey > mx) mx = ey;
-                    if (ez > mx) mx = ez;
-                    const float len = 0.25f * mx;
-                    qc[3] = qbits(r0.x + len * r1.x, sc.lo[0], ex, 5);
-                    qc[4] = qbits(r0.y + len * r1.y, sc.lo[1], ey, 5);
-                    qc[5] = qbits(r0.z + len * r1.z, sc.lo[2], ez, 5);
+    for (int e = 0; e < kKeysPerThread; ++e) {
+        const uint32_t i = (blockIdx.x * kKeysPerThread + (uint32_t)e) * 1024u + threadIdx.x;
+        if (i < total) {
+            const uint32_t key = ray_key(sc, r0[e], r1[e], kind);
+            keys[i] = key;
+            vals[i] = pos[e];
+            for (int ps = 0; ps < passes; ++ps) atomicAdd(&h[ps * R + ((key >> (D * ps)) & (R - 1u))], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < (uint32_t)passes * R; d += 1024)
+        if (h[d]) atomicAdd(&hist[d], h[d]);
+}
+
+// digit histograms of all passes of d-bit digits over n keys (a plain sort)
+template <int D>
+__global__ __launch_bounds__(256) void k_digit_hist(const uint32_t* keys, uint32_t n, int passes, uint32_t* hist) {
+    constexpr uint32_t R = 1u << D;
+    __shared__ uint32_t h[4 * R];
+    for (uint32_t d = threadIdx.x; d < 4 * R; d += 256) h[d] = 0;
+    __syncthreads();
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+        const uint32_t key = keys[i];
+        for (int ps = 0; ps < passes; ++ps) atomicAdd(&h[ps * R + ((key >> (D * ps)) & (R - 1u))], 1u);
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < (uint32_t)passes * R; d += 256)
+        if (h[d]) atomicAdd(&hist[d], h[d]);
+}
+
+// One stable pass over digit (key >> shift) & (2^d - 1) of n keys (n = the rays of fill when
+// fill is given).  ghist: the pass's digit histogram over all keys; lookback: [tiles][2^d] words,
+// zero on entry; tile_ctr: zero on entry.  A look-back step loads the words of kLbWindow lower
+// tiles at once, so a walk over t tiles takes t / kLbWindow dependent loads.
+template <int D>
+__global__ __launch_bounds__(kOsThreads) void k_onesweep(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
+                                                         uint32_t* vout, const uint32_t* fill, uint32_t n_plain,
+                                                         int shift, const uint32_t* ghist, uint32_t* lookback,
+                                                         uint32_t* tile_ctr) {
+    constexpr uint32_t R = 1u << D;
+    constexpr int DPT = R >= (uint32_t)kOsThreads ? (int)(R / kOsThreads) : 1;   // digits per thread
+    __shared__ uint32_t s_cnt[R];      // the tile's digit counts, then the running count per digit
+    __shared__ uint32_t s_gbase[R];    // destination of the tile's first key of each digit
+    __shared__ uint32_t s_lbase[R];    // tile-local start of each digit
+    __shared__ uint32_t s_wcnt[kOsThreads / 64][R];
+    __shared__ uint32_t s_k[kOsTile], s_v[kOsTile];   // the tile in digit order
+    __shared__ uint32_t s_wsum[8];
+    __shared__ uint32_t s_tile;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const uint32_t n = fill_total(fill, n_plain);
+    if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
+    for (uint32_t d = tid; d < R; d += kOsThreads) {
+        s_cnt[d] = 0;
+        for (int w = 0; w < kOsThreads / 64; ++w) s_wcnt[w][d] = 0;
+    }
+    __syncthreads();
+    const uint32_t t = s_tile;
+    const uint32_t first = t * kOsTile;
+    if (first >= n) return;   // the whole workgroup: no tile left
+    const uint32_t valid_n = n - first < kOsTile ? n - first : kOsTile;
+    uint32_t k[kOsItems], v[kOsItems];
+#pragma unroll
+    for (int r = 0; r < kOsItems; ++r) {
+        const uint32_t j = (uint32_t)r * kOsThreads + (uint32_t)tid;
+        k[r] = j < valid_n ? kin[first + j] : 0u;
+        v[r] = j < valid_n ? vin[first + j] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kOsItems; ++r)
+        if ((uint32_t)r * kOsThreads + (uint32_t)tid < valid_n) atomicAdd(&s_cnt[(k[r] >> shift) & (R - 1u)], 1u);
+    __syncthreads();
+    // publish the tile's counts (tile 0: its inclusive prefix)
+    for (uint32_t d = tid; d < R; d += kOsThreads)
+        __hip_atomic_store(&lookback[(size_t)t * R + d], (t == 0 ? kLbInc : kLbAgg) | s_cnt[d], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    // exclusive prefixes over the digits (contiguous digits per thread): of the global
+    // histogram and of the tile's counts
+    uint32_t gsum = 0, lsum = 0;
+#pragma unroll
+    for (int e = 0; e < DPT; ++e) {
+        const uint32_t d = (uint32_t)tid * DPT + e;
+        if (d < R) {
+            gsum += ghist[d];
+            lsum += s_cnt[d];
+        }
+    }
+    uint32_t gpre = scan256(gsum, s_wsum, nullptr);
+    uint32_t lpre = scan256(lsum, s_wsum, nullptr);
+#pragma unroll
+    for (int e = 0; e < DPT; ++e) {
+        const uint32_t d = (uint32_t)tid * DPT + e;
+        if (d < R) {
+            s_gbase[d] = gpre;
+            s_lbase[d] = lpre;
+            gpre += ghist[d];
+            lpre += s_cnt[d];
+        }
+    }
+    __syncthreads();
+    // counts of each digit in the lower tiles: walk back to the nearest inclusive prefix, a
+    // window of lower tiles per step, every digit of the thread at once (digit tid + e * 256)
+    if (t > 0) {
+        uint32_t below[DPT];
+        int jt[DPT];
+        bool done[DPT];
+#pragma unroll
+        for (int e = 0; e < DPT; ++e) {
+            below[e] = 0;
+            jt[e] = (int)t - 1;
+            done[e] = !(tid + (uint32_t)e * kOsThreads < R);
+        }
+        for (;;) {
+            bool all = true;
+#pragma unroll
+            for (int e = 0; e < DPT; ++e) all = all && done[e];
+            if (all) break;
+            uint32_t wv[DPT][kLbWindow];
+#pragma unroll
+            for (int e = 0; e < DPT; ++e) {
+                const uint32_t d = tid + (uint32_t)e * kOsThreads;
+#pragma unroll
+                for (int i = 0; i < kLbWindow; ++i)
+                    wv[e][i] = (!done[e] && jt[e] >= i)
+                                   ? __hip_atomic_load(&lookback[(size_t)(jt[e] - i) * R + d], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT)
+                                   : 0u;
+            }
+#pragma unroll
+            for (int e = 0; e < DPT; ++e) {
+                if (done[e]) continue;
+                int used = 0;
+#pragma unroll
+                for (int i = 0; i < kLbWindow; ++i) {
+                    if (done[e] || used < i) continue;   // stopped earlier in this window
+                    const uint32_t f = wv[e][i] & ~kLbCount;
+                    if (f == 0 || jt[e] < i) continue;    // not published yet: load it again next step
+                    below[e] += wv[e][i] & kLbCount;
+                    used = i + 1;
+                    if (f == kLbInc) done[e] = true;
                 }
-                qc[0] = qbits(r0.x, sc.lo[0], ex, 5);
-                qc[1] = qbits(r0.y, sc.lo[1], ey, 5);
-                qc[2] = qbits(r0.z, sc.lo[2], ez, 5);
-#pragma unroll
-                for (int bit = 4; bit >= 0; --bit)
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) key = (key << 1) | ((qc[c] >> bit) & 1u);
+                if (!done[e]) jt[e] -= used;
             }
         }
-        keys[j] = key;
-        if (vals) vals[j] = j;
+#pragma unroll
+        for (int e = 0; e < DPT; ++e) {
+            const uint32_t d = tid + (uint32_t)e * kOsThreads;
+            if (d < R) {
+                __hip_atomic_store(&lookback[(size_t)t * R + d], kLbInc | (below[e] + s_cnt[d]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                s_gbase[d] += below[e];
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t d = tid; d < R; d += kOsThreads) s_cnt[d] = 0;
+    __syncthreads();
+    // stable ranking in index order (round, wave, lane), the tile staged in LDS in digit order
+#pragma unroll
+    for (int r = 0; r < kOsItems; ++r) {
+        const uint32_t j = (uint32_t)r * kOsThreads + (uint32_t)tid;
+        const bool ok = j < valid_n;
+        const uint32_t dg = (k[r] >> shift) & (R - 1u);
+        unsigned long long same = __ballot(ok);
+#pragma unroll
+        for (int bit = 0; bit < D; ++bit) {
+            const unsigned long long bb = __ballot((dg >> bit) & 1u);
+            same &= ((dg >> bit) & 1u) ? bb : ~bb;
+        }
+        const uint32_t rank = (uint32_t)__popcll(same & lt);
+        const bool leader = ok && rank == 0;
+        if (leader) s_wcnt[wave][dg] = (uint32_t)__popcll(same);
+        __syncthreads();
+        if (ok) {
+            uint32_t before = s_cnt[dg];
+            for (int w = 0; w < wave; ++w) before += s_wcnt[w][dg];
+            const uint32_t lpos = s_lbase[dg] + before + rank;
+            s_k[lpos] = k[r];
+            s_v[lpos] = v[r];
+        }
+        __syncthreads();
+        if (leader) {
+            atomicAdd(&s_cnt[dg], (uint32_t)__popcll(same));
+            s_wcnt[wave][dg] = 0;
+        }
+    }
+    __syncthreads();
+    // runs of equal digits go to consecutive places, written by consecutive threads
+    for (uint32_t i = tid; i < valid_n; i += kOsThreads) {
+        const uint32_t key = s_k[i];
+        const uint32_t dg = (key >> shift) & (R - 1u);
+        const uint32_t dst = s_gbase[dg] + (i - s_lbase[dg]);
+        if (dst < n) {   // always, when the histograms describe the keys
+            kout[dst] = key;
+            vout[dst] = s_v[i];
+        }
     }
 }
 
@@ -1498,161 +1843,9 @@ __global__ __launch_bounds__(256) void k_count_finalize(const uint32_t* partial,
     if (threadIdx.x == 0) ray_count[blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(256) void k_gather(const float4* q, const uint32_t* idx, uint32_t n, float4* out) {
-    const uint32_t j = blockIdx.x * 256u + threadIdx.x;
-    if (j >= n) return;
-    const uint32_t src = idx[j];
-    out[2 * (size_t)j] = q[2 * (size_t)src];
-    out[2 * (size_t)j + 1] = q[2 * (size_t)src + 1];
-}
-
 __global__ __launch_bounds__(256) void k_zero(uint32_t* p, size_t n) {
     const size_t j = (size_t)blockIdx.x * 256u + threadIdx.x;
     if (j < n) p[j] = 0u;
-}
-
-// ------------------------------------------------------------------ stable LSD radix sort
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 8;
-constexpr uint32_t kSortTile = kSortThreads * kSortItems;
-
-__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* keys, uint32_t n, int shift,
-                                                            uint32_t* hist, uint32_t nblocks) {
-    __shared__ uint32_t h[256];
-    const int tid = threadIdx.x;
-    h[tid] = 0;
-    __syncthreads();
-    const uint32_t base = blockIdx.x * kSortTile;
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint32_t j = base + (uint32_t)r * kSortThreads + (uint32_t)tid;
-        if (j < n) atomicAdd(&h[(keys[j] >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    hist[(size_t)tid * nblocks + blockIdx.x] = h[tid];
-}
-
-// Exclusive scan of m counts in three steps: chunk sums, scan of the chunk sums
-// (one workgroup), scan of each chunk plus its offset.  1024 threads x 4 items.
-constexpr uint32_t kScanChunk = 4096;
-
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    uint32_t x = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) wsum[wave] = x;
-    __syncthreads();
-    if (wave == 0) {
-        uint32_t w = lane < 16 ? wsum[lane] : 0u;
-        uint32_t z = w;
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-            const uint32_t y = __shfl_up(z, off);
-            if (lane >= off) z += y;
-        }
-        if (lane < 16) wsum[16 + lane] = z - w;   // exclusive prefix of wave sums
-        if (lane == 15) wsum[32] = z;
-    }
-    __syncthreads();
-    total = wsum[32];
-    const uint32_t r = wsum[16 + wave] + x - v;
-    __syncthreads();
-    return r;
-}
-
-__global__ __launch_bounds__(1024) void k_scan_reduce(const uint32_t* in, uint32_t m, uint32_t* sums) {
-    __shared__ uint32_t red[1024];
-    const uint32_t base = blockIdx.x * kScanChunk;
-    uint32_t v = 0;
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t i = base + (uint32_t)j * 1024u + threadIdx.x;
-        if (i < m) v += in[i];
-    }
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
-}
-
-// exclusive scan of the chunk sums in place (nchunks <= 4096)
-__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* sums, uint32_t nchunks) {
-    __shared__ uint32_t wsum[40];
-    const uint32_t i0 = threadIdx.x * 4u;
-    uint32_t v[4], t = 0;
-    for (int j = 0; j < 4; ++j) {
-        v[j] = (i0 + j < nchunks) ? sums[i0 + j] : 0u;
-        t += v[j];
-    }
-    uint32_t total;
-    uint32_t run = block_exclusive_scan(t, wsum, total);
-    for (int j = 0; j < 4; ++j) {
-        if (i0 + j < nchunks) sums[i0 + j] = run;
-        run += v[j];
-    }
-}
-
-__global__ __launch_bounds__(1024) void k_scan_down(uint32_t* data, uint32_t m, const uint32_t* sums) {
-    __shared__ uint32_t wsum[40];
-    const uint32_t i0 = blockIdx.x * kScanChunk + threadIdx.x * 4u;
-    uint32_t v[4], t = 0;
-    for (int j = 0; j < 4; ++j) {
-        v[j] = (i0 + j < m) ? data[i0 + j] : 0u;
-        t += v[j];
-    }
-    uint32_t total;
-    uint32_t run = block_exclusive_scan(t, wsum, total) + sums[blockIdx.x];
-    for (int j = 0; j < 4; ++j) {
-        if (i0 + j < m) data[i0 + j] = run;
-        run += v[j];
-    }
-}
-
-__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
-                                                               uint32_t* vout, uint32_t n, int shift,
-                                                               const uint32_t* offs, uint32_t nblocks) {
-    __shared__ uint32_t base_digit[256];
-    __shared__ uint32_t wave_cnt[kSortThreads / 64][256];
-    __shared__ uint32_t gofs[256];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    base_digit[tid] = 0;
-    gofs[tid] = offs[(size_t)tid * nblocks + blockIdx.x];
-    const unsigned long long lt = (1ull << lane) - 1ull;
-    const uint32_t tile = blockIdx.x * kSortTile;
-    for (int r = 0; r < kSortItems; ++r) {
-        for (int w = 0; w < kSortThreads / 64; ++w) wave_cnt[w][tid] = 0;
-        __syncthreads();
-        const uint32_t j = tile + (uint32_t)r * kSortThreads + (uint32_t)tid;
-        const bool valid = j < n;
-        const uint32_t key = valid ? kin[j] : 0u;
-        const uint32_t dg = (key >> shift) & 255u;
-        unsigned long long same = __ballot(valid);
-#pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            const unsigned long long bb = __ballot((dg >> bit) & 1u);
-            same &= ((dg >> bit) & 1u) ? bb : ~bb;
-        }
-        const uint32_t rank = (uint32_t)__popcll(same & lt);
-        if (valid && rank == 0) wave_cnt[wave][dg] = (uint32_t)__popcll(same);
-        __syncthreads();
-        if (valid) {
-            uint32_t before = base_digit[dg];
-            for (int w = 0; w < wave; ++w) before += wave_cnt[w][dg];
-            const uint32_t dst = gofs[dg] + before + rank;
-            kout[dst] = key;
-            vout[dst] = vin[j];
-        }
-        __syncthreads();
-        uint32_t add = 0;
-        for (int w = 0; w < kSortThreads / 64; ++w) add += wave_cnt[w][tid];
-        base_digit[tid] += add;
-        __syncthreads();
-    }
 }
 
 int g_trace_blocks[64] = {0};
@@ -1776,12 +1969,13 @@ hipError_t launch_raygen(const Frame& f, int s, float4* q, float4* state, float4
 
 hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const float4* q_in, float4* q_out,
                         float4* state, int32_t* hit_prim, float* hit_t, float* radiance, float4* rays_out,
-                        float4* shadow_rays, float4* shadow_light, hipStream_t st) {
+                        float4* shadow_rays, float4* shadow_light, uint32_t* fill, hipStream_t st) {
     const unsigned blocks = (unsigned)(f.nslots / (uint32_t)f.TS);
     const bool reuse = f.mode == PT_MODE_REUSE || f.mode == PT_MODE_REUSE_PLAIN || f.mode == PT_MODE_REUSE_WORLD;
-    const size_t lds = reuse ? (size_t)f.TS * 8 * sizeof(float) : 0;
+    // reuse exchange (8 words per slot), then the compaction's ranks (1 per slot) and wave sums (40)
+    const size_t lds = ((reuse ? (size_t)f.TS * 8 : 0) + (fill ? (size_t)f.TS + 40 : 0)) * sizeof(float);
     hipLaunchKernelGGL(k_shade, dim3(blocks), dim3(f.TS), lds, st, sc, f, b, s, q_in, q_out, state, hit_prim, hit_t,
-                       radiance, rays_out, shadow_rays, shadow_light);
+                       radiance, rays_out, shadow_rays, shadow_light, fill);
     return hipGetLastError();
 }
 
@@ -1807,40 +2001,73 @@ hipError_t launch_count_finalize(const uint32_t* partial, int stride, int parts,
     return hipGetLastError();
 }
 
-hipError_t launch_gather(const float4* q, const uint32_t* idx, uint32_t n, float4* out, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, st, q, idx, n, out);
+// ---- sorted modes and the plain sort
+// 30-bit keys: 4 passes of 8-bit digits.  3 passes of 10-bit digits measured slower (87 against
+// 37 us per pass for 2M keys on MI355X): a pass's look-back and tile-count words grow with the
+// number of digits, and at ~4 keys per digit and tile its writes are short runs.
+constexpr int kRenderDigit = 8;
+constexpr int kRenderPasses = 4;
+static_assert(kRenderDigit * kRenderPasses >= 30 && kRenderPasses <= 4, "the keys' 30 bits, at most 4 passes");
+constexpr int kPlainDigit = 8;                 // 32-bit keys: 4 passes of 8-bit digits
+constexpr int kPlainPasses = 4;
+
+static uint32_t sort_tiles(uint32_t n) { return (n + kOsTile - 1) / kOsTile; }
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// render workspace: keys, vals, their alternates (n each), the histograms and tile counters
+// (zeroed per bounce), the look-back words of every pass
+size_t sort_compacted_workspace_bytes(uint32_t n) {
+    const size_t R = (size_t)1 << kRenderDigit;
+    return 4 * al256((size_t)n * 4) + al256((kRenderPasses * R + kRenderPasses) * 4) +
+           al256((size_t)kRenderPasses * sort_tiles(n) * R * 4);
+}
+
+struct SortWs {
+    uint32_t *keys, *vals, *kalt, *valt, *hist, *ctr, *lookback;
+};
+
+static SortWs sort_ws(void* ws, uint32_t n) {
+    const size_t R = (size_t)1 << kRenderDigit;
+    char* p = (char*)ws;
+    SortWs w;
+    w.keys = (uint32_t*)p;
+    p += al256((size_t)n * 4);
+    w.vals = (uint32_t*)p;
+    p += al256((size_t)n * 4);
+    w.kalt = (uint32_t*)p;
+    p += al256((size_t)n * 4);
+    w.valt = (uint32_t*)p;
+    p += al256((size_t)n * 4);
+    w.hist = (uint32_t*)p;
+    w.ctr = w.hist + kRenderPasses * R;
+    p += al256((kRenderPasses * R + kRenderPasses) * 4);
+    w.lookback = (uint32_t*)p;
+    return w;
+}
+
+hipError_t launch_keys_compacted(const DevScene& sc, const float4* q, const uint32_t* fill, uint32_t region,
+                                 uint32_t nslots, int kind, void* ws, hipStream_t st) {
+    const uint32_t R = 1u << kRenderDigit;
+    const SortWs w = sort_ws(ws, nslots);
+    hipError_t e = launch_zero(w.hist, (size_t)kRenderPasses * R + kRenderPasses, st);
+    if (e != hipSuccess) return e;
+    const uint32_t kb = (nslots + kKeysPerThread * 1024 - 1) / (kKeysPerThread * 1024);
+    hipLaunchKernelGGL(k_keys_compacted<kRenderDigit>, dim3(kb), dim3(1024), 0, st, sc, q, fill,
+                       region, w.keys, w.vals, kind, kRenderPasses, w.hist, w.lookback,
+                       (uint32_t)((size_t)kRenderPasses * sort_tiles(nslots) * R));
     return hipGetLastError();
 }
 
-size_t sort_workspace_bytes(uint32_t n) {
-    const size_t nb = (n + kSortTile - 1) / kSortTile;
-    const size_t m = 256 * nb;
-    const size_t chunks = (m + kScanChunk - 1) / kScanChunk;
-    return 2 * (size_t)n * sizeof(uint32_t) + m * sizeof(uint32_t) + chunks * sizeof(uint32_t) + 256;
-}
-
-hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t n, void* ws, hipStream_t st) {
-    if (n <= 1) return hipSuccess;
-    const uint32_t nb = (n + kSortTile - 1) / kSortTile;
-    uint32_t* kalt = (uint32_t*)ws;
-    uint32_t* valt = kalt + n;
-    uint32_t* hist = valt + n;
-    const uint32_t m = 256u * nb;
-    const uint32_t chunks = (m + kScanChunk - 1) / kScanChunk;
-    uint32_t* csum = hist + m;
-    if (chunks > 4096u) return hipErrorInvalidValue;   // n > 2^32 / 64: outside the supported range
-    uint32_t* kin = keys;
-    uint32_t* vin = vals;
-    uint32_t* kout = kalt;
-    uint32_t* vout = valt;
-    for (int pass = 0; pass < 4; ++pass) {
-        const int shift = 8 * pass;
-        hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(kSortThreads), 0, st, kin, n, shift, hist, nb);
-        hipLaunchKernelGGL(k_scan_reduce, dim3(chunks), dim3(1024), 0, st, hist, m, csum);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, csum, chunks);
-        hipLaunchKernelGGL(k_scan_down, dim3(chunks), dim3(1024), 0, st, hist, m, csum);
-        hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, n, shift, hist, nb);
+hipError_t launch_sort_compacted(const uint32_t* fill, uint32_t nslots, void* ws, const uint32_t** perm,
+                                 hipStream_t st) {
+    const uint32_t R = 1u << kRenderDigit;
+    const SortWs w = sort_ws(ws, nslots);
+    const uint32_t tiles = sort_tiles(nslots);
+    uint32_t *kin = w.keys, *vin = w.vals, *kout = w.kalt, *vout = w.valt;
+    for (int ps = 0; ps < kRenderPasses; ++ps) {
+        hipLaunchKernelGGL(k_onesweep<kRenderDigit>, dim3(tiles), dim3(kOsThreads), 0, st, kin, vin, kout, vout, fill,
+                           0u, kRenderDigit * ps, w.hist + (size_t)ps * R, w.lookback + (size_t)ps * tiles * R,
+                           w.ctr + ps);
         uint32_t* tk = kin;
         kin = kout;
         kout = tk;
@@ -1848,7 +2075,45 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t n, void* ws
         vin = vout;
         vout = tv;
     }
-    return hipGetLastError();   // 4 passes: the result is back in keys/vals
+    *perm = vin;   // after the last pass: the queue slots in key order
+    return hipGetLastError();
+}
+
+size_t sort_workspace_bytes(uint32_t n) {
+    const size_t R = (size_t)1 << kPlainDigit;
+    return 2 * al256((size_t)n * 4) + al256((kPlainPasses * R + kPlainPasses) * 4) +
+           al256((size_t)kPlainPasses * sort_tiles(n) * R * 4);
+}
+
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t n, void* ws, hipStream_t st) {
+    if (n <= 1) return hipSuccess;
+    const uint32_t R = 1u << kPlainDigit;
+    const uint32_t tiles = sort_tiles(n);
+    char* p = (char*)ws;
+    uint32_t* kalt = (uint32_t*)p;
+    p += al256((size_t)n * 4);
+    uint32_t* valt = (uint32_t*)p;
+    p += al256((size_t)n * 4);
+    uint32_t* hist = (uint32_t*)p;
+    uint32_t* ctr = hist + kPlainPasses * R;
+    hipError_t e = launch_zero(hist, sort_workspace_bytes(n) / 4 - 2 * al256((size_t)n * 4) / 4, st);
+    if (e != hipSuccess) return e;
+    uint32_t* lookback = (uint32_t*)(p + al256((kPlainPasses * R + kPlainPasses) * 4));
+    const uint32_t hblocks = (n + 255) / 256 < 128u ? (n + 255) / 256 : 128u;
+    hipLaunchKernelGGL(k_digit_hist<kPlainDigit>, dim3(hblocks), dim3(256), 0, st, keys, n, kPlainPasses, hist);
+    uint32_t *kin = keys, *vin = vals, *kout = kalt, *vout = valt;
+    for (int ps = 0; ps < kPlainPasses; ++ps) {
+        hipLaunchKernelGGL(k_onesweep<kPlainDigit>, dim3(tiles), dim3(kOsThreads), 0, st, kin, vin, kout, vout,
+                           (const uint32_t*)nullptr, n, kPlainDigit * ps, hist + (size_t)ps * R,
+                           lookback + (size_t)ps * tiles * R, ctr + ps);
+        uint32_t* tk = kin;
+        kin = kout;
+        kout = tk;
+        uint32_t* tv = vin;
+        vin = vout;
+        vout = tv;
+    }
+    return hipGetLastError();   // an even number of passes: the result is back in keys/vals
 }
 
 }  // namespace pt
