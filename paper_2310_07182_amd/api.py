@@ -162,7 +162,7 @@ class Renderer:
     """Holds the workspace and output tensors for repeated frames of one configuration."""
 
     def __init__(self, scene: Scene, cfg: RenderConfig, stats: bool = False, timer: Timer | None = None,
-                 rays: bool = False, touched: bool = False):
+                 rays: bool = False, touched: bool = False, debug: bool = False):
         self.scene = scene
         self.cfg = cfg
         dev = scene.device
@@ -186,6 +186,8 @@ class Renderer:
             self.touched = (torch.zeros(inf["nnodes"] + inf["ntri"], dtype=torch.uint8, device=dev)
                             if (stats and touched) else None)
             self.rays = torch.zeros((B + 1, cfg.spp, cfg.h, cfg.w, 8), dtype=torch.float32, device=dev) if rays else None
+            self.debug = (torch.zeros((max(B, 1), cfg.spp, cfg.h, cfg.w, 4), dtype=torch.float32, device=dev)
+                          if debug else None)
         self.timer = timer
         self.out = capi.Outputs()
         self.out.radiance = self.radiance.data_ptr()
@@ -197,6 +199,7 @@ class Renderer:
         self.out.timer = timer.handle if timer is not None else None
         self.out.shadow_count = self.shadow_count.data_ptr() if cfg.nee else None
         self.out.touched = self.touched.data_ptr() if self.touched is not None else None
+        self.out.debug = self.debug.data_ptr() if self.debug is not None else None
 
     def render(self, seed: int = 1, camera: dict | None = None):
         cfg = self.cfg
@@ -219,6 +222,8 @@ class Renderer:
             r["shadow_rays_per_bounce"] = self.shadow_count.sum(dim=1)
         if self.touched is not None:
             r["touched"] = self.touched
+        if self.debug is not None:
+            r["debug"] = self.debug
         return r
 
     def touched_counts(self) -> tuple:
@@ -237,9 +242,9 @@ class Renderer:
 
 def render(scene: Scene, w, h, spp=1, bounces=2, mode="incoherent", tile=(8, 8), k=8,
            reuse_max_bounce=None, seed=1, camera=None, stats=False, rays=False, refill=0, leaf_gate=0,
-           nee=False, traversal=0, frame_groups=False) -> dict:
+           nee=False, traversal=0, frame_groups=False, debug=False) -> dict:
     r = Renderer(scene, RenderConfig(w, h, spp, bounces, mode, tuple(tile), k, reuse_max_bounce, refill, 0, leaf_gate,
-                                     nee, traversal, frame_groups), stats=stats, rays=rays)
+                                     nee, traversal, frame_groups), stats=stats, rays=rays, debug=debug)
     r.render(seed, camera)
     return r.results()
 

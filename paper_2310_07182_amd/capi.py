@@ -59,7 +59,7 @@ class SceneInfo(C.Structure):
 class Outputs(C.Structure):
     _fields_ = [("radiance", C.c_void_p), ("hit_prim", C.c_void_p), ("hit_t", C.c_void_p),
                 ("ray_count", C.c_void_p), ("stats", C.c_void_p), ("rays", C.c_void_p), ("timer", C.c_void_p),
-                ("shadow_count", C.c_void_p), ("touched", C.c_void_p)]
+                ("shadow_count", C.c_void_p), ("touched", C.c_void_p), ("debug", C.c_void_p)]
 
 
 class Job(C.Structure):

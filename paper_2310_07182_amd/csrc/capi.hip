@@ -622,7 +622,7 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
                 // the next rays go compacted into the regions counted by the next launch's fill words
                 uint32_t* fill_next = b < B ? work + ((size_t)(b + 1) * spp + s) * pt::kWorkWords + pt::kFillWord : nullptr;
                 e = pt::launch_shade(scene->dev, f, b, s, q[b & 1], q[(b + 1) & 1], state, out->hit_prim, out->hit_t,
-                                     out->radiance, (float4*)out->rays, shray, shc, fill_next, st);
+                                     out->radiance, (float4*)out->rays, shray, shc, fill_next, (float4*)out->debug, st);
             }
             if (e != hipSuccess) return hip_fail(e, "launch (shade)");
             if (f.nee && b < B) {

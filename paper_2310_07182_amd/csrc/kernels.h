@@ -140,9 +140,14 @@ hipError_t launch_raygen(const Frame& f, int s, float4* q, float4* state, float4
 // fill: null = the next rays at their slots (dead slots hold kNoRay records); else the live
 // rays compacted into 8 regions of f.region slots, region r's count in fill[r * kCounterStride]
 // (zero before the launch), dead rays not written
+// debug: null, or pt_outputs.debug (the record of hit b of every pixel with a path, b < B)
 hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const float4* q_in, float4* q_out,
                         float4* state, int32_t* hit_prim, float* hit_t, float* radiance, float4* rays_out,
-                        float4* shadow_rays, float4* shadow_light, uint32_t* fill, hipStream_t st);
+                        float4* shadow_rays, float4* shadow_light, uint32_t* fill, float4* debug, hipStream_t st);
+
+// flags of the per-ray record (the w word of pt_outputs.debug)
+constexpr uint32_t kDbgActive = 1u << 0, kDbgRep = 1u << 5, kDbgReused = 1u << 6, kDbgValid = 1u << 7;
+constexpr int kDbgClassShift = 1, kDbgCatShift = 3, kDbgSlotShift = 16;
 // next-event estimation: adds shadow_light[p].rgb to the radiance of path p when its shadow
 // ray exists (pixel word != kNoRay) and shadow_prim[p] == -1 (nothing in between)
 hipError_t launch_nee_accumulate(const float4* shadow_rays, const float4* shadow_light, const int32_t* shadow_prim,

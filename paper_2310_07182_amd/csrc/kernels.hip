@@ -290,8 +290,9 @@ __device__ __forceinline__ uint64_t claimed_ray(uint32_t v, uint32_t c) {
 // (fill, no permutation): the first nc = fill[c] slots of region c.  The index is monotone
 // in v, so the first v without a ray ends the counter.
 constexpr uint64_t kNoClaim = ~0ull;
-__device__ __forceinline__ uint64_t claim_index(const TraceArgs& a, uint32_t v, uint32_t c, uint32_t n, uint32_t nc) {
-    if (a.fill && !a.perm) return v < nc ? (uint64_t)c * a.region + v : kNoClaim;
+__device__ __forceinline__ uint64_t claim_index(bool regions, uint32_t region, uint32_t v, uint32_t c, uint32_t n,
+                                                uint32_t nc) {
+    if (regions) return v < nc ? (uint64_t)c * region + v : kNoClaim;
     const uint64_t i = claimed_ray(v, c);
     return i < n ? i : kNoClaim;
 }
@@ -312,8 +313,12 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
     __shared__ PairT pairs[kTraceBlock * kMaxLeaf];   // lane | (triangle in leaf) << 6
     const int lane = threadIdx.x;
     const uint32_t gtid = blockIdx.x * kTraceBlock + lane;
-    const uint32_t n = launch_rays(a);
-    uint32_t ncq = a.fill ? a.fill[(blockIdx.x % kRayCounters) * kCounterStride] : 0u;   // rays of counter cq
+    // merged launches (MULTI) never use compacted or permuted queues
+    const uint32_t* const fillp = MULTI ? nullptr : a.fill;
+    const uint32_t* const permp = MULTI ? nullptr : a.perm;
+    const bool regions = fillp && !permp;
+    const uint32_t n = MULTI ? a.n : launch_rays(a);
+    uint32_t ncq = fillp ? fillp[(blockIdx.x % kRayCounters) * kCounterStride] : 0u;   // rays of counter cq
     const unsigned long long lt = (1ull << lane) - 1ull;
     unsigned long long nv = 0, nt = 0;
     uint32_t traced = 0;
@@ -347,18 +352,18 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(DevScene sc, TraceArgs a,
             uint32_t base = 0;
             if (lane == 0) base = atomicAdd(a.work + c * kCounterStride, need);
             base = __shfl(base, 0);
-            if (claim_index(a, base + need, c, n, nc) == kNoClaim) {   // this counter has no rays left
+            if (claim_index(regions, a.region, base + need, c, n, nc) == kNoClaim) {   // this counter has no rays left
                 if (++tries == kRayCounters) exhausted = true;
                 cq = (cq + 1u) % kRayCounters;
-                ncq = a.fill ? a.fill[cq * kCounterStride] : 0u;
+                ncq = fillp ? fillp[cq * kCounterStride] : 0u;
             }
             const uint32_t rank = (uint32_t)__popcll(idle & lt);
             if (!have && rank < need) {
-                const uint64_t i64 = claim_index(a, base + rank, c, n, nc);
+                const uint64_t i64 = claim_index(regions, a.region, base + rank, c, n, nc);
                 const uint32_t i = (uint32_t)i64;
                 if (i64 != kNoClaim) {
                     const float4* rays = a.rays;
-                    uint32_t li = a.perm ? a.perm[i] : i;   // sorted launches read the rays through the sort's permutation
+                    uint32_t li = permp ? permp[i] : i;   // sorted launches read the rays through the sort's permutation
                     if constexpr (MULTI) {
                         int lo = 0, hi = njobs - 1;
                         while (lo < hi) {
@@ -733,8 +738,12 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
     __shared__ unsigned long long bestk[kTraceBlock];
     const int lane = threadIdx.x;
     const uint32_t gtid = blockIdx.x * kTraceBlock + lane;
-    const uint32_t n = launch_rays(a);
-    uint32_t ncq = a.fill ? a.fill[(blockIdx.x % kRayCounters) * kCounterStride] : 0u;   // rays of counter cq
+    // merged launches (MULTI) never use compacted or permuted queues
+    const uint32_t* const fillp = MULTI ? nullptr : a.fill;
+    const uint32_t* const permp = MULTI ? nullptr : a.perm;
+    const bool regions = fillp && !permp;
+    const uint32_t n = MULTI ? a.n : launch_rays(a);
+    uint32_t ncq = fillp ? fillp[(blockIdx.x % kRayCounters) * kCounterStride] : 0u;   // rays of counter cq
     const unsigned long long lt = (1ull << lane) - 1ull;
     // a shadow ray keeps hits at t < kShadowTmax; prim ids are below INT32_MAX
     const unsigned long long key0 = a.shadow ? hit_key(kShadowTmax, 0u) : hit_key(INFINITY, (uint32_t)INT32_MAX);
@@ -778,18 +787,18 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
             uint32_t base = 0;
             if (lane == 0) base = atomicAdd(a.work + c * kCounterStride, need);
             base = __shfl(base, 0);
-            if (claim_index(a, base + need, c, n, nc) == kNoClaim) {   // this counter has no rays left
+            if (claim_index(regions, a.region, base + need, c, n, nc) == kNoClaim) {   // this counter has no rays left
                 if (++tries == kRayCounters) exhausted = true;
                 cq = (cq + 1u) % kRayCounters;
-                ncq = a.fill ? a.fill[cq * kCounterStride] : 0u;
+                ncq = fillp ? fillp[cq * kCounterStride] : 0u;
             }
             const uint32_t rank = (uint32_t)__popcll(idle & lt);
             if (!have && rank < need) {
-                const uint64_t i64 = claim_index(a, base + rank, c, n, nc);
+                const uint64_t i64 = claim_index(regions, a.region, base + rank, c, n, nc);
                 const uint32_t i = (uint32_t)i64;
                 if (i64 != kNoClaim) {
                     const float4* rays = a.rays;
-                    uint32_t li = a.perm ? a.perm[i] : i;   // sorted launches read the rays through the sort's permutation
+                    uint32_t li = permp ? permp[i] : i;   // sorted launches read the rays through the sort's permutation
                     if constexpr (MULTI) {
                         int lo = 0, hi = njobs - 1;
                         while (lo < hi) {
@@ -899,7 +908,7 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
                 }
                 return false;
             }
-            return true;
+            return !exhausted;
         }
         // ---- a lane on a leaf queues its triangles and takes the next node
         const bool on_leaf = have && node < 0 && node != kDone;
@@ -1091,11 +1100,18 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
         }
         return true;
     };
-    while (!exhausted) step(std::false_type{});
-    // the drain: every lane that walks owns its ray
-    own = have;
-    owner = lane;
-    while (step(std::true_type{})) {
+    if constexpr (MULTI) {
+        // merged launches of a batch: their many small jobs leave little drain, and the
+        // copies of the per-lane job pointers a donation needs cost registers: no donation
+        while (step(std::false_type{})) {
+        }
+    } else {
+        while (!exhausted) step(std::false_type{});
+        // the drain: every lane that walks owns its ray
+        own = have;
+        owner = lane;
+        while (step(std::true_type{})) {
+        }
     }
     unsigned int tsum = traced;
     for (int off = 32; off > 0; off >>= 1) tsum += __shfl_down(tsum, off);
@@ -1189,7 +1205,7 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
                                            const float4* __restrict__ q_in, float4* __restrict__ q_out,
                                            float4* state, int32_t* hit_prim, float* hit_t, float* radiance,
                                            float4* rays_out, float4* shadow_rays, float4* shadow_light, float* lds,
-                                           uint32_t* fill) {
+                                           uint32_t* fill, float4* debug) {
     // group exchange in LDS, TS entries each: own tangent exit, tree sums, info bits, min active slot
     const int TS = f.TS;
     float* sq0 = lds;
@@ -1306,6 +1322,9 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
     }
     V3 use = own;
     bool use_ok = own_ok;
+    // per-ray record of the rules applied (pt_outputs.debug): active, material class, group
+    // category, representative, reused, ray exists, shuffled slot
+    uint32_t dfl = active ? (kDbgActive | ((uint32_t)kind << kDbgClassShift)) : 0u;
     bool use_world = false;   // direct reuse: the next direction is given in world space
     V3 wdir = mk3(0.f, 0.f, 0.f);
     uint32_t newpos = p;
@@ -1368,7 +1387,25 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
         use_world = world && active && kind == 0 && srep[root] < f.WH && (int)slot != rslot && repq.x <= 1.5f;
         wdir = repq;
         use_ok = use_world ? dot3(repq, n) > 0.0f : use_ok;
+        if (active) {
+            dfl |= slot << kDbgSlotShift;
+            if (!world) {
+                const uint32_t cat = (info & 1) ? ((info & 2) ? 3u : 1u) : ((info & 2) ? 2u : 0u);
+                dfl |= cat << kDbgCatShift;
+                if (cat == 1u && (int)slot == rslot) dfl |= kDbgRep;
+                if ((take_rep && (int)slot != rslot) || take_avg) dfl |= kDbgReused;
+            } else {
+                if (srep[root] < f.WH && (int)slot == rslot) dfl |= kDbgRep;
+                if (use_world) dfl |= kDbgReused;
+            }
+        }
         newpos = blk * (uint32_t)TS + (uint32_t)e;
+    }
+    if (debug && b < f.B && spx.inside) {
+        const V3 dq = use_world ? wdir : use;
+        debug[((size_t)b * f.spp + s) * plane + pix] =
+            active ? make_float4(dq.x, dq.y, dq.z, __uint_as_float(dfl | (use_ok ? kDbgValid : 0u)))
+                   : make_float4(0.f, 0.f, 0.f, __uint_as_float(0u));
     }
     if (fill && b < f.B) {
         // the compacted queue: the live rays of workgroup blk go, in their queue order (group by
@@ -1444,10 +1481,10 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
 __global__ __launch_bounds__(1024) void k_shade(DevScene sc, Frame f, int b, int s, const float4* __restrict__ q_in,
                                                 float4* __restrict__ q_out, float4* state, int32_t* hit_prim,
                                                 float* hit_t, float* radiance, float4* rays_out, float4* shadow_rays,
-                                                float4* shadow_light, uint32_t* fill) {
+                                                float4* shadow_light, uint32_t* fill, float4* debug) {
     extern __shared__ float lds[];
     shade_body(sc, f, b, s, blockIdx.x, q_in, q_out, state, hit_prim, hit_t, radiance, rays_out, shadow_rays,
-               shadow_light, lds, fill);
+               shadow_light, lds, fill, debug);
 }
 
 // adds the light of unblocked shadow rays to their paths (one thread per path slot)
@@ -1469,7 +1506,7 @@ __global__ __launch_bounds__(1024) void k_shade_multi(const StepJob* jobs, int n
     const int j = job_of_block(jobs, njobs, blockIdx.x);
     const StepJob& J = jobs[j];
     shade_body(J.sc, J.f, J.b, J.s, blockIdx.x - J.block_start, J.q_in, J.q_out, J.state, J.hit_prim, J.hit_t,
-               J.radiance, nullptr, nullptr, nullptr, lds, nullptr);
+               J.radiance, nullptr, nullptr, nullptr, lds, nullptr, nullptr);
 }
 
 // ------------------------------------------------------------------ two-point key, gather
@@ -1969,13 +2006,13 @@ hipError_t launch_raygen(const Frame& f, int s, float4* q, float4* state, float4
 
 hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const float4* q_in, float4* q_out,
                         float4* state, int32_t* hit_prim, float* hit_t, float* radiance, float4* rays_out,
-                        float4* shadow_rays, float4* shadow_light, uint32_t* fill, hipStream_t st) {
+                        float4* shadow_rays, float4* shadow_light, uint32_t* fill, float4* debug, hipStream_t st) {
     const unsigned blocks = (unsigned)(f.nslots / (uint32_t)f.TS);
     const bool reuse = f.mode == PT_MODE_REUSE || f.mode == PT_MODE_REUSE_PLAIN || f.mode == PT_MODE_REUSE_WORLD;
     // reuse exchange (8 words per slot), then the compaction's ranks (1 per slot) and wave sums (40)
     const size_t lds = ((reuse ? (size_t)f.TS * 8 : 0) + (fill ? (size_t)f.TS + 40 : 0)) * sizeof(float);
     hipLaunchKernelGGL(k_shade, dim3(blocks), dim3(f.TS), lds, st, sc, f, b, s, q_in, q_out, state, hit_prim, hit_t,
-                       radiance, rays_out, shadow_rays, shadow_light, fill);
+                       radiance, rays_out, shadow_rays, shadow_light, fill, debug);
     return hipGetLastError();
 }
 

@@ -194,6 +194,39 @@ def test_render_parity_frame_groups(api, orc, torch_dev, mode, tile, k, w, h, sp
     assert np.array_equal(g["rays_per_bounce"].cpu().numpy(), o["rays_per_bounce"].astype(np.int64))
 
 
+@pytest.mark.parametrize("mode,tile,k,frame_groups", [
+    ("reuse", (8, 8), 8, False), ("reuse", (4, 4), 4, False), ("reuse", (16, 16), 32, True),
+    ("reuse", (8, 8), 64, False), ("reuse_world", (8, 8), 8, False), ("reuse_plain", (8, 8), 8, False),
+    ("incoherent", (8, 8), 8, False), ("sorted", (8, 8), 8, False),
+])
+def test_rule_records_match_oracle(api, orc, torch_dev, mode, tile, k, frame_groups):
+    """The per-ray record of the rules (pt_outputs.debug) against the oracle's, at every hit
+    of every pixel: the flags (active, material class, group category, representative,
+    reused, ray exists, shuffled slot) bit for bit, and the tangent direction taken bit for
+    bit wherever a next ray exists: the GPU applies the diffuse, glossy and hybrid rules of
+    Sec. 3.2 in the groups of Sec. 3.3 exactly as the oracle does."""
+    s, sc, osc = both(api, orc, "mixed_small")
+    w, h, spp, B = 83, 61, 2, 3
+    _say(f"[gpu] rule records {w}x{h} spp={spp} B={B} mode={mode} tile={tile} k={k} frame_groups={frame_groups}")
+    g = api.render(sc, w, h, spp, B, mode, tile, k, None, 55, rays=True, frame_groups=frame_groups, debug=True)
+    torch_dev.cuda.synchronize()
+    o = osc.render(w, h, spp, B, mode=mode, tile=tile, k=k, seed=55, debug=True, frame_groups=frame_groups)
+    compare_render(g, o, tile, mode)
+    gd = g["debug"].cpu().numpy()
+    gf = np.ascontiguousarray(gd[..., 3]).view(np.uint32)
+    of = o["dbg_flags"].view(np.uint32)
+    assert np.array_equal(gf, of)
+    valid = (of & orc.F_VALID) != 0
+    assert valid.sum() > 0
+    gq = np.ascontiguousarray(gd[..., :3]).view(np.uint32)
+    assert np.array_equal(gq[valid], o["dbg_q"].view(np.uint32)[valid])
+    if mode == "reuse":
+        # every category occurs (groups of K <= 8 pixels in this mixed scene), and reused directions
+        cats = (of[(of & orc.F_ACTIVE) != 0] >> orc.F_CAT_SH) & 3
+        assert (cats == 1).any() and (cats == 3).any() and (k > 8 or (cats == 2).any())
+        assert ((of & orc.F_REUSED) != 0).any()
+
+
 @pytest.mark.parametrize("mode,refill", [("incoherent", 1), ("sorted", 64), ("reuse", 8), ("reuse", 64),
                                          ("sorted", 1), ("incoherent", 40)])
 def test_render_parity_refill(api, orc, torch_dev, mode, refill):
