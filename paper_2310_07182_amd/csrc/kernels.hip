@@ -922,9 +922,12 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
             total += (uint32_t)__popcll(qb) << bit;
         }
         if (on_leaf) {
-            const uint32_t first = code >> 3;
-            for (uint32_t j = 0; j < cnt; ++j)
-                queue[(qtail + off + j) & (uint32_t)(kLeafQ - 1)] = ((uint32_t)lane << kQTriBits) | (first + j);
+            // a leaf holds at most kMaxLeaf triangles: one predicated store each
+            const uint32_t tag = ((uint32_t)lane << kQTriBits) | (code >> 3);
+            const uint32_t pos = qtail + off;
+#pragma unroll
+            for (uint32_t j = 0; j < (uint32_t)kMaxLeaf; ++j)
+                if (j < cnt) queue[(pos + j) & (uint32_t)(kLeafQ - 1)] = tag + j;
             last = qtail + off + cnt - 1u;
             if (sp == 0 && novf > 0) {
                 const int m = novf < kStackLds / 2 ? novf : kStackLds / 2;
