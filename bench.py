@@ -346,10 +346,10 @@ def _median_ms(run, reps):
     return float(np.median(times)), [round(t, 3) for t in times]
 
 
-def bench_batched(api, serve, autotune, scs, args):
+def bench_batched(api, serve, autotune, scs, args, tune=True):
     """Batched workload: 64 jobs over the resident scenes, mixed resolution and spp,
     4 bounces; per-job pt_render calls vs one batch (merged launches, captured graph)
-    with the default and the autotuned launch parameters."""
+    with the default and (tune) the autotuned launch parameters."""
     import torch
     out = {}
     for mode in args.modes.split(","):
@@ -388,6 +388,14 @@ def bench_batched(api, serve, autotune, scs, args):
         default = dict(autotune.DEFAULT)
         d_ms, d_all = batch_ms(default)
         e_ms, _ = batch_ms(default, graph=False)
+        if not tune:
+            out[mode] = dict(jobs=len(reqs), secondary_rays=rays,
+                             per_job_ms=round(per_ms, 3), per_job_mrays_s=round(rays / per_ms / 1e3, 1),
+                             batch_graph_ms=round(d_ms, 3), batch_graph_mrays_s=round(rays / d_ms / 1e3, 1),
+                             batch_stepped_no_graph_ms=round(e_ms, 3), speedup_vs_per_job=round(per_ms / d_ms, 3),
+                             runs_ms=dict(per_job=per_all, batch=d_all))
+            log(f"[batched] {mode}: {json.dumps(out[mode])}")
+            continue
         t0 = time.perf_counter()
         best, _, tlog = autotune.coordinate_descent(lambda p: batch_ms(p)[0], autotune.search_space(mode), default)
         tune_s = time.perf_counter() - t0
@@ -774,6 +782,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="all",
                     help="all (indoor, then landscape: the default run) or one of the scene configs")
+    ap.add_argument("--no-deploy", action="store_true",
+                    help="leave out the short batched and serving run of the default workload")
     ap.add_argument("--latency-frames", type=int, default=200,
                     help="frames rendered after the timed ones, for the p50/p99 frame latency")
     ap.add_argument("--modes", default="reuse,incoherent,sorted")
@@ -1036,6 +1046,34 @@ def bench_config(api, scenes, name, points, args, torch):
     return results, info
 
 
+def bench_deploy(api, scenes, args, resident):
+    """A short run of the deployment patterns over the resident scenes (indoor and landscape
+    from the frame runs, plus tiny and mid): 64 mixed jobs as per-job pt_render calls and as
+    one batch (merged launches, captured graph, default launch parameters), and a Poisson
+    serving run at 100 requests/s with continuous batching, for reuse and incoherent jobs."""
+    import types
+    from paper_2310_07182_amd import autotune, serve
+    scs = dict(resident)
+    for n in ("tiny", "mid"):
+        scs[n] = api.Scene(getattr(scenes, n)(), device="cuda:0")
+    a = types.SimpleNamespace(modes="reuse,incoherent", jobs=64, reps=3, rates="100", requests=400, serve_warmup=50,
+                              budget_gb=200.0, max_jobs=64)
+    log("[bench] deployment: batched")
+    batched = bench_batched(api, serve, autotune, scs, a, tune=False)
+    log("[bench] deployment: serving")
+    serving, setup = bench_serve(api, serve, scs, a)
+    keep = ("requests", "latency_ms_p50", "latency_ms_p99", "mrays_s", "requests_per_s", "max_in_flight",
+            "refused_admissions")
+    return {"workload": f"{a.jobs} mixed jobs / {a.requests} Poisson requests at 100/s over resident scenes "
+                        f"{sorted(scs)}: resolutions {[f'{w}x{h}' for w, h in serve.RESOLUTIONS]}, spp "
+                        f"{list(serve.SPPS)}, 4 bounces, tile 8x8 / K=8; first {a.serve_warmup} requests excluded",
+            "batched": {m: {k: v[k] for k in ("jobs", "secondary_rays", "per_job_ms", "batch_graph_ms",
+                                               "batch_stepped_no_graph_ms", "batch_graph_mrays_s", "speedup_vs_per_job")}
+                        for m, v in batched.items()},
+            "serving": {m: {k: v[k] for k in keep if k in v} for m, v in serving.items()},
+            "serving_setup": setup}
+
+
 def bench_frames(api, scenes, args, torch):
     """The default run: every configured workload, its modes and extra points, the memory
     ceilings, the roofline of the traversal kernel and the CPU oracle baseline."""
@@ -1047,10 +1085,13 @@ def bench_frames(api, scenes, args, torch):
     for name, points in plan:
         res, info = bench_config(api, scenes, name, points, args, torch)
         out[name] = (res, info)
+    deploy = None
+    if args.config == "all" and not args.no_deploy:
+        deploy = bench_deploy(api, scenes, args, {n: info["sc"] for n, (res, info) in out.items()})
+    for name, (res, info) in out.items():
         if name != plan[0][0]:
-            # large scenes leave the device before the next one is built
             del info["sc"], info["scene"]
-            torch.cuda.empty_cache()
+    torch.cuda.empty_cache()
     log("[bench] memory ceilings")
     ceil = measure_ceilings(api)
     log(f"[bench] ceilings: {ceil}")
@@ -1104,6 +1145,8 @@ def bench_frames(api, scenes, args, torch):
                       "p99_frame_ms": round(h["frame_ms_p99"], 4),
                       "modes": {lab: _mode_summary(v, args.nee) for lab, v in res.items()},
                       "roofline": roofline(h, info["sc_info"], args.traversal, ceil, name, info["level"])}
+    if deploy is not None:
+        line["deployment"] = deploy
     line["ceilings"] = ceil
     line["cpu_baseline"] = None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample",
                                                                          "single_core_value", "single_core_sample")}
