@@ -35,6 +35,9 @@ __device__ __forceinline__ V3 unit3(V3 v) {
     return scl3(v, inv);
 }
 __device__ __forceinline__ V3 xyz(float4 v) { return mk3(v.x, v.y, v.z); }
+// component-wise select: a select of whole structs can be lowered to a select of their
+// addresses, which puts the candidates in scratch memory
+__device__ __forceinline__ V3 sel3(bool c, V3 a, V3 b) { return mk3(c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z); }
 
 // ------------------------------------------------------------------ Philox4x64-10
 struct U64x4 {
@@ -1284,7 +1287,7 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
     float gw[3];
     const bool g_ok = ggx_dir(wi, m.alpha, m.albedo, u2, u3, gg, gw);
     const V3 mir = mk3(-wi.x, -wi.y, wi.z);
-    const V3 own = kind == 0 ? lam : (kind == 1 ? gg : mir);
+    const V3 own = sel3(kind == 0, lam, sel3(kind == 1, gg, mir));
     const bool own_ok = active && (kind == 0 ? true : (kind == 1 ? g_ok : mir.z > 0.0f));
     float w3[3];
     for (int c = 0; c < 3; ++c) w3[c] = kind == 1 ? gw[c] : m.albedo[c];
@@ -1352,7 +1355,7 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
         const bool gl_exit = active && kind != 0 && own_ok;
         // direct reuse shares the own exit in world space; x = 2 marks a sample that died
         const V3 ow = tangent_to_world(own, tt, bt, n);
-        const V3 shared = world ? (own_ok ? ow : mk3(2.0f, 0.0f, 0.0f)) : own;
+        const V3 shared = sel3(world, sel3(own_ok, ow, mk3(2.0f, 0.0f, 0.0f)), own);
         sq0[e] = shared.x;
         sq1[e] = shared.y;
         sq2[e] = shared.z;
@@ -1383,7 +1386,7 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
         const bool take_avg = !world && active && kind == 0 && (info & 2) && (info & 4);
         const V3 repq = mk3(sq0[r], sq1[r], sq2[r]);
         const V3 avgq = unit3(mk3(ss0[root], ss1[root], ss2[root]));
-        use = take_rep ? repq : (take_avg ? avgq : use);
+        use = sel3(take_rep, repq, sel3(take_avg, avgq, use));
         use_ok = (take_rep || take_avg) ? true : use_ok;
         // direct reuse: Lambert members other than the representative take its world
         // direction; a member below whose surface it points ends its path
@@ -1405,7 +1408,7 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
         newpos = blk * (uint32_t)TS + (uint32_t)e;
     }
     if (debug && b < f.B && spx.inside) {
-        const V3 dq = use_world ? wdir : use;
+        const V3 dq = sel3(use_world, wdir, use);
         debug[((size_t)b * f.spp + s) * plane + pix] =
             active ? make_float4(dq.x, dq.y, dq.z, __uint_as_float(dfl | (use_ok ? kDbgValid : 0u)))
                    : make_float4(0.f, 0.f, 0.f, __uint_as_float(0u));
@@ -1444,7 +1447,7 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
     if (b < f.B) {
         float4 o0 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1)), o1 = make_float4(0.f, 0.f, 0.f, __uint_as_float(kNoRay));
         if (active && use_ok) {
-            const V3 nd = use_world ? wdir : tangent_to_world(use, tt, bt, n);
+            const V3 nd = sel3(use_world, wdir, tangent_to_world(use, tt, bt, n));
             for (int c = 0; c < 3; ++c) T[c] = T[c] * w3[c];
             o0 = make_float4(origin.x, origin.y, origin.z, __int_as_float(prim));
             o1 = make_float4(nd.x, nd.y, nd.z, __uint_as_float(pix));
