@@ -1074,6 +1074,66 @@ def bench_deploy(api, scenes, args, resident):
             "serving_setup": setup}
 
 
+def bench_sort_yardstick(api, torch, n, reps=20):
+    """The sorted modes' radix sort (pt_sort_pairs: 4 passes of 8-bit digits) beside the vendor
+    library's device radix sort (rocPRIM radix_sort_pairs in libptsortref.so) on n seeded
+    uniform 30-bit keys with their indices as values; median microseconds of reps sorts each."""
+    import ctypes as C
+    from paper_2310_07182_amd import build as B
+    L = C.CDLL(B.SORTREF_LIB)
+    L.ptref_sort_workspace_bytes.argtypes = [C.c_uint32, C.c_int, C.POINTER(C.c_size_t)]
+    L.ptref_sort_pairs.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_uint32, C.c_int, C.c_void_p]
+    rng = np.random.default_rng(2310071825)
+    k0 = torch.from_numpy(rng.integers(0, 1 << 30, n, dtype=np.int64).astype(np.int32)).to("cuda:0")
+    v0 = torch.arange(n, dtype=torch.int32, device="cuda:0")
+    k1, v1 = torch.empty_like(k0), torch.empty_like(v0)
+    kr, vr = torch.empty_like(k0), torch.empty_like(v0)
+    st = torch.cuda.current_stream()
+    out = {"n": n, "keys": "uniform 30-bit, seeded; values = indices", "reps": reps}
+
+    def ours():
+        k1.copy_(k0)
+        v1.copy_(v0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        api.sort_pairs(k1, v1)
+        b.record(st)
+        return a, b
+
+    for bits in (30, 32):
+        need = C.c_size_t(0)
+        assert L.ptref_sort_workspace_bytes(n, bits, C.byref(need)) == 0
+        ws = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device="cuda:0")
+
+        def lib_sort():
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            rc = L.ptref_sort_pairs(ws.data_ptr(), ws.numel(), k0.data_ptr(), kr.data_ptr(), v0.data_ptr(),
+                                    vr.data_ptr(), n, bits, st.cuda_stream)
+            b.record(st)
+            assert rc == 0, rc
+            return a, b
+
+        times = []
+        for i in range(reps + 2):
+            a, b = lib_sort()
+            torch.cuda.synchronize()
+            if i >= 2:
+                times.append(a.elapsed_time(b) * 1e3)
+        out[f"rocprim_{bits}bit_us"] = round(float(np.median(times)), 1)
+    times = []
+    for i in range(reps + 2):
+        a, b = ours()
+        torch.cuda.synchronize()
+        if i >= 2:
+            times.append(a.elapsed_time(b) * 1e3)
+    out["ours_us"] = round(float(np.median(times)), 1)
+    # both sorts are stable: equal keys and equal values
+    out["same_result"] = bool(torch.equal(k1, kr) and torch.equal(v1, vr))
+    return out
+
+
 def bench_frames(api, scenes, args, torch):
     """The default run: every configured workload, its modes and extra points, the memory
     ceilings, the roofline of the traversal kernel and the CPU oracle baseline."""
@@ -1092,6 +1152,19 @@ def bench_frames(api, scenes, args, torch):
         if name != plan[0][0]:
             del info["sc"], info["scene"]
     torch.cuda.empty_cache()
+    yard = None
+    res_first = out[plan[0][0]][0]
+    srt = next((v for v in res_first.values() if v["mode"] == "sorted" and not v.get("frame_groups")), None)
+    if srt is not None:
+        nb = len(srt["rays_per_bounce"]) - 1
+        n_live = int(round(float(np.mean(srt["rays_per_bounce"][1:]))))
+        log(f"[bench] sort yardstick, {n_live} keys")
+        yard = bench_sort_yardstick(api, torch, n_live)
+        yard["in_frame_us_per_bounce"] = {
+            "keys": round(srt["ms_by_kind"].get(3, 0.0) * 1e3 / nb, 1),
+            "sort": round(srt["ms_by_kind"].get(4, 0.0) * 1e3 / nb, 1),
+            "workload": f"{plan[0][0]} sorted mode: live rays of a bounce, 30-bit keys, 4 passes of 8-bit digits"}
+        log(f"[bench] sort yardstick: {yard}")
     log("[bench] memory ceilings")
     ceil = measure_ceilings(api)
     log(f"[bench] ceilings: {ceil}")
@@ -1147,6 +1220,8 @@ def bench_frames(api, scenes, args, torch):
                       "roofline": roofline(h, info["sc_info"], args.traversal, ceil, name, info["level"])}
     if deploy is not None:
         line["deployment"] = deploy
+    if yard is not None:
+        line["sort_yardstick"] = yard
     line["ceilings"] = ceil
     line["cpu_baseline"] = None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample",
                                                                          "single_core_value", "single_core_sample")}

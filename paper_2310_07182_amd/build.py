@@ -10,6 +10,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["kernels.hip", "probe.hip", "capi.hip", "bvh_build.cpp"]
+# the vendor library's radix sort behind a C entry point (the sort's yardstick in the benchmark)
+SORTREF_LIB = os.path.join(HERE, "libptsortref.so")
+SORTREF_SOURCES = ["sort_reference.hip"]
 
 # -ffp-contract=off: the ray chain is binary32 without FMA contraction (host and device).
 # -packed-fp32-ops off: no packed FP32 instructions are generated.
@@ -30,9 +33,18 @@ def build(verbose: bool = False, sanitize: bool = False) -> str:
     """Compiles libpt.so; with sanitize, libpt_san.so with host-side ASan and UBSan (load it with
     the compiler's ASan runtime preloaded; for CPU runs of the host code)."""
     out = SAN_LIB if sanitize else LIB
-    tmp = out + ".tmp"
     flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-g"] + SAN_HOST if sanitize else FLAGS
-    cmd = [HIPCC] + flags + ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    return _compile(out, flags, SOURCES, verbose)
+
+
+def build_sortref(verbose: bool = False) -> str:
+    """Compiles libptsortref.so (pt_sortref.h)."""
+    return _compile(SORTREF_LIB, FLAGS, SORTREF_SOURCES, verbose)
+
+
+def _compile(out, flags, sources, verbose):
+    tmp = out + ".tmp"
+    cmd = [HIPCC] + flags + ["-o", tmp] + [os.path.join(CSRC, s) for s in sources]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -50,3 +62,4 @@ def build(verbose: bool = False, sanitize: bool = False) -> str:
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_sortref(verbose=True))

@@ -29,6 +29,19 @@ def test_exports_every_declared_symbol(L):
     assert decl == set(capi.PROTOTYPES), decl ^ set(capi.PROTOTYPES)
 
 
+def test_sortref_exports_every_declared_symbol():
+    import ctypes
+
+    from paper_2310_07182_amd import build as B
+
+    hdr = open(os.path.join(ROOT, "include", "pt_sortref.h")).read()
+    decl = set(re.findall(r"^int\s+(ptref_[a-z0-9_]+)\s*\(", hdr, re.M))
+    assert decl == {"ptref_sort_workspace_bytes", "ptref_sort_pairs"}, decl
+    L2 = ctypes.CDLL(B.SORTREF_LIB)
+    for name in sorted(decl):
+        assert hasattr(L2, name), name
+
+
 def _desc(scene):
     tris = np.ascontiguousarray(scene["tris"], np.float32)
     mat = np.ascontiguousarray(scene["tri_mat"], np.uint32)
