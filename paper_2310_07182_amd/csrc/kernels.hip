@@ -1589,19 +1589,18 @@ __global__ __launch_bounds__(256) void k_keys(DevScene sc, const float4* q, uint
 }
 
 // ------------------------------------------------------------------ stable radix sort, one pass per digit
-// Each pass (Merrill and Garland's decoupled look-back, as in single-pass "onesweep" radix
-// sorts): a workgroup takes the next tile id from a counter (ids follow the order workgroups
-// start in, so every lower tile belongs to a workgroup that is already running), counts the
-// tile's digits, publishes the counts, and adds the counts of the lower tiles by walking back
-// until it meets one that has published its inclusive prefix (tile 0 publishes that at once).
-// Keys are ranked stably in the tile (by index), staged in LDS in digit order and written out
-// in runs.  The global start of each digit comes from histograms of all passes taken before
-// the first pass.
+// Each pass is a single kernel (in the manner of single-pass "onesweep" radix sorts, with
+// a two-level look-back in place of Merrill and Garland's walk over every lower tile): a
+// workgroup takes the next tile id from a counter (ids follow the order workgroups start in,
+// so every lower tile belongs to a workgroup that is already running), counts the tile's
+// digits and publishes the counts, ranks its keys stably, and adds the counts of the lower
+// tiles from per-block sums.  Keys are staged in LDS in digit order and written out in runs.
+// The global start of each digit comes from histograms of all passes taken before the first
+// pass.
 constexpr int kOsThreads = 256;
 constexpr int kOsItems = 16;
 constexpr uint32_t kOsTile = (uint32_t)kOsThreads * kOsItems;
 constexpr uint32_t kLbAgg = 1u << 30, kLbInc = 2u << 30, kLbCount = (1u << 30) - 1u;
-constexpr int kLbWindow = 16;   // lower tiles whose words one look-back step loads at once
 
 // exclusive scan over the 256 threads of a workgroup; *total = sum
 __device__ __forceinline__ uint32_t scan256(uint32_t v, uint32_t* wsum, uint32_t* total) {
@@ -1703,137 +1702,110 @@ __global__ __launch_bounds__(256) void k_digit_hist(const uint32_t* keys, uint32
 }
 
 // One stable pass over digit (key >> shift) & (2^d - 1) of n keys (n = the rays of fill when
-// fill is given).  ghist: the pass's digit histogram over all keys; lookback: [tiles][2^d] words,
-// zero on entry; tile_ctr: zero on entry.  A look-back step loads the words of kLbWindow lower
-// tiles at once, so a walk over t tiles takes t / kLbWindow dependent loads.
+// fill is given), 2^d = the workgroup's 256 threads.  ghist: the pass's digit histogram over all
+// keys; lookback: lb_words(tiles) words, zero on entry (tile counts, then block counts, then
+// block counters); tile_ctr: zero on entry.
+//
+// Tile t (ids in start order) holds keys [t * kOsTile, ...), wave w of it the kOsItems x 64
+// consecutive keys from w * kOsItems * 64 on.  The pass: count the tile's digits and publish
+// the counts; the last tile of each block of kLbBlock tiles to publish adds up the block's
+// counts and publishes them; rank the keys stably (each wave ranks its own keys round by
+// round with per-wave digit counters, no barrier between rounds) and stage the tile in LDS
+// in digit order; add the counts of the lower blocks and of the lower tiles of its own block
+// (two rounds of loads instead of a walk over every lower tile); write the runs out.  Every
+// lower tile belongs to a workgroup that started earlier and publishes without waiting on
+// anything, so every wait below ends.
+constexpr int kLbBlock = 16;
+static_assert(kOsThreads == 256, "one digit per thread (8-bit digits)");
+
+__device__ __forceinline__ uint32_t lb_wait(const uint32_t* w) {
+    uint32_t v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while ((v & ~kLbCount) == 0) v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return v & kLbCount;
+}
+
+// sum of the published words w[i * stride], i < m (m <= kLbBlock), loads issued together
+__device__ __forceinline__ uint32_t lb_sum(const uint32_t* w, size_t stride, uint32_t m) {
+    uint32_t v[kLbBlock];
+#pragma unroll
+    for (int i = 0; i < kLbBlock; ++i)
+        v[i] = (uint32_t)i < m ? __hip_atomic_load(w + (size_t)i * stride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                               : kLbAgg;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kLbBlock; ++i) {
+        if ((v[i] & ~kLbCount) == 0) v[i] = kLbAgg | lb_wait(w + (size_t)i * stride);   // not published yet
+        sum += (uint32_t)i < m ? (v[i] & kLbCount) : 0u;
+    }
+    return sum;
+}
+
 template <int D>
 __global__ __launch_bounds__(kOsThreads) void k_onesweep(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                                                          uint32_t* vout, const uint32_t* fill, uint32_t n_plain,
                                                          int shift, const uint32_t* ghist, uint32_t* lookback,
                                                          uint32_t* tile_ctr) {
     constexpr uint32_t R = 1u << D;
-    constexpr int DPT = R >= (uint32_t)kOsThreads ? (int)(R / kOsThreads) : 1;   // digits per thread
-    __shared__ uint32_t s_cnt[R];      // the tile's digit counts, then the running count per digit
+    static_assert(R == (uint32_t)kOsThreads, "one digit per thread");
+    constexpr int W = kOsThreads / 64;
+    constexpr uint32_t WK = (uint32_t)kOsItems * 64u;   // keys per wave
+    __shared__ uint32_t s_cnt[R];      // the tile's digit counts
     __shared__ uint32_t s_gbase[R];    // destination of the tile's first key of each digit
     __shared__ uint32_t s_lbase[R];    // tile-local start of each digit
-    __shared__ uint32_t s_wcnt[kOsThreads / 64][R];
+    __shared__ uint32_t s_wcnt[W][R];  // per-wave running digit counts, then per-wave offsets
     __shared__ uint32_t s_k[kOsTile], s_v[kOsTile];   // the tile in digit order
     __shared__ uint32_t s_wsum[8];
-    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_tile, s_last;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
     const uint32_t n = fill_total(fill, n_plain);
+    const uint32_t tiles = gridDim.x;
+    const uint32_t nblk = (tiles + kLbBlock - 1) / kLbBlock;
+    uint32_t* const bagg = lookback + (size_t)tiles * R;   // [nblk][R] block counts
+    uint32_t* const bctr = bagg + (size_t)nblk * R;        // [nblk] tiles of the block published
     if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
-    for (uint32_t d = tid; d < R; d += kOsThreads) {
-        s_cnt[d] = 0;
-        for (int w = 0; w < kOsThreads / 64; ++w) s_wcnt[w][d] = 0;
-    }
+    s_cnt[tid] = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) s_wcnt[w][tid] = 0;
     __syncthreads();
     const uint32_t t = s_tile;
     const uint32_t first = t * kOsTile;
     if (first >= n) return;   // the whole workgroup: no tile left
     const uint32_t valid_n = n - first < kOsTile ? n - first : kOsTile;
+    const uint32_t wfirst = (uint32_t)wave * WK + (uint32_t)lane;
     uint32_t k[kOsItems], v[kOsItems];
 #pragma unroll
     for (int r = 0; r < kOsItems; ++r) {
-        const uint32_t j = (uint32_t)r * kOsThreads + (uint32_t)tid;
+        const uint32_t j = wfirst + (uint32_t)r * 64u;
         k[r] = j < valid_n ? kin[first + j] : 0u;
         v[r] = j < valid_n ? vin[first + j] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < kOsItems; ++r)
-        if ((uint32_t)r * kOsThreads + (uint32_t)tid < valid_n) atomicAdd(&s_cnt[(k[r] >> shift) & (R - 1u)], 1u);
+        if (wfirst + (uint32_t)r * 64u < valid_n) atomicAdd(&s_cnt[(k[r] >> shift) & (R - 1u)], 1u);
     __syncthreads();
-    // publish the tile's counts (tile 0: its inclusive prefix)
-    for (uint32_t d = tid; d < R; d += kOsThreads)
-        __hip_atomic_store(&lookback[(size_t)t * R + d], (t == 0 ? kLbInc : kLbAgg) | s_cnt[d], __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    // exclusive prefixes over the digits (contiguous digits per thread): of the global
-    // histogram and of the tile's counts
-    uint32_t gsum = 0, lsum = 0;
-#pragma unroll
-    for (int e = 0; e < DPT; ++e) {
-        const uint32_t d = (uint32_t)tid * DPT + e;
-        if (d < R) {
-            gsum += ghist[d];
-            lsum += s_cnt[d];
-        }
+    // publish the tile's counts; the block's last tile to do so publishes the block's counts
+    const uint32_t blk = t / kLbBlock, b0 = blk * kLbBlock;
+    const uint32_t bsize = tiles - b0 < (uint32_t)kLbBlock ? tiles - b0 : (uint32_t)kLbBlock;
+    __hip_atomic_store(&lookback[(size_t)t * R + tid], kLbAgg | s_cnt[tid], __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(&bctr[blk], 1u) == bsize - 1u ? 1u : 0u;
+    __syncthreads();
+    if (s_last) {
+        const uint32_t sum = lb_sum(lookback + (size_t)b0 * R + tid, R, bsize);
+        __hip_atomic_store(&bagg[(size_t)blk * R + tid], kLbInc | sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    uint32_t gpre = scan256(gsum, s_wsum, nullptr);
-    uint32_t lpre = scan256(lsum, s_wsum, nullptr);
-#pragma unroll
-    for (int e = 0; e < DPT; ++e) {
-        const uint32_t d = (uint32_t)tid * DPT + e;
-        if (d < R) {
-            s_gbase[d] = gpre;
-            s_lbase[d] = lpre;
-            gpre += ghist[d];
-            lpre += s_cnt[d];
-        }
-    }
-    __syncthreads();
-    // counts of each digit in the lower tiles: walk back to the nearest inclusive prefix, a
-    // window of lower tiles per step, every digit of the thread at once (digit tid + e * 256)
-    if (t > 0) {
-        uint32_t below[DPT];
-        int jt[DPT];
-        bool done[DPT];
-#pragma unroll
-        for (int e = 0; e < DPT; ++e) {
-            below[e] = 0;
-            jt[e] = (int)t - 1;
-            done[e] = !(tid + (uint32_t)e * kOsThreads < R);
-        }
-        for (;;) {
-            bool all = true;
-#pragma unroll
-            for (int e = 0; e < DPT; ++e) all = all && done[e];
-            if (all) break;
-            uint32_t wv[DPT][kLbWindow];
-#pragma unroll
-            for (int e = 0; e < DPT; ++e) {
-                const uint32_t d = tid + (uint32_t)e * kOsThreads;
-#pragma unroll
-                for (int i = 0; i < kLbWindow; ++i)
-                    wv[e][i] = (!done[e] && jt[e] >= i)
-                                   ? __hip_atomic_load(&lookback[(size_t)(jt[e] - i) * R + d], __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT)
-                                   : 0u;
-            }
-#pragma unroll
-            for (int e = 0; e < DPT; ++e) {
-                if (done[e]) continue;
-                int used = 0;
-#pragma unroll
-                for (int i = 0; i < kLbWindow; ++i) {
-                    if (done[e] || used < i) continue;   // stopped earlier in this window
-                    const uint32_t f = wv[e][i] & ~kLbCount;
-                    if (f == 0 || jt[e] < i) continue;    // not published yet: load it again next step
-                    below[e] += wv[e][i] & kLbCount;
-                    used = i + 1;
-                    if (f == kLbInc) done[e] = true;
-                }
-                if (!done[e]) jt[e] -= used;
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < DPT; ++e) {
-            const uint32_t d = tid + (uint32_t)e * kOsThreads;
-            if (d < R) {
-                __hip_atomic_store(&lookback[(size_t)t * R + d], kLbInc | (below[e] + s_cnt[d]), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                s_gbase[d] += below[e];
-            }
-        }
-    }
-    __syncthreads();
-    for (uint32_t d = tid; d < R; d += kOsThreads) s_cnt[d] = 0;
-    __syncthreads();
-    // stable ranking in index order (round, wave, lane), the tile staged in LDS in digit order
+    // exclusive prefixes over the digits: of the global histogram and of the tile's counts
+    const uint32_t gh = ghist[tid], lc = s_cnt[tid];
+    s_gbase[tid] = scan256(gh, s_wsum, nullptr);
+    s_lbase[tid] = scan256(lc, s_wsum, nullptr);
+    // stable ranking in index order (wave, round, lane): per-wave running counts, the
+    // lowest lane of each digit in a round adding the round's keys of that digit
+    uint32_t rk[kOsItems];
 #pragma unroll
     for (int r = 0; r < kOsItems; ++r) {
-        const uint32_t j = (uint32_t)r * kOsThreads + (uint32_t)tid;
-        const bool ok = j < valid_n;
+        const bool ok = wfirst + (uint32_t)r * 64u < valid_n;
         const uint32_t dg = (k[r] >> shift) & (R - 1u);
         unsigned long long same = __ballot(ok);
 #pragma unroll
@@ -1842,22 +1814,38 @@ __global__ __launch_bounds__(kOsThreads) void k_onesweep(const uint32_t* kin, co
             same &= ((dg >> bit) & 1u) ? bb : ~bb;
         }
         const uint32_t rank = (uint32_t)__popcll(same & lt);
-        const bool leader = ok && rank == 0;
-        if (leader) s_wcnt[wave][dg] = (uint32_t)__popcll(same);
-        __syncthreads();
-        if (ok) {
-            uint32_t before = s_cnt[dg];
-            for (int w = 0; w < wave; ++w) before += s_wcnt[w][dg];
-            const uint32_t lpos = s_lbase[dg] + before + rank;
+        const uint32_t before = ok ? s_wcnt[wave][dg] : 0u;
+        rk[r] = before + rank;
+        if (ok && rank == 0) s_wcnt[wave][dg] = before + (uint32_t)__popcll(same);
+    }
+    __syncthreads();
+    {   // per-wave counts -> offsets of each wave's keys of digit tid within the tile's digit run
+        uint32_t acc = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint32_t c = s_wcnt[w][tid];
+            s_wcnt[w][tid] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kOsItems; ++r) {
+        if (wfirst + (uint32_t)r * 64u < valid_n) {
+            const uint32_t dg = (k[r] >> shift) & (R - 1u);
+            const uint32_t lpos = s_lbase[dg] + s_wcnt[wave][dg] + rk[r];
             s_k[lpos] = k[r];
             s_v[lpos] = v[r];
         }
-        __syncthreads();
-        if (leader) {
-            atomicAdd(&s_cnt[dg], (uint32_t)__popcll(same));
-            s_wcnt[wave][dg] = 0;
-        }
     }
+    // keys of digit tid in the lower tiles: the lower blocks, then the block's lower tiles
+    uint32_t below = 0;
+    for (uint32_t bb = 0; bb < blk; bb += kLbBlock) {
+        const uint32_t m = blk - bb < (uint32_t)kLbBlock ? blk - bb : (uint32_t)kLbBlock;
+        below += lb_sum(bagg + (size_t)bb * R + tid, R, m);
+    }
+    below += lb_sum(lookback + (size_t)b0 * R + tid, R, t - b0);
+    s_gbase[tid] += below;
     __syncthreads();
     // runs of equal digits go to consecutive places, written by consecutive threads
     for (uint32_t i = tid; i < valid_n; i += kOsThreads) {
@@ -2055,6 +2043,11 @@ constexpr int kPlainDigit = 8;                 // 32-bit keys: 4 passes of 8-bit
 constexpr int kPlainPasses = 4;
 
 static uint32_t sort_tiles(uint32_t n) { return (n + kOsTile - 1) / kOsTile; }
+// look-back words of one pass over this many tiles: tile counts, block counts, block counters
+static size_t lb_words(uint32_t tiles) {
+    const size_t nb = (tiles + kLbBlock - 1) / kLbBlock;
+    return ((size_t)tiles + nb) * kOsThreads + nb;
+}
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // render workspace: keys, vals, their alternates (n each), the histograms and tile counters
@@ -2062,7 +2055,7 @@ static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 size_t sort_compacted_workspace_bytes(uint32_t n) {
     const size_t R = (size_t)1 << kRenderDigit;
     return 4 * al256((size_t)n * 4) + al256((kRenderPasses * R + kRenderPasses) * 4) +
-           al256((size_t)kRenderPasses * sort_tiles(n) * R * 4);
+           al256((size_t)kRenderPasses * lb_words(sort_tiles(n)) * 4);
 }
 
 struct SortWs {
@@ -2097,7 +2090,7 @@ hipError_t launch_keys_compacted(const DevScene& sc, const float4* q, const uint
     const uint32_t kb = (nslots + kKeysPerThread * 1024 - 1) / (kKeysPerThread * 1024);
     hipLaunchKernelGGL(k_keys_compacted<kRenderDigit>, dim3(kb), dim3(1024), 0, st, sc, q, fill,
                        region, w.keys, w.vals, kind, kRenderPasses, w.hist, w.lookback,
-                       (uint32_t)((size_t)kRenderPasses * sort_tiles(nslots) * R));
+                       (uint32_t)((size_t)kRenderPasses * lb_words(sort_tiles(nslots))));
     return hipGetLastError();
 }
 
@@ -2109,7 +2102,7 @@ hipError_t launch_sort_compacted(const uint32_t* fill, uint32_t nslots, void* ws
     uint32_t *kin = w.keys, *vin = w.vals, *kout = w.kalt, *vout = w.valt;
     for (int ps = 0; ps < kRenderPasses; ++ps) {
         hipLaunchKernelGGL(k_onesweep<kRenderDigit>, dim3(tiles), dim3(kOsThreads), 0, st, kin, vin, kout, vout, fill,
-                           0u, kRenderDigit * ps, w.hist + (size_t)ps * R, w.lookback + (size_t)ps * tiles * R,
+                           0u, kRenderDigit * ps, w.hist + (size_t)ps * R, w.lookback + (size_t)ps * lb_words(tiles),
                            w.ctr + ps);
         uint32_t* tk = kin;
         kin = kout;
@@ -2125,7 +2118,7 @@ hipError_t launch_sort_compacted(const uint32_t* fill, uint32_t nslots, void* ws
 size_t sort_workspace_bytes(uint32_t n) {
     const size_t R = (size_t)1 << kPlainDigit;
     return 2 * al256((size_t)n * 4) + al256((kPlainPasses * R + kPlainPasses) * 4) +
-           al256((size_t)kPlainPasses * sort_tiles(n) * R * 4);
+           al256((size_t)kPlainPasses * lb_words(sort_tiles(n)) * 4);
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t n, void* ws, hipStream_t st) {
@@ -2148,7 +2141,7 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t n, void* ws
     for (int ps = 0; ps < kPlainPasses; ++ps) {
         hipLaunchKernelGGL(k_onesweep<kPlainDigit>, dim3(tiles), dim3(kOsThreads), 0, st, kin, vin, kout, vout,
                            (const uint32_t*)nullptr, n, kPlainDigit * ps, hist + (size_t)ps * R,
-                           lookback + (size_t)ps * tiles * R, ctr + ps);
+                           lookback + (size_t)ps * lb_words(tiles), ctr + ps);
         uint32_t* tk = kin;
         kin = kout;
         kout = tk;
