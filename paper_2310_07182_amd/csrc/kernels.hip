@@ -1598,6 +1598,7 @@ __global__ __launch_bounds__(256) void k_keys(DevScene sc, const float4* q, uint
 // The global start of each digit comes from histograms of all passes taken before the first
 // pass.
 constexpr int kOsThreads = 256;
+constexpr uint32_t kHistCopies = 8;   // copies of the digit histograms (workgroup mod 8)
 constexpr int kOsItems = 16;
 constexpr uint32_t kOsTile = (uint32_t)kOsThreads * kOsItems;
 constexpr uint32_t kLbAgg = 1u << 30, kLbInc = 2u << 30, kLbCount = (1u << 30) - 1u;
@@ -1635,7 +1636,8 @@ __device__ __forceinline__ uint32_t fill_total(const uint32_t* fill, uint32_t n)
 
 // Keys of the live rays of a compacted queue (sorted modes): ray i (i < the launch's rays, in
 // region order) gets its key and its queue slot; the digit histograms of all `passes` passes
-// of d bits each are added to hist[pass][2^d].  Also clears the look-back words of the passes.
+// of d bits each are added to hist[copy][pass][2^d], copy = workgroup mod kHistCopies (one
+// copy per XCD: fewer device-wide atomics on each word; a pass adds the copies up).  Also clears the look-back words of the passes.
 // 1024 threads x kKeysPerThread rays per workgroup, the rays' loads issued together.
 constexpr int kKeysPerThread = 8;
 template <int D>
@@ -1681,11 +1683,13 @@ __global__ __launch_bounds__(1024) void k_keys_compacted(DevScene sc, const floa
         }
     }
     __syncthreads();
+    uint32_t* const hc = hist + (blockIdx.x % kHistCopies) * (uint32_t)passes * R;
     for (uint32_t d = threadIdx.x; d < (uint32_t)passes * R; d += 1024)
-        if (h[d]) atomicAdd(&hist[d], h[d]);
+        if (h[d]) atomicAdd(&hc[d], h[d]);
 }
 
-// digit histograms of all passes of d-bit digits over n keys (a plain sort)
+// digit histograms of all passes of d-bit digits over n keys (a plain sort), in kHistCopies
+// copies as above
 template <int D>
 __global__ __launch_bounds__(256) void k_digit_hist(const uint32_t* keys, uint32_t n, int passes, uint32_t* hist) {
     constexpr uint32_t R = 1u << D;
@@ -1697,14 +1701,15 @@ __global__ __launch_bounds__(256) void k_digit_hist(const uint32_t* keys, uint32
         for (int ps = 0; ps < passes; ++ps) atomicAdd(&h[ps * R + ((key >> (D * ps)) & (R - 1u))], 1u);
     }
     __syncthreads();
+    uint32_t* const hc = hist + (blockIdx.x % kHistCopies) * (uint32_t)passes * R;
     for (uint32_t d = threadIdx.x; d < (uint32_t)passes * R; d += 256)
-        if (h[d]) atomicAdd(&hist[d], h[d]);
+        if (h[d]) atomicAdd(&hc[d], h[d]);
 }
 
 // One stable pass over digit (key >> shift) & (2^d - 1) of n keys (n = the rays of fill when
-// fill is given), 2^d = the workgroup's 256 threads.  ghist: the pass's digit histogram over all
-// keys; lookback: lb_words(tiles) words, zero on entry (tile counts, then block counts, then
-// block counters); tile_ctr: zero on entry.
+// fill is given), 2^d = the workgroup's 256 threads.  ghist: the pass's digit histogram over
+// all keys, in kHistCopies copies gstride words apart; lookback: lb_words(tiles) words, zero
+// on entry (tile counts, then block counts, then block counters); tile_ctr: zero on entry.
 //
 // Tile t (ids in start order) holds keys [t * kOsTile, ...), wave w of it the kOsItems x 64
 // consecutive keys from w * kOsItems * 64 on.  The pass: count the tile's digits and publish
@@ -1743,8 +1748,8 @@ __device__ __forceinline__ uint32_t lb_sum(const uint32_t* w, size_t stride, uin
 template <int D>
 __global__ __launch_bounds__(kOsThreads) void k_onesweep(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                                                          uint32_t* vout, const uint32_t* fill, uint32_t n_plain,
-                                                         int shift, const uint32_t* ghist, uint32_t* lookback,
-                                                         uint32_t* tile_ctr) {
+                                                         int shift, const uint32_t* ghist, uint32_t gstride,
+                                                         uint32_t* lookback, uint32_t* tile_ctr) {
     constexpr uint32_t R = 1u << D;
     static_assert(R == (uint32_t)kOsThreads, "one digit per thread");
     constexpr int W = kOsThreads / 64;
@@ -1797,7 +1802,10 @@ __global__ __launch_bounds__(kOsThreads) void k_onesweep(const uint32_t* kin, co
         __hip_atomic_store(&bagg[(size_t)blk * R + tid], kLbInc | sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     // exclusive prefixes over the digits: of the global histogram and of the tile's counts
-    const uint32_t gh = ghist[tid], lc = s_cnt[tid];
+    uint32_t gh = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < kHistCopies; ++c) gh += ghist[c * gstride + tid];
+    const uint32_t lc = s_cnt[tid];
     s_gbase[tid] = scan256(gh, s_wsum, nullptr);
     s_lbase[tid] = scan256(lc, s_wsum, nullptr);
     // stable ranking in index order (wave, round, lane): per-wave running counts, the
@@ -2054,7 +2062,7 @@ static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 // (zeroed per bounce), the look-back words of every pass
 size_t sort_compacted_workspace_bytes(uint32_t n) {
     const size_t R = (size_t)1 << kRenderDigit;
-    return 4 * al256((size_t)n * 4) + al256((kRenderPasses * R + kRenderPasses) * 4) +
+    return 4 * al256((size_t)n * 4) + al256((kHistCopies * kRenderPasses * R + kRenderPasses) * 4) +
            al256((size_t)kRenderPasses * lb_words(sort_tiles(n)) * 4);
 }
 
@@ -2075,8 +2083,8 @@ static SortWs sort_ws(void* ws, uint32_t n) {
     w.valt = (uint32_t*)p;
     p += al256((size_t)n * 4);
     w.hist = (uint32_t*)p;
-    w.ctr = w.hist + kRenderPasses * R;
-    p += al256((kRenderPasses * R + kRenderPasses) * 4);
+    w.ctr = w.hist + kHistCopies * kRenderPasses * R;
+    p += al256((kHistCopies * kRenderPasses * R + kRenderPasses) * 4);
     w.lookback = (uint32_t*)p;
     return w;
 }
@@ -2085,7 +2093,7 @@ hipError_t launch_keys_compacted(const DevScene& sc, const float4* q, const uint
                                  uint32_t nslots, int kind, void* ws, hipStream_t st) {
     const uint32_t R = 1u << kRenderDigit;
     const SortWs w = sort_ws(ws, nslots);
-    hipError_t e = launch_zero(w.hist, (size_t)kRenderPasses * R + kRenderPasses, st);
+    hipError_t e = launch_zero(w.hist, (size_t)kHistCopies * kRenderPasses * R + kRenderPasses, st);
     if (e != hipSuccess) return e;
     const uint32_t kb = (nslots + kKeysPerThread * 1024 - 1) / (kKeysPerThread * 1024);
     hipLaunchKernelGGL(k_keys_compacted<kRenderDigit>, dim3(kb), dim3(1024), 0, st, sc, q, fill,
@@ -2102,8 +2110,8 @@ hipError_t launch_sort_compacted(const uint32_t* fill, uint32_t nslots, void* ws
     uint32_t *kin = w.keys, *vin = w.vals, *kout = w.kalt, *vout = w.valt;
     for (int ps = 0; ps < kRenderPasses; ++ps) {
         hipLaunchKernelGGL(k_onesweep<kRenderDigit>, dim3(tiles), dim3(kOsThreads), 0, st, kin, vin, kout, vout, fill,
-                           0u, kRenderDigit * ps, w.hist + (size_t)ps * R, w.lookback + (size_t)ps * lb_words(tiles),
-                           w.ctr + ps);
+                           0u, kRenderDigit * ps, w.hist + (size_t)ps * R, (uint32_t)(kRenderPasses * R),
+                           w.lookback + (size_t)ps * lb_words(tiles), w.ctr + ps);
         uint32_t* tk = kin;
         kin = kout;
         kout = tk;
@@ -2117,7 +2125,7 @@ hipError_t launch_sort_compacted(const uint32_t* fill, uint32_t nslots, void* ws
 
 size_t sort_workspace_bytes(uint32_t n) {
     const size_t R = (size_t)1 << kPlainDigit;
-    return 2 * al256((size_t)n * 4) + al256((kPlainPasses * R + kPlainPasses) * 4) +
+    return 2 * al256((size_t)n * 4) + al256((kHistCopies * kPlainPasses * R + kPlainPasses) * 4) +
            al256((size_t)kPlainPasses * lb_words(sort_tiles(n)) * 4);
 }
 
@@ -2131,17 +2139,17 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t n, void* ws
     uint32_t* valt = (uint32_t*)p;
     p += al256((size_t)n * 4);
     uint32_t* hist = (uint32_t*)p;
-    uint32_t* ctr = hist + kPlainPasses * R;
+    uint32_t* ctr = hist + kHistCopies * kPlainPasses * R;
     hipError_t e = launch_zero(hist, sort_workspace_bytes(n) / 4 - 2 * al256((size_t)n * 4) / 4, st);
     if (e != hipSuccess) return e;
-    uint32_t* lookback = (uint32_t*)(p + al256((kPlainPasses * R + kPlainPasses) * 4));
+    uint32_t* lookback = (uint32_t*)(p + al256((kHistCopies * kPlainPasses * R + kPlainPasses) * 4));
     const uint32_t hblocks = (n + 255) / 256 < 128u ? (n + 255) / 256 : 128u;
     hipLaunchKernelGGL(k_digit_hist<kPlainDigit>, dim3(hblocks), dim3(256), 0, st, keys, n, kPlainPasses, hist);
     uint32_t *kin = keys, *vin = vals, *kout = kalt, *vout = valt;
     for (int ps = 0; ps < kPlainPasses; ++ps) {
         hipLaunchKernelGGL(k_onesweep<kPlainDigit>, dim3(tiles), dim3(kOsThreads), 0, st, kin, vin, kout, vout,
                            (const uint32_t*)nullptr, n, kPlainDigit * ps, hist + (size_t)ps * R,
-                           lookback + (size_t)ps * lb_words(tiles), ctr + ps);
+                           (uint32_t)(kPlainPasses * R), lookback + (size_t)ps * lb_words(tiles), ctr + ps);
         uint32_t* tk = kin;
         kin = kout;
         kout = tk;
