@@ -779,7 +779,8 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
         constexpr bool DRAIN = decltype(drain_tag)::value;
         // ---- refill idle lanes with the next rays of the queue
         const unsigned long long idle = __ballot(!have);
-        if (!DRAIN && idle != 0 && (__popcll(idle) >= a.refill || idle == ~0ull)) {
+        // (merged launches run only this instantiation: no claims once the counters are used up)
+        if (!DRAIN && !exhausted && idle != 0 && (__popcll(idle) >= a.refill || idle == ~0ull)) {
             // a launch with few rays spreads them over every wave (latency hiding) instead of
             // filling the first waves' 64 lanes and leaving the others without work
             const uint32_t share = n / gridDim.x + 1u;
