@@ -575,6 +575,43 @@ def bench_quality(api, sc, cfg, args):
     return out
 
 
+def bench_quality_short(api, sc, cfg, ref_frames=1024, frames=128, long_frames=1024):
+    """A short form of the quality study for the default run (indoor, 1 spp per frame, a new
+    seed per frame): PSNR after `frames` frames against an incoherent reference of
+    `ref_frames` frames, for incoherent tracing and reuse in 8x8 tiles with K = 8, 32, 64
+    (Table 2 and Table 3 protocols), and the tile variance ratio of the error (structured,
+    tile-periodic noise; Sec. 5.3's K = 32 case) after `frames` and `long_frames` frames."""
+    import torch
+    w, h, B = cfg["w"], cfg["h"], cfg["bounces"]
+
+    def average(mode, tile, k, n, seed0):
+        r = api.Renderer(sc, api.RenderConfig(w, h, 1, B, mode, tile, k))
+        acc = torch.zeros((h, w, 3), dtype=torch.float64, device="cuda:0")
+        for i in range(n):
+            r.render(seed0 + i)
+            acc += r.radiance.double()
+        torch.cuda.synchronize()
+        return acc / n
+
+    t0 = time.perf_counter()
+    ref_np = _ldr(average("incoherent", (8, 8), 8, ref_frames, 7_000_000)).cpu().numpy()
+    rows = []
+    for mode, k in (("incoherent", 8), ("reuse", 8), ("reuse", 32), ("reuse", 64)):
+        row = {"mode": mode, "tile": [8, 8], "k": k}
+        for n in (frames, long_frames):
+            img = _ldr(average(mode, (8, 8), k, n, 1)).cpu().numpy()
+            row[f"psnr_db_{n}"] = round(psnr_db(img, ref_np), 3)
+            row[f"tile_variance_ratio_{n}"] = round(tile_variance_ratio(img - ref_np, (8, 8)), 3)
+        rows.append(row)
+        log(f"[quality] {row}")
+    return {"workload": f"indoor {w}x{h}, 1 spp per frame, {B} bounces, a new seed per frame; reference: "
+                        f"{ref_frames} incoherent frames (other seeds); display: clamp to [0,1], gamma 1/2.2",
+            "tile_variance_ratio": "variance of the error averaged over each 8x8 tile, times 64, over the "
+                                   "variance of the per-pixel error: 1 for independent pixel errors, up to K "
+                                   "for errors shared by the K pixels of a group",
+            "rows": rows, "seconds": round(time.perf_counter() - t0, 1)}
+
+
 def _csv_rows(path):
     import csv
     with open(path, newline="") as f:
@@ -1145,6 +1182,10 @@ def bench_frames(api, scenes, args, torch):
     for name, points in plan:
         res, info = bench_config(api, scenes, name, points, args, torch)
         out[name] = (res, info)
+    quality = None
+    if args.config == "all" and not args.no_deploy:
+        log("[bench] short quality study")
+        quality = bench_quality_short(api, out[plan[0][0]][1]["sc"], out[plan[0][0]][1]["cfg"])
     deploy = None
     if args.config == "all" and not args.no_deploy:
         deploy = bench_deploy(api, scenes, args, {n: info["sc"] for n, (res, info) in out.items()})
@@ -1218,6 +1259,8 @@ def bench_frames(api, scenes, args, torch):
                       "p99_frame_ms": round(h["frame_ms_p99"], 4),
                       "modes": {lab: _mode_summary(v, args.nee) for lab, v in res.items()},
                       "roofline": roofline(h, info["sc_info"], args.traversal, ceil, name, info["level"])}
+    if quality is not None:
+        line["quality"] = quality
     if deploy is not None:
         line["deployment"] = deploy
     if yard is not None:
