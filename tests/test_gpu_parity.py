@@ -372,6 +372,35 @@ def test_radix_sort_stable(api, torch_dev, n):
     assert np.array_equal(k.cpu().numpy().view(np.uint32), keys[order])
 
 
+@pytest.mark.parametrize("n", [17, 100003, 2100000])
+def test_radix_sort_matches_vendor_sort(api, torch_dev, n):
+    """pt_sort_pairs against the vendor library's device radix sort (libptsortref, the
+    benchmark's yardstick) on the same 30-bit keys: both stable, so keys and values agree."""
+    import ctypes as C
+    from paper_2310_07182_amd import build as B
+    L = C.CDLL(B.SORTREF_LIB)
+    L.ptref_sort_workspace_bytes.argtypes = [C.c_uint32, C.c_int, C.POINTER(C.c_size_t)]
+    L.ptref_sort_pairs.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_uint32, C.c_int, C.c_void_p]
+    _say(f"[gpu] sort vs vendor sort n={n}")
+    rng = np.random.default_rng(n + 5)
+    keys = rng.integers(0, 1 << 30, n, dtype=np.int64).astype(np.int32)
+    keys[: n // 3] &= 0xFFF                          # many duplicates
+    k0 = torch_dev.from_numpy(keys).cuda()
+    v0 = torch_dev.arange(n, dtype=torch_dev.int32, device="cuda")
+    kr, vr = torch_dev.empty_like(k0), torch_dev.empty_like(v0)
+    need = C.c_size_t(0)
+    assert L.ptref_sort_workspace_bytes(n, 30, C.byref(need)) == 0
+    ws = torch_dev.empty(max(int(need.value), 256), dtype=torch_dev.uint8, device="cuda")
+    st = torch_dev.cuda.current_stream()
+    assert L.ptref_sort_pairs(ws.data_ptr(), ws.numel(), k0.data_ptr(), kr.data_ptr(), v0.data_ptr(), vr.data_ptr(),
+                              n, 30, st.cuda_stream) == 0
+    k1, v1 = k0.clone(), v0.clone()
+    api.sort_pairs(k1, v1)
+    torch_dev.cuda.synchronize()
+    assert torch_dev.equal(k1, kr) and torch_dev.equal(v1, vr)
+
+
 def test_workspace_too_small_is_enomem(api, torch_dev):
     from paper_2310_07182_amd import capi
     import ctypes as C
