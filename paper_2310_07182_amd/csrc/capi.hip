@@ -221,7 +221,7 @@ Layout layout(const Frame& f) {
     o = align256(o + launches * pt::kMaxTraceBlocks * 4);
     if (is_sorted_mode(f.mode)) {
         L.sortws = o;
-        o = align256(o + pt::sort_compacted_workspace_bytes(f.nslots));
+        o = align256(o + pt::sort_compacted_workspace_bytes(f.nslots, 8 * f.region));
     }
     if (f.nee) {
         L.shray = o;
@@ -578,8 +578,7 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
             if (is_sorted_mode(mode) && b >= 1) {
                 {
                     TimerScope ts(out->timer, st, 3, b);
-                    e = pt::launch_keys_compacted(scene->dev, q[b & 1], fill, f.region, f.nslots, (int)mode,
-                                                  ws + L.sortws, st);
+                    e = pt::launch_keys_compacted(fill, f.region, f.nslots, ws + L.sortws, st);
                 }
                 if (e != hipSuccess) return hip_fail(e, "launch (keys)");
                 {
@@ -621,8 +620,11 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
                 TimerScope ts(out->timer, st, 2, b);
                 // the next rays go compacted into the regions counted by the next launch's fill words
                 uint32_t* fill_next = b < B ? work + ((size_t)(b + 1) * spp + s) * pt::kWorkWords + pt::kFillWord : nullptr;
+                // sorted modes: the shade kernel writes each next ray's key beside it
+                uint32_t* keys_next = is_sorted_mode(mode) && b < B ? pt::sort_key_slots(ws + L.sortws, f.nslots) : nullptr;
                 e = pt::launch_shade(scene->dev, f, b, s, q[b & 1], q[(b + 1) & 1], state, out->hit_prim, out->hit_t,
-                                     out->radiance, (float4*)out->rays, shray, shc, fill_next, (float4*)out->debug, st);
+                                     out->radiance, (float4*)out->rays, shray, shc, fill_next, keys_next,
+                                     (float4*)out->debug, st);
             }
             if (e != hipSuccess) return hip_fail(e, "launch (shade)");
             if (f.nee && b < B) {

@@ -140,10 +140,13 @@ hipError_t launch_raygen(const Frame& f, int s, float4* q, float4* state, float4
 // fill: null = the next rays at their slots (dead slots hold kNoRay records); else the live
 // rays compacted into 8 regions of f.region slots, region r's count in fill[r * kCounterStride]
 // (zero before the launch), dead rays not written
+// keys_out: null, or (sorted modes, with fill) the reordering key of each next ray, written at
+// the ray's queue slot (sort_key_slots)
 // debug: null, or pt_outputs.debug (the record of hit b of every pixel with a path, b < B)
 hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const float4* q_in, float4* q_out,
                         float4* state, int32_t* hit_prim, float* hit_t, float* radiance, float4* rays_out,
-                        float4* shadow_rays, float4* shadow_light, uint32_t* fill, float4* debug, hipStream_t st);
+                        float4* shadow_rays, float4* shadow_light, uint32_t* fill, uint32_t* keys_out, float4* debug,
+                        hipStream_t st);
 
 // flags of the per-ray record (the w word of pt_outputs.debug)
 constexpr uint32_t kDbgActive = 1u << 0, kDbgRep = 1u << 5, kDbgReused = 1u << 6, kDbgValid = 1u << 7;
@@ -157,13 +160,15 @@ hipError_t launch_keys(const DevScene& sc, const float4* q, uint32_t n, uint32_t
 // ray_count[i] = sum of partial[i * stride + j] for j < parts, i < launches
 hipError_t launch_count_finalize(const uint32_t* partial, int stride, int parts, int launches, uint32_t* ray_count,
                                  hipStream_t st);
-// sorted modes over a compacted queue (launch_shade's regions, counts in fill): the 30-bit keys of
-// the live rays with their queue slots and the digit histograms (launch_keys_compacted), then a
-// stable radix sort in 4 passes of 8-bit digits (launch_sort_compacted), whose *perm gives the
-// queue slots in key order for the traversal (TraceArgs.perm); ws: sort_compacted_workspace_bytes
-size_t sort_compacted_workspace_bytes(uint32_t nslots);
-hipError_t launch_keys_compacted(const DevScene& sc, const float4* q, const uint32_t* fill, uint32_t region,
-                                 uint32_t nslots, int kind, void* ws, hipStream_t st);
+// sorted modes over a compacted queue (launch_shade's regions, counts in fill): the 30-bit keys
+// that the shade kernel wrote at the live rays' queue slots (sort_key_slots: qslots = 8 x region
+// words) gathered in region order with their slots, and the digit histograms
+// (launch_keys_compacted), then a stable radix sort in 4 passes of 8-bit digits
+// (launch_sort_compacted), whose *perm gives the queue slots in key order for the traversal
+// (TraceArgs.perm); ws: sort_compacted_workspace_bytes
+size_t sort_compacted_workspace_bytes(uint32_t nslots, uint32_t qslots);
+uint32_t* sort_key_slots(void* ws, uint32_t nslots);
+hipError_t launch_keys_compacted(const uint32_t* fill, uint32_t region, uint32_t nslots, void* ws, hipStream_t st);
 hipError_t launch_sort_compacted(const uint32_t* fill, uint32_t nslots, void* ws, const uint32_t** perm,
                                  hipStream_t st);
 

@@ -1206,13 +1206,74 @@ __global__ __launch_bounds__(1024) void k_raygen_multi(const StepJob* jobs, int 
     raygen_body(J.f, J.s, blockIdx.x - J.block_start, J.q_out_raygen, J.state, nullptr);
 }
 
+// ------------------------------------------------------------------ reordering keys (sorted modes)
+// nb-bit quantization of x over [lo, lo + ext]: floor(((x - lo) / ext) * 2^nb), clamped
+__device__ __forceinline__ uint32_t qbits(float x, float lo, float ext, int nb) {
+    if (!(ext > 0.0f)) return 0u;
+    const float top = (float)(1u << nb);
+    const float f = ((x - lo) / ext) * top;
+    if (!(f > 0.0f)) return 0u;
+    if (f >= top - 1.0f) return (1u << nb) - 1u;
+    return (uint32_t)f;
+}
+
+// 30-bit reordering key of a live ray for a sorted mode (bits interleaved most significant first)
+__device__ __forceinline__ uint32_t ray_key(const DevScene& sc, float4 r0, float4 r1, int kind) {
+    const float ex = sc.hi[0] - sc.lo[0], ey = sc.hi[1] - sc.lo[1], ez = sc.hi[2] - sc.lo[2];
+    uint32_t key = 0;
+    if (kind == PT_MODE_SORTED_ORIGIN) {
+        const uint32_t qc[3] = {qbits(r0.x, sc.lo[0], ex, 10), qbits(r0.y, sc.lo[1], ey, 10),
+                                qbits(r0.z, sc.lo[2], ez, 10)};
+#pragma unroll
+        for (int bit = 9; bit >= 0; --bit)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) key = (key << 1) | ((qc[c] >> bit) & 1u);
+    } else if (kind == PT_MODE_SORTED_REIS) {
+        const uint32_t qo[3] = {qbits(r0.x, sc.lo[0], ex, 6), qbits(r0.y, sc.lo[1], ey, 6),
+                                qbits(r0.z, sc.lo[2], ez, 6)};
+        const uint32_t qd[3] = {qbits(r1.x, -1.0f, 2.0f, 4), qbits(r1.y, -1.0f, 2.0f, 4),
+                                qbits(r1.z, -1.0f, 2.0f, 4)};
+#pragma unroll
+        for (int bit = 5; bit >= 0; --bit)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) key = (key << 1) | ((qo[c] >> bit) & 1u);
+#pragma unroll
+        for (int bit = 3; bit >= 0; --bit)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) key = (key << 1) | ((qd[c] >> bit) & 1u);
+    } else {
+        uint32_t qc[6];
+        if (kind == PT_MODE_SORTED_AILA) {
+            qc[3] = qbits(r1.x, -1.0f, 2.0f, 5);
+            qc[4] = qbits(r1.y, -1.0f, 2.0f, 5);
+            qc[5] = qbits(r1.z, -1.0f, 2.0f, 5);
+        } else {   // TwoPoint: the point at a fixed length of 0.25 x the largest extent
+            float mx = ex;
+            if (ey > mx) mx = ey;
+            if (ez > mx) mx = ez;
+            const float len = 0.25f * mx;
+            qc[3] = qbits(r0.x + len * r1.x, sc.lo[0], ex, 5);
+            qc[4] = qbits(r0.y + len * r1.y, sc.lo[1], ey, 5);
+            qc[5] = qbits(r0.z + len * r1.z, sc.lo[2], ez, 5);
+        }
+        qc[0] = qbits(r0.x, sc.lo[0], ex, 5);
+        qc[1] = qbits(r0.y, sc.lo[1], ey, 5);
+        qc[2] = qbits(r0.z, sc.lo[2], ez, 5);
+#pragma unroll
+        for (int bit = 4; bit >= 0; --bit)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) key = (key << 1) | ((qc[c] >> bit) & 1u);
+    }
+    return key;
+}
+
 // ------------------------------------------------------------------ shade + next direction
 // One workgroup = one super tile (whole reuse tiles), one thread per slot.
 __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, int b, int s, uint32_t blk,
                                            const float4* __restrict__ q_in, float4* __restrict__ q_out,
                                            float4* state, int32_t* hit_prim, float* hit_t, float* radiance,
                                            float4* rays_out, float4* shadow_rays, float4* shadow_light, float* lds,
-                                           uint32_t* fill, float4* debug) {
+                                           uint32_t* fill, uint32_t* keys_out, float4* debug) {
     // group exchange in LDS, TS entries each: own tangent exit, tree sums, info bits, min active slot
     const int TS = f.TS;
     float* sq0 = lds;
@@ -1463,6 +1524,8 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
         if (!fill || (active && use_ok)) {   // a compacted queue holds live rays only
             q_out[2 * (size_t)newpos] = o0;
             q_out[2 * (size_t)newpos + 1] = o1;
+            // sorted modes: the ray's reordering key beside it (read by the sort, not the ray)
+            if (keys_out && fill && active && use_ok) keys_out[newpos] = ray_key(sc, o0, o1, f.mode);
         }
     }
     if (died) {
@@ -1488,10 +1551,10 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
 __global__ __launch_bounds__(1024) void k_shade(DevScene sc, Frame f, int b, int s, const float4* __restrict__ q_in,
                                                 float4* __restrict__ q_out, float4* state, int32_t* hit_prim,
                                                 float* hit_t, float* radiance, float4* rays_out, float4* shadow_rays,
-                                                float4* shadow_light, uint32_t* fill, float4* debug) {
+                                                float4* shadow_light, uint32_t* fill, uint32_t* keys_out, float4* debug) {
     extern __shared__ float lds[];
     shade_body(sc, f, b, s, blockIdx.x, q_in, q_out, state, hit_prim, hit_t, radiance, rays_out, shadow_rays,
-               shadow_light, lds, fill, debug);
+               shadow_light, lds, fill, keys_out, debug);
 }
 
 // adds the light of unblocked shadow rays to their paths (one thread per path slot)
@@ -1513,70 +1576,10 @@ __global__ __launch_bounds__(1024) void k_shade_multi(const StepJob* jobs, int n
     const int j = job_of_block(jobs, njobs, blockIdx.x);
     const StepJob& J = jobs[j];
     shade_body(J.sc, J.f, J.b, J.s, blockIdx.x - J.block_start, J.q_in, J.q_out, J.state, J.hit_prim, J.hit_t,
-               J.radiance, nullptr, nullptr, nullptr, lds, nullptr, nullptr);
+               J.radiance, nullptr, nullptr, nullptr, lds, nullptr, nullptr, nullptr);
 }
 
-// ------------------------------------------------------------------ two-point key, gather
-// nb-bit quantization of x over [lo, lo + ext]: floor(((x - lo) / ext) * 2^nb), clamped
-__device__ __forceinline__ uint32_t qbits(float x, float lo, float ext, int nb) {
-    if (!(ext > 0.0f)) return 0u;
-    const float top = (float)(1u << nb);
-    const float f = ((x - lo) / ext) * top;
-    if (!(f > 0.0f)) return 0u;
-    if (f >= top - 1.0f) return (1u << nb) - 1u;
-    return (uint32_t)f;
-}
-
-// 30-bit reordering key of a live ray for a sorted mode (bits interleaved most significant first)
-__device__ __forceinline__ uint32_t ray_key(const DevScene& sc, float4 r0, float4 r1, int kind) {
-    const float ex = sc.hi[0] - sc.lo[0], ey = sc.hi[1] - sc.lo[1], ez = sc.hi[2] - sc.lo[2];
-    uint32_t key = 0;
-    if (kind == PT_MODE_SORTED_ORIGIN) {
-        const uint32_t qc[3] = {qbits(r0.x, sc.lo[0], ex, 10), qbits(r0.y, sc.lo[1], ey, 10),
-                                qbits(r0.z, sc.lo[2], ez, 10)};
-#pragma unroll
-        for (int bit = 9; bit >= 0; --bit)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) key = (key << 1) | ((qc[c] >> bit) & 1u);
-    } else if (kind == PT_MODE_SORTED_REIS) {
-        const uint32_t qo[3] = {qbits(r0.x, sc.lo[0], ex, 6), qbits(r0.y, sc.lo[1], ey, 6),
-                                qbits(r0.z, sc.lo[2], ez, 6)};
-        const uint32_t qd[3] = {qbits(r1.x, -1.0f, 2.0f, 4), qbits(r1.y, -1.0f, 2.0f, 4),
-                                qbits(r1.z, -1.0f, 2.0f, 4)};
-#pragma unroll
-        for (int bit = 5; bit >= 0; --bit)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) key = (key << 1) | ((qo[c] >> bit) & 1u);
-#pragma unroll
-        for (int bit = 3; bit >= 0; --bit)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) key = (key << 1) | ((qd[c] >> bit) & 1u);
-    } else {
-        uint32_t qc[6];
-        if (kind == PT_MODE_SORTED_AILA) {
-            qc[3] = qbits(r1.x, -1.0f, 2.0f, 5);
-            qc[4] = qbits(r1.y, -1.0f, 2.0f, 5);
-            qc[5] = qbits(r1.z, -1.0f, 2.0f, 5);
-        } else {   // TwoPoint: the point at a fixed length of 0.25 x the largest extent
-            float mx = ex;
-            if (ey > mx) mx = ey;
-            if (ez > mx) mx = ez;
-            const float len = 0.25f * mx;
-            qc[3] = qbits(r0.x + len * r1.x, sc.lo[0], ex, 5);
-            qc[4] = qbits(r0.y + len * r1.y, sc.lo[1], ey, 5);
-            qc[5] = qbits(r0.z + len * r1.z, sc.lo[2], ez, 5);
-        }
-        qc[0] = qbits(r0.x, sc.lo[0], ex, 5);
-        qc[1] = qbits(r0.y, sc.lo[1], ey, 5);
-        qc[2] = qbits(r0.z, sc.lo[2], ez, 5);
-#pragma unroll
-        for (int bit = 4; bit >= 0; --bit)
-#pragma unroll
-            for (int c = 0; c < 6; ++c) key = (key << 1) | ((qc[c] >> bit) & 1u);
-    }
-    return key;
-}
-
+// ------------------------------------------------------------------ reordering keys
 // keys of n rays in a plain queue (dead rays, pixel word kNoRay, get 0xFFFFFFFF)
 __global__ __launch_bounds__(256) void k_keys(DevScene sc, const float4* q, uint32_t n, uint32_t* keys,
                                               uint32_t* vals, int kind) {
@@ -1636,14 +1639,16 @@ __device__ __forceinline__ uint32_t fill_total(const uint32_t* fill, uint32_t n)
 }
 
 // Keys of the live rays of a compacted queue (sorted modes): ray i (i < the launch's rays, in
-// region order) gets its key and its queue slot; the digit histograms of all `passes` passes
-// of d bits each are added to hist[copy][pass][2^d], copy = workgroup mod kHistCopies (one
-// copy per XCD: fewer device-wide atomics on each word; a pass adds the copies up).  Also clears the look-back words of the passes.
-// 1024 threads x kKeysPerThread rays per workgroup, the rays' loads issued together.
+// region order) gets the key the shade kernel wrote at its queue slot (kslot) and the slot
+// itself; the digit histograms of all `passes` passes of d bits each are added to
+// hist[copy][pass][2^d], copy = workgroup mod kHistCopies (one copy per XCD: fewer
+// device-wide atomics on each word; a pass adds the copies up).  Also clears the look-back
+// words of the passes.  1024 threads x kKeysPerThread rays per workgroup, the loads issued
+// together.
 constexpr int kKeysPerThread = 8;
 template <int D>
-__global__ __launch_bounds__(1024) void k_keys_compacted(DevScene sc, const float4* q, const uint32_t* fill,
-                                                         uint32_t region, uint32_t* keys, uint32_t* vals, int kind,
+__global__ __launch_bounds__(1024) void k_keys_compacted(const uint32_t* kslot, const uint32_t* fill,
+                                                         uint32_t region, uint32_t* keys, uint32_t* vals,
                                                          int passes, uint32_t* hist, uint32_t* lookback,
                                                          uint32_t lookback_words) {
     constexpr uint32_t R = 1u << D;
@@ -1658,8 +1663,7 @@ __global__ __launch_bounds__(1024) void k_keys_compacted(DevScene sc, const floa
         cnt[c] = fill[c * kCounterStride];
         total += cnt[c];
     }
-    uint32_t pos[kKeysPerThread];
-    float4 r0[kKeysPerThread], r1[kKeysPerThread];
+    uint32_t pos[kKeysPerThread], key[kKeysPerThread];
 #pragma unroll
     for (int e = 0; e < kKeysPerThread; ++e) {
         const uint32_t i = (blockIdx.x * kKeysPerThread + (uint32_t)e) * 1024u + threadIdx.x;
@@ -1669,18 +1673,15 @@ __global__ __launch_bounds__(1024) void k_keys_compacted(DevScene sc, const floa
             ++c;
         }
         pos[e] = c * region + v;
-        const bool ok = i < total;
-        r0[e] = ok ? q[2 * (size_t)pos[e]] : make_float4(0.f, 0.f, 0.f, 0.f);
-        r1[e] = ok ? q[2 * (size_t)pos[e] + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+        key[e] = i < total ? kslot[pos[e]] : 0u;
     }
 #pragma unroll
     for (int e = 0; e < kKeysPerThread; ++e) {
         const uint32_t i = (blockIdx.x * kKeysPerThread + (uint32_t)e) * 1024u + threadIdx.x;
         if (i < total) {
-            const uint32_t key = ray_key(sc, r0[e], r1[e], kind);
-            keys[i] = key;
+            keys[i] = key[e];
             vals[i] = pos[e];
-            for (int ps = 0; ps < passes; ++ps) atomicAdd(&h[ps * R + ((key >> (D * ps)) & (R - 1u))], 1u);
+            for (int ps = 0; ps < passes; ++ps) atomicAdd(&h[ps * R + ((key[e] >> (D * ps)) & (R - 1u))], 1u);
         }
     }
     __syncthreads();
@@ -2009,13 +2010,14 @@ hipError_t launch_raygen(const Frame& f, int s, float4* q, float4* state, float4
 
 hipError_t launch_shade(const DevScene& sc, const Frame& f, int b, int s, const float4* q_in, float4* q_out,
                         float4* state, int32_t* hit_prim, float* hit_t, float* radiance, float4* rays_out,
-                        float4* shadow_rays, float4* shadow_light, uint32_t* fill, float4* debug, hipStream_t st) {
+                        float4* shadow_rays, float4* shadow_light, uint32_t* fill, uint32_t* keys_out, float4* debug,
+                        hipStream_t st) {
     const unsigned blocks = (unsigned)(f.nslots / (uint32_t)f.TS);
     const bool reuse = f.mode == PT_MODE_REUSE || f.mode == PT_MODE_REUSE_PLAIN || f.mode == PT_MODE_REUSE_WORLD;
     // reuse exchange (8 words per slot), then the compaction's ranks (1 per slot) and wave sums (40)
     const size_t lds = ((reuse ? (size_t)f.TS * 8 : 0) + (fill ? (size_t)f.TS + 40 : 0)) * sizeof(float);
     hipLaunchKernelGGL(k_shade, dim3(blocks), dim3(f.TS), lds, st, sc, f, b, s, q_in, q_out, state, hit_prim, hit_t,
-                       radiance, rays_out, shadow_rays, shadow_light, fill, debug);
+                       radiance, rays_out, shadow_rays, shadow_light, fill, keys_out, debug);
     return hipGetLastError();
 }
 
@@ -2061,14 +2063,14 @@ static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // render workspace: keys, vals, their alternates (n each), the histograms and tile counters
 // (zeroed per bounce), the look-back words of every pass
-size_t sort_compacted_workspace_bytes(uint32_t n) {
+size_t sort_compacted_workspace_bytes(uint32_t n, uint32_t qslots) {
     const size_t R = (size_t)1 << kRenderDigit;
     return 4 * al256((size_t)n * 4) + al256((kHistCopies * kRenderPasses * R + kRenderPasses) * 4) +
-           al256((size_t)kRenderPasses * lb_words(sort_tiles(n)) * 4);
+           al256((size_t)kRenderPasses * lb_words(sort_tiles(n)) * 4) + al256((size_t)qslots * 4);
 }
 
 struct SortWs {
-    uint32_t *keys, *vals, *kalt, *valt, *hist, *ctr, *lookback;
+    uint32_t *keys, *vals, *kalt, *valt, *hist, *ctr, *lookback, *kslot;
 };
 
 static SortWs sort_ws(void* ws, uint32_t n) {
@@ -2087,18 +2089,21 @@ static SortWs sort_ws(void* ws, uint32_t n) {
     w.ctr = w.hist + kHistCopies * kRenderPasses * R;
     p += al256((kHistCopies * kRenderPasses * R + kRenderPasses) * 4);
     w.lookback = (uint32_t*)p;
+    p += al256((size_t)kRenderPasses * lb_words(sort_tiles(n)) * 4);
+    w.kslot = (uint32_t*)p;
     return w;
 }
 
-hipError_t launch_keys_compacted(const DevScene& sc, const float4* q, const uint32_t* fill, uint32_t region,
-                                 uint32_t nslots, int kind, void* ws, hipStream_t st) {
+uint32_t* sort_key_slots(void* ws, uint32_t nslots) { return sort_ws(ws, nslots).kslot; }
+
+hipError_t launch_keys_compacted(const uint32_t* fill, uint32_t region, uint32_t nslots, void* ws, hipStream_t st) {
     const uint32_t R = 1u << kRenderDigit;
     const SortWs w = sort_ws(ws, nslots);
     hipError_t e = launch_zero(w.hist, (size_t)kHistCopies * kRenderPasses * R + kRenderPasses, st);
     if (e != hipSuccess) return e;
     const uint32_t kb = (nslots + kKeysPerThread * 1024 - 1) / (kKeysPerThread * 1024);
-    hipLaunchKernelGGL(k_keys_compacted<kRenderDigit>, dim3(kb), dim3(1024), 0, st, sc, q, fill,
-                       region, w.keys, w.vals, kind, kRenderPasses, w.hist, w.lookback,
+    hipLaunchKernelGGL(k_keys_compacted<kRenderDigit>, dim3(kb), dim3(1024), 0, st, w.kslot, fill, region, w.keys,
+                       w.vals, kRenderPasses, w.hist, w.lookback,
                        (uint32_t)((size_t)kRenderPasses * lb_words(sort_tiles(nslots))));
     return hipGetLastError();
 }
