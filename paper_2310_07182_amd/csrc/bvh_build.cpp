@@ -1,4 +1,4 @@
-// Host BVH2 builder: binned surface-area heuristic (32 centroid bins per axis,
+// Host BVH2 builder: binned surface-area heuristic (64 centroid bins per axis,
 // traversal and intersection cost 1), leaves of at most kMaxLeaf triangles,
 // object-median splits once the remaining depth budget only just fits a
 // balanced subtree, so that the leaf depth never exceeds kMaxDepth.  Large subtrees are built on separate threads; the output
@@ -23,7 +23,7 @@
 namespace pt {
 namespace {
 
-constexpr int kBins = 32;
+constexpr int kBins = 64;
 constexpr uint32_t kParallelMin = 1u << 16;
 constexpr uint32_t kParallelBinMin = 1u << 20;
 
