@@ -53,8 +53,11 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_trace_{config}_1080p.md")
+# sources whose change makes the committed counter summaries stale (the kernels, the host code
+# that launches them, the build flags and the BVH builder, which sets the work per ray)
 KERNEL_SOURCES = ("paper_2310_07182_amd/csrc/kernels.hip", "paper_2310_07182_amd/csrc/kernels.h",
-                  "paper_2310_07182_amd/csrc/capi.hip", "paper_2310_07182_amd/build.py")
+                  "paper_2310_07182_amd/csrc/capi.hip", "paper_2310_07182_amd/build.py",
+                  "paper_2310_07182_amd/csrc/bvh_build.cpp")
 
 
 def measured_traffic(mode, config):
@@ -786,7 +789,7 @@ def summarize_profile(config, prof_dir, out_path, modes, bounces, counters):
                      f"{abl / t / 1e9 / HBM_PEAK_GBS:.3f} | {traffic[m]:.4g} | {traffic[m] / t / 1e9:.0f} | "
                      f"{lane_ops[m]:.4g} | {lane_ops[m] / t / 1e12 / VALU_PEAK_TOPS:.3f} |".replace("nan", "-"))
     L.append("")
-    L.append("Machine-readable lines read by bench.py (source digest of kernels.hip, kernels.h, capi.hip and build.py "
+    L.append("Machine-readable lines read by bench.py (source digest of kernels.hip, kernels.h, capi.hip, build.py and bvh_build.cpp "
              "when the counters were taken):")
     L.append("")
     L.append("```")
