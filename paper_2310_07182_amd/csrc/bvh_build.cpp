@@ -14,6 +14,7 @@
 #include <cmath>
 #include <array>
 #include <cstring>
+#include <functional>
 #include <future>
 #include <limits>
 #include <thread>
@@ -301,6 +302,13 @@ bool build_bvh(const float* tris, uint32_t ntri, HostBvh& out, std::string& err)
 namespace pt {
 
 void collapse_bvh4(const std::vector<BvhNode>& n2, std::vector<Bvh4Node>& n4, uint32_t& max_depth4) {
+    // Which binary nodes become four-wide nodes: each inner binary node either roots a
+    // four-wide node (cost: its surface area, the probability that a ray visits it) or is
+    // opened, its two subtrees taking its place among the entries of the four-wide node above
+    // it (at most four entries per node).  Leaves are entries wherever they land, so their
+    // cost is fixed; the total area of the four-wide nodes is minimized by dynamic programming
+    // over (binary node, entries available), children before parents (every child follows its
+    // parent in the depth-first order of the binary nodes).
     struct Entry {
         float lo[3], hi[3];
         int32_t code;
@@ -317,8 +325,81 @@ void collapse_bvh4(const std::vector<BvhNode>& n2, std::vector<Bvh4Node>& n4, ui
     n4.clear();
     max_depth4 = 0;
     if (n2.empty()) return;
+    const size_t nn = n2.size();
+    // own[k]: area of binary node k's box (the union of its children's boxes)
+    // cost[k][m-1]: least cost of covering subtree k with at most m entries (m = 1..4);
+    // m = 1: k roots a four-wide node.  split[k][m-1]: entries given to child 0 when k is
+    // opened (0: not opened; 255: k has one child, which takes all m)
+    std::vector<double> cost(nn * 4);
+    std::vector<uint8_t> split(nn * 4);
+    std::vector<double> own(nn);
+    auto entry_cost = [&](const Entry& e, int m) -> double {   // an entry with at most m slots
+        if (e.code == kEmpty || e.code < 0) return 0.0;          // leaves cost the same anywhere
+        return cost[(size_t)e.code * 4 + (size_t)(m - 1)];
+    };
+    for (size_t kk = nn; kk-- > 0;) {
+        const int32_t k = (int32_t)kk;
+        Entry two[2];
+        children(k, two);
+        const bool has0 = two[0].code != kEmpty, has1 = two[1].code != kEmpty;
+        Entry u = two[0];
+        for (int a = 0; a < 3; ++a) {
+            u.lo[a] = std::min(two[0].lo[a], two[1].lo[a]);
+            u.hi[a] = std::max(two[0].hi[a], two[1].hi[a]);
+        }
+        own[kk] = has0 && has1 ? half_area(u) : half_area(has0 ? two[0] : two[1]);
+        // opened with m slots: the best division of the slots between the two children
+        auto opened = [&](int m, int& best0) -> double {
+            double best = std::numeric_limits<double>::infinity();
+            best0 = 0;
+            if (has0 && has1) {
+                for (int m0 = 1; m0 < m; ++m0) {
+                    const double c = entry_cost(two[0], m0) + entry_cost(two[1], m - m0);
+                    if (c < best) {
+                        best = c;
+                        best0 = m0;
+                    }
+                }
+            } else {
+                best = entry_cost(has0 ? two[0] : two[1], m);
+                best0 = has0 ? m : 0;
+            }
+            return best;
+        };
+        int b0 = 0;
+        const double root = own[kk] + opened(4, b0);   // k roots a four-wide node over 4 slots
+        cost[kk * 4 + 0] = root;
+        split[kk * 4 + 0] = 0;
+        for (int m = 2; m <= 4; ++m) {
+            const double op = opened(m, b0);
+            const bool open = op < root;   // opening k pays when its subtrees fill the slots more cheaply
+            cost[kk * 4 + (size_t)(m - 1)] = open ? op : root;
+            split[kk * 4 + (size_t)(m - 1)] = (uint8_t)(open ? (has0 && has1 ? b0 : 255) : 0);
+        }
+    }
+    // the entries of binary node k placed with at most m slots (k opened or not)
+    std::function<void(const Entry&, int, Entry*, int&)> place = [&](const Entry& e, int m, Entry* out, int& ne) {
+        if (e.code == kEmpty) return;
+        if (e.code < 0 || m == 1) {
+            out[ne++] = e;
+            return;
+        }
+        const uint8_t s = split[(size_t)e.code * 4 + (size_t)(m - 1)];
+        if (s == 0) {
+            out[ne++] = e;
+            return;
+        }
+        Entry two[2];
+        children(e.code, two);
+        if (s == 255) {   // one child only: it takes all m slots
+            place(two[0].code != kEmpty ? two[0] : two[1], m, out, ne);
+            return;
+        }
+        place(two[0], s, out, ne);
+        place(two[1], m - s, out, ne);
+    };
     struct Item {
-        int32_t k2;       // child-pair node to collapse
+        int32_t k2;       // binary node that roots a four-wide node
         uint32_t slot;    // four-wide node it becomes
         uint32_t depth;
     };
@@ -332,22 +413,21 @@ void collapse_bvh4(const std::vector<BvhNode>& n2, std::vector<Bvh4Node>& n4, ui
         int ne = 0;
         Entry two[2];
         children(it.k2, two);
-        for (const Entry& x : two)
-            if (x.code != kEmpty) e[ne++] = x;
-        while (ne < 4) {
-            int best = -1;
-            double area = -1.0;
-            for (int j = 0; j < ne; ++j)
-                if (e[j].code >= 0 && half_area(e[j]) > area) {
-                    area = half_area(e[j]);
-                    best = j;
+        const bool has0 = two[0].code != kEmpty, has1 = two[1].code != kEmpty;
+        if (has0 && has1) {
+            int b0 = 0;
+            double best = std::numeric_limits<double>::infinity();
+            for (int m0 = 1; m0 < 4; ++m0) {
+                const double c = entry_cost(two[0], m0) + entry_cost(two[1], 4 - m0);
+                if (c < best) {
+                    best = c;
+                    b0 = m0;
                 }
-            if (best < 0) break;
-            Entry sub[2];
-            children(e[best].code, sub);
-            e[best] = e[--ne];
-            for (const Entry& x : sub)
-                if (x.code != kEmpty) e[ne++] = x;
+            }
+            place(two[0], b0, e, ne);
+            place(two[1], 4 - b0, e, ne);
+        } else if (has0 || has1) {
+            place(has0 ? two[0] : two[1], 4, e, ne);
         }
         Bvh4Node nd;
         for (int j = 0; j < 4; ++j) {
