@@ -413,3 +413,76 @@ def test_bvh4_empty_and_single_leaf(L):
         codes = raw[:, 24:28].view(np.int32)
         assert info.nnodes4 == 1 and codes[0, 0] < 0 and (codes[0, 1:] == np.iinfo(np.int32).min).all()
         L.pt_scene_free(h)
+
+
+@pytest.mark.parametrize("ntri,seed", [(24, 1), (36, 2), (40, 3)])
+def test_bvh4_collapse_is_optimal(L, ntri, seed):
+    """The four-wide collapse chooses which binary nodes root four-wide nodes so that their
+    summed surface area (the visit cost; leaves cost the same wherever they land) is least:
+    checked against every valid choice on small random trees (brute force)."""
+    import itertools
+
+    s = dict(scenes.furnace())
+    rng = np.random.default_rng(seed)
+    cen = rng.uniform(0.0, 10.0, (ntri, 1, 3))
+    cen[: ntri // 2] *= 0.3                                   # a cluster and a spread
+    s["tris"] = (cen + rng.uniform(-0.4, 0.4, (ntri, 3, 3))).astype(np.float32)
+    s["tri_mat"] = np.zeros(ntri, np.uint32)
+    st, h, keep = _create(L, s)
+    assert st == 0
+    info = capi.SceneInfo()
+    L.pt_scene_get_info(h, C.byref(info))
+    n2 = np.zeros((info.nnodes, 16), np.float32)
+    order = np.zeros(ntri, np.uint32)
+    L.pt_scene_export_bvh(h, n2.ctypes.data, order.ctypes.data)
+    _, raw = _bvh4(L, h)
+    L.pt_scene_free(h)
+    EMPTY = np.iinfo(np.int32).min
+    codes2 = n2[:, 12:14].view(np.int32)
+
+    def area(lo, hi):
+        d = np.asarray(hi, np.float64) - np.asarray(lo, np.float64)
+        return d[0] * d[1] + d[1] * d[2] + d[2] * d[0]
+
+    def child_boxes(k):
+        f = n2[k].astype(np.float64)
+        return [((f[0], f[2], f[8]), (f[1], f[3], f[9])), ((f[4], f[6], f[10]), (f[5], f[7], f[11]))]
+
+    def node_area(k):
+        bs = [b for b, c in zip(child_boxes(k), codes2[k]) if c != EMPTY]
+        lo = np.min([b[0] for b in bs], axis=0)
+        hi = np.max([b[1] for b in bs], axis=0)
+        return area(lo, hi)
+
+    inner = [k for k in range(info.nnodes)]
+    assert 4 <= len(inner) <= 18, len(inner)                # brute force stays small
+
+    def entries(k, opened):
+        n = 0
+        for c in codes2[k]:
+            if c == EMPTY:
+                continue
+            n += entries(int(c), opened) if (c >= 0 and int(c) in opened) else 1
+        return n
+
+    best = np.inf
+    others = inner[1:]
+    for r in range(len(others) + 1):
+        for opened in itertools.combinations(others, r):
+            op = set(opened)
+            roots = [k for k in inner if k not in op]
+            if all(entries(k, op) <= 4 for k in roots):
+                best = min(best, sum(node_area(k) for k in roots))
+    # cost of the exported four-wide tree: the root's box plus every inner entry's box
+    boxes = raw[:, :24].reshape(-1, 6, 4).astype(np.float64)
+    codes4 = raw[:, 24:28].view(np.int32)
+    valid = codes4[0] != EMPTY
+    lo0 = [boxes[0, 2 * a][valid].min() for a in range(3)]
+    hi0 = [boxes[0, 2 * a + 1][valid].max() for a in range(3)]
+    got = area(lo0, hi0)
+    for n in range(len(raw)):
+        for j in range(4):
+            if codes4[n, j] >= 0:
+                got += area([boxes[n, 0, j], boxes[n, 2, j], boxes[n, 4, j]], [boxes[n, 1, j], boxes[n, 3, j], boxes[n, 5, j]])
+    assert got <= best * (1 + 1e-9), (got, best)
+    assert got >= best * (1 - 1e-9), (got, best)
