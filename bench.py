@@ -694,12 +694,13 @@ def summarize_profile(config, prof_dir, out_path, modes, bounces, counters):
     L.append("Commands (from the repository root, `export TMPDIR=/tmp` first), then this summary:")
     L.append("")
     L.append("```")
-    L.append(f"rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/pf_{config}_kt -o kt -- "
-             f"python -u bench.py --config {config} --profile > gpurun_out/pf_{config}_kt.log 2>&1")
+    pd = os.path.normpath(os.path.relpath(prof_dir, ROOT)) if os.path.isabs(prof_dir) else os.path.normpath(prof_dir)
+    L.append(f"rocprofv3 --kernel-trace --stats --output-format csv -d {pd}/pf_{config}_kt -o kt -- "
+             f"python -u bench.py --config {config} --profile > {pd}/pf_{config}_kt.log 2>&1")
     for j, names in enumerate(counters, start=1):
-        L.append(f"timeout -s KILL 300 rocprofv3 --pmc {names} --output-format csv -d gpurun_out/pf_{config}_pmc{j} "
+        L.append(f"timeout -s KILL 300 rocprofv3 --pmc {names} --output-format csv -d {pd}/pf_{config}_pmc{j} "
                  f"-o pmc -- python -u bench.py --config {config} --profile")
-    L.append(f"python bench.py --summarize-profile gpurun_out --config {config}")
+    L.append(f"python bench.py --summarize-profile {pd} --config {config}")
     L.append("```")
     L.append("")
     L.append("## Kernel trace summary (rocprofv3 --stats, all kernels of the run)")
@@ -874,7 +875,7 @@ def main():
         print(out)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {args.gpus}); "
+        print(f"bench.py measures one GPU only: the library has no multi-GPU path (asked for {args.gpus}); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
