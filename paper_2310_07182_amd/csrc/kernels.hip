@@ -293,6 +293,7 @@ __device__ __forceinline__ uint64_t claimed_ray(uint32_t v, uint32_t c) {
 // (fill, no permutation): the first nc = fill[c] slots of region c.  The index is monotone
 // in v, so the first v without a ray ends the counter.
 constexpr uint64_t kNoClaim = ~0ull;
+constexpr uint32_t kSpread = 64;   // stripes of the spread claim order of launches with fewer rays than lanes
 __device__ __forceinline__ uint64_t claim_index(bool regions, uint32_t region, uint32_t v, uint32_t c, uint32_t n,
                                                 uint32_t nc) {
     if (regions) return v < nc ? (uint64_t)c * region + v : kNoClaim;
@@ -798,7 +799,22 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
             }
             const uint32_t rank = (uint32_t)__popcll(idle & lt);
             if (!have && rank < need) {
-                const uint64_t i64 = claim_index(regions, a.region, base + rank, c, n, nc);
+                // a launch with fewer rays than lanes is latency-bound: each wave's rays are
+                // spread over the queue (a stripe transpose, a bijection on the rays of the
+                // counter, or of the launch), so that neighbouring rays, alike in a reuse group
+                // or in key order, do not all land in one wave and leave it last to finish
+                uint32_t v = base + rank;
+                const bool spread = !MULTI && n < gthreads;
+                if (spread && regions && v < nc) {
+                    const uint32_t sq = nc / kSpread, sr = nc % kSpread, st = v % kSpread, sp = v / kSpread;
+                    v = st * sq + (st < sr ? st : sr) + sp;
+                }
+                uint64_t i64 = claim_index(regions, a.region, v, c, n, nc);
+                if (spread && !regions && i64 != kNoClaim) {
+                    const uint32_t w = (uint32_t)i64;
+                    const uint32_t sq = n / kSpread, sr = n % kSpread, st = w % kSpread, sp = w / kSpread;
+                    i64 = st * sq + (st < sr ? st : sr) + sp;
+                }
                 const uint32_t i = (uint32_t)i64;
                 if (i64 != kNoClaim) {
                     const float4* rays = a.rays;
