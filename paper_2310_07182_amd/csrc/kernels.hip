@@ -1322,7 +1322,13 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
         prim = hit_prim[hb + pix];
         t = hit_t[hb + pix];
     }
-    const float4 r0 = q_in[2 * (size_t)qpos], r1 = q_in[2 * (size_t)qpos + 1];
+    // a path that is already over reads no ray and keeps its state as it is: later bounces
+    // read only its cleared alive bit, and the next sample's ray generation rewrites it
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+    if (alive_in) {
+        r0 = q_in[2 * (size_t)qpos];
+        r1 = q_in[2 * (size_t)qpos + 1];
+    }
     const V3 o = xyz(r0), d = xyz(r1);
     const bool hit = alive_in && prim >= 0;
     pt_material m;
@@ -1560,8 +1566,10 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
     }
     // the next hit's emission is skipped when this point estimated its direct light
     const bool nee_next = alive && f.nee && kind == 0;
-    state[2 * (size_t)p] = make_float4(T[0], T[1], T[2], __uint_as_float((alive ? 1u : 0u) | (nee_next ? 2u : 0u)));
-    state[2 * (size_t)p + 1] = make_float4(L[0], L[1], L[2], __uint_as_float(newpos));
+    if (alive_in) {
+        state[2 * (size_t)p] = make_float4(T[0], T[1], T[2], __uint_as_float((alive ? 1u : 0u) | (nee_next ? 2u : 0u)));
+        state[2 * (size_t)p + 1] = make_float4(L[0], L[1], L[2], __uint_as_float(newpos));
+    }
 }
 
 __global__ __launch_bounds__(1024) void k_shade(DevScene sc, Frame f, int b, int s, const float4* __restrict__ q_in,
@@ -1725,9 +1733,10 @@ __global__ __launch_bounds__(256) void k_digit_hist(const uint32_t* keys, uint32
 }
 
 // One stable pass over digit (key >> shift) & (2^d - 1) of n keys (n = the rays of fill when
-// fill is given), 2^d = the workgroup's 256 threads.  ghist: the pass's digit histogram over
-// all keys, in kHistCopies copies gstride words apart; lookback: lb_words(tiles) words, zero
-// on entry (tile counts, then block counts, then block counters); tile_ctr: zero on entry.
+// fill is given), 2^d a multiple of the workgroup's 256 threads (DPT digits per thread).
+// ghist: the pass's digit histogram over all keys, in kHistCopies copies gstride words
+// apart; lookback: lb_words(tiles, d) words, zero on entry (tile counts, then block
+// counts, then block counters); tile_ctr: zero on entry.
 //
 // Tile t (ids in start order) holds keys [t * kOsTile, ...), wave w of it the kOsItems x 64
 // consecutive keys from w * kOsItems * 64 on.  The pass: count the tile's digits and publish
@@ -1739,7 +1748,7 @@ __global__ __launch_bounds__(256) void k_digit_hist(const uint32_t* keys, uint32
 // lower tile belongs to a workgroup that started earlier and publishes without waiting on
 // anything, so every wait below ends.
 constexpr int kLbBlock = 16;
-static_assert(kOsThreads == 256, "one digit per thread (8-bit digits)");
+static_assert(kOsThreads == 256, "scan256 spans the workgroup");
 
 __device__ __forceinline__ uint32_t lb_wait(const uint32_t* w) {
     uint32_t v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1769,7 +1778,8 @@ __global__ __launch_bounds__(kOsThreads) void k_onesweep(const uint32_t* kin, co
                                                          int shift, const uint32_t* ghist, uint32_t gstride,
                                                          uint32_t* lookback, uint32_t* tile_ctr) {
     constexpr uint32_t R = 1u << D;
-    static_assert(R == (uint32_t)kOsThreads, "one digit per thread");
+    static_assert(R % (uint32_t)kOsThreads == 0, "whole digits per thread");
+    constexpr int DPT = (int)(R / kOsThreads);           // digits per thread
     constexpr int W = kOsThreads / 64;
     constexpr uint32_t WK = (uint32_t)kOsItems * 64u;   // keys per wave
     __shared__ uint32_t s_cnt[R];      // the tile's digit counts
@@ -1787,9 +1797,13 @@ __global__ __launch_bounds__(kOsThreads) void k_onesweep(const uint32_t* kin, co
     uint32_t* const bagg = lookback + (size_t)tiles * R;   // [nblk][R] block counts
     uint32_t* const bctr = bagg + (size_t)nblk * R;        // [nblk] tiles of the block published
     if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
-    s_cnt[tid] = 0;
 #pragma unroll
-    for (int w = 0; w < W; ++w) s_wcnt[w][tid] = 0;
+    for (int e = 0; e < DPT; ++e) {
+        const uint32_t d = (uint32_t)tid + (uint32_t)e * kOsThreads;
+        s_cnt[d] = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) s_wcnt[w][d] = 0;
+    }
     __syncthreads();
     const uint32_t t = s_tile;
     const uint32_t first = t * kOsTile;
@@ -1808,24 +1822,51 @@ __global__ __launch_bounds__(kOsThreads) void k_onesweep(const uint32_t* kin, co
         if (wfirst + (uint32_t)r * 64u < valid_n) atomicAdd(&s_cnt[(k[r] >> shift) & (R - 1u)], 1u);
     __syncthreads();
     // publish the tile's counts; the block's last tile to do so publishes the block's counts
+    // (digits tid + e * 256: neighbouring threads, neighbouring words)
     const uint32_t blk = t / kLbBlock, b0 = blk * kLbBlock;
     const uint32_t bsize = tiles - b0 < (uint32_t)kLbBlock ? tiles - b0 : (uint32_t)kLbBlock;
-    __hip_atomic_store(&lookback[(size_t)t * R + tid], kLbAgg | s_cnt[tid], __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int e = 0; e < DPT; ++e) {
+        const uint32_t d = (uint32_t)tid + (uint32_t)e * kOsThreads;
+        __hip_atomic_store(&lookback[(size_t)t * R + d], kLbAgg | s_cnt[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __syncthreads();
     if (tid == 0) s_last = atomicAdd(&bctr[blk], 1u) == bsize - 1u ? 1u : 0u;
     __syncthreads();
     if (s_last) {
-        const uint32_t sum = lb_sum(lookback + (size_t)b0 * R + tid, R, bsize);
-        __hip_atomic_store(&bagg[(size_t)blk * R + tid], kLbInc | sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    // exclusive prefixes over the digits: of the global histogram and of the tile's counts
-    uint32_t gh = 0;
 #pragma unroll
-    for (uint32_t c = 0; c < kHistCopies; ++c) gh += ghist[c * gstride + tid];
-    const uint32_t lc = s_cnt[tid];
-    s_gbase[tid] = scan256(gh, s_wsum, nullptr);
-    s_lbase[tid] = scan256(lc, s_wsum, nullptr);
+        for (int e = 0; e < DPT; ++e) {
+            const uint32_t d = (uint32_t)tid + (uint32_t)e * kOsThreads;
+            const uint32_t sum = lb_sum(lookback + (size_t)b0 * R + d, R, bsize);
+            __hip_atomic_store(&bagg[(size_t)blk * R + d], kLbInc | sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    // exclusive prefixes over the digits, of the global histogram and of the tile's counts
+    // (here each thread takes DPT consecutive digits)
+    {
+        uint32_t gv[DPT], lv[DPT], gsum = 0, lsum = 0;
+#pragma unroll
+        for (int e = 0; e < DPT; ++e) {
+            const uint32_t d = (uint32_t)tid * DPT + (uint32_t)e;
+            uint32_t g = 0;
+#pragma unroll
+            for (uint32_t c = 0; c < kHistCopies; ++c) g += ghist[c * gstride + d];
+            gv[e] = g;
+            lv[e] = s_cnt[d];
+            gsum += g;
+            lsum += lv[e];
+        }
+        uint32_t gpre = scan256(gsum, s_wsum, nullptr);
+        uint32_t lpre = scan256(lsum, s_wsum, nullptr);
+#pragma unroll
+        for (int e = 0; e < DPT; ++e) {
+            const uint32_t d = (uint32_t)tid * DPT + (uint32_t)e;
+            s_gbase[d] = gpre;
+            s_lbase[d] = lpre;
+            gpre += gv[e];
+            lpre += lv[e];
+        }
+    }
     // stable ranking in index order (wave, round, lane): per-wave running counts, the
     // lowest lane of each digit in a round adding the round's keys of that digit
     uint32_t rk[kOsItems];
@@ -1845,12 +1886,14 @@ __global__ __launch_bounds__(kOsThreads) void k_onesweep(const uint32_t* kin, co
         if (ok && rank == 0) s_wcnt[wave][dg] = before + (uint32_t)__popcll(same);
     }
     __syncthreads();
-    {   // per-wave counts -> offsets of each wave's keys of digit tid within the tile's digit run
+#pragma unroll
+    for (int e = 0; e < DPT; ++e) {   // per-wave counts -> offsets of each wave's keys in its digit's run
+        const uint32_t d = (uint32_t)tid + (uint32_t)e * kOsThreads;
         uint32_t acc = 0;
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            const uint32_t c = s_wcnt[w][tid];
-            s_wcnt[w][tid] = acc;
+            const uint32_t c = s_wcnt[w][d];
+            s_wcnt[w][d] = acc;
             acc += c;
         }
     }
@@ -1864,14 +1907,18 @@ __global__ __launch_bounds__(kOsThreads) void k_onesweep(const uint32_t* kin, co
             s_v[lpos] = v[r];
         }
     }
-    // keys of digit tid in the lower tiles: the lower blocks, then the block's lower tiles
-    uint32_t below = 0;
-    for (uint32_t bb = 0; bb < blk; bb += kLbBlock) {
-        const uint32_t m = blk - bb < (uint32_t)kLbBlock ? blk - bb : (uint32_t)kLbBlock;
-        below += lb_sum(bagg + (size_t)bb * R + tid, R, m);
+    // keys of each digit in the lower tiles: the lower blocks, then the block's lower tiles
+#pragma unroll
+    for (int e = 0; e < DPT; ++e) {
+        const uint32_t d = (uint32_t)tid + (uint32_t)e * kOsThreads;
+        uint32_t below = 0;
+        for (uint32_t bb = 0; bb < blk; bb += kLbBlock) {
+            const uint32_t m = blk - bb < (uint32_t)kLbBlock ? blk - bb : (uint32_t)kLbBlock;
+            below += lb_sum(bagg + (size_t)bb * R + d, R, m);
+        }
+        below += lb_sum(lookback + (size_t)b0 * R + d, R, t - b0);
+        s_gbase[d] += below;
     }
-    below += lb_sum(lookback + (size_t)b0 * R + tid, R, t - b0);
-    s_gbase[tid] += below;
     __syncthreads();
     // runs of equal digits go to consecutive places, written by consecutive threads
     for (uint32_t i = tid; i < valid_n; i += kOsThreads) {
@@ -2060,9 +2107,10 @@ hipError_t launch_count_finalize(const uint32_t* partial, int stride, int parts,
 }
 
 // ---- sorted modes and the plain sort
-// 30-bit keys: 4 passes of 8-bit digits.  3 passes of 10-bit digits measured slower (87 against
-// 37 us per pass for 2M keys on MI355X): a pass's look-back and tile-count words grow with the
-// number of digits, and at ~4 keys per digit and tile its writes are short runs.
+// 30-bit keys: 4 passes of 8-bit digits.  3 passes of 10-bit digits (the same kernel, 4 digits
+// per thread) measured slower: 40 against 26 us per pass over the ~2M live rays of a 1080p
+// bounce on MI355X.  A workgroup's LDS grows from 39 to 60 KB (2 workgroups per CU instead of
+// 4), its count words fourfold, and at ~4 keys per digit and tile the writes are short runs.
 constexpr int kRenderDigit = 8;
 constexpr int kRenderPasses = 4;
 static_assert(kRenderDigit * kRenderPasses >= 30 && kRenderPasses <= 4, "the keys' 30 bits, at most 4 passes");
@@ -2070,10 +2118,11 @@ constexpr int kPlainDigit = 8;                 // 32-bit keys: 4 passes of 8-bit
 constexpr int kPlainPasses = 4;
 
 static uint32_t sort_tiles(uint32_t n) { return (n + kOsTile - 1) / kOsTile; }
-// look-back words of one pass over this many tiles: tile counts, block counts, block counters
-static size_t lb_words(uint32_t tiles) {
+// look-back words of one pass of d-bit digits over this many tiles: tile counts, block
+// counts (2^d words each), block counters
+static size_t lb_words(uint32_t tiles, int d) {
     const size_t nb = (tiles + kLbBlock - 1) / kLbBlock;
-    return ((size_t)tiles + nb) * kOsThreads + nb;
+    return ((size_t)tiles + nb) * ((size_t)1 << d) + nb;
 }
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -2082,7 +2131,7 @@ static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 size_t sort_compacted_workspace_bytes(uint32_t n, uint32_t qslots) {
     const size_t R = (size_t)1 << kRenderDigit;
     return 4 * al256((size_t)n * 4) + al256((kHistCopies * kRenderPasses * R + kRenderPasses) * 4) +
-           al256((size_t)kRenderPasses * lb_words(sort_tiles(n)) * 4) + al256((size_t)qslots * 4);
+           al256((size_t)kRenderPasses * lb_words(sort_tiles(n), kRenderDigit) * 4) + al256((size_t)qslots * 4);
 }
 
 struct SortWs {
@@ -2105,7 +2154,7 @@ static SortWs sort_ws(void* ws, uint32_t n) {
     w.ctr = w.hist + kHistCopies * kRenderPasses * R;
     p += al256((kHistCopies * kRenderPasses * R + kRenderPasses) * 4);
     w.lookback = (uint32_t*)p;
-    p += al256((size_t)kRenderPasses * lb_words(sort_tiles(n)) * 4);
+    p += al256((size_t)kRenderPasses * lb_words(sort_tiles(n), kRenderDigit) * 4);
     w.kslot = (uint32_t*)p;
     return w;
 }
@@ -2120,7 +2169,7 @@ hipError_t launch_keys_compacted(const uint32_t* fill, uint32_t region, uint32_t
     const uint32_t kb = (nslots + kKeysPerThread * 1024 - 1) / (kKeysPerThread * 1024);
     hipLaunchKernelGGL(k_keys_compacted<kRenderDigit>, dim3(kb), dim3(1024), 0, st, w.kslot, fill, region, w.keys,
                        w.vals, kRenderPasses, w.hist, w.lookback,
-                       (uint32_t)((size_t)kRenderPasses * lb_words(sort_tiles(nslots))));
+                       (uint32_t)((size_t)kRenderPasses * lb_words(sort_tiles(nslots), kRenderDigit)));
     return hipGetLastError();
 }
 
@@ -2133,7 +2182,7 @@ hipError_t launch_sort_compacted(const uint32_t* fill, uint32_t nslots, void* ws
     for (int ps = 0; ps < kRenderPasses; ++ps) {
         hipLaunchKernelGGL(k_onesweep<kRenderDigit>, dim3(tiles), dim3(kOsThreads), 0, st, kin, vin, kout, vout, fill,
                            0u, kRenderDigit * ps, w.hist + (size_t)ps * R, (uint32_t)(kRenderPasses * R),
-                           w.lookback + (size_t)ps * lb_words(tiles), w.ctr + ps);
+                           w.lookback + (size_t)ps * lb_words(tiles, kRenderDigit), w.ctr + ps);
         uint32_t* tk = kin;
         kin = kout;
         kout = tk;
@@ -2148,7 +2197,7 @@ hipError_t launch_sort_compacted(const uint32_t* fill, uint32_t nslots, void* ws
 size_t sort_workspace_bytes(uint32_t n) {
     const size_t R = (size_t)1 << kPlainDigit;
     return 2 * al256((size_t)n * 4) + al256((kHistCopies * kPlainPasses * R + kPlainPasses) * 4) +
-           al256((size_t)kPlainPasses * lb_words(sort_tiles(n)) * 4);
+           al256((size_t)kPlainPasses * lb_words(sort_tiles(n), kPlainDigit) * 4);
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t n, void* ws, hipStream_t st) {
@@ -2171,7 +2220,7 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t n, void* ws
     for (int ps = 0; ps < kPlainPasses; ++ps) {
         hipLaunchKernelGGL(k_onesweep<kPlainDigit>, dim3(tiles), dim3(kOsThreads), 0, st, kin, vin, kout, vout,
                            (const uint32_t*)nullptr, n, kPlainDigit * ps, hist + (size_t)ps * R,
-                           (uint32_t)(kPlainPasses * R), lookback + (size_t)ps * lb_words(tiles), ctr + ps);
+                           (uint32_t)(kPlainPasses * R), lookback + (size_t)ps * lb_words(tiles, kPlainDigit), ctr + ps);
         uint32_t* tk = kin;
         kin = kout;
         kout = tk;
