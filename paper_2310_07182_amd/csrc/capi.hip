@@ -200,7 +200,7 @@ void set_camera(Frame& f, const pt_camera* cam, int w, int h) {
 }
 
 struct Layout {
-    size_t q0, q1, state, work, partial, sortws, ovf, total;
+    size_t q0, q1, state, live, work, partial, sortws, ovf, total;
     size_t shray, shc, sprim, st, swork, spartial;   // next-event estimation
 };
 
@@ -215,6 +215,8 @@ Layout layout(const Frame& f) {
     o = align256(o + qb);
     L.state = o;
     o = align256(o + qb);
+    L.live = o;
+    o = align256(o + (size_t)(f.nslots / (uint32_t)f.TS) * 4);
     L.work = o;
     o = align256(o + launches * pt::kWorkWords * 4);
     L.partial = o;
@@ -547,6 +549,7 @@ pt_status pt_render(pt_scene scene, const pt_camera* cam, int w, int h, int spp,
     char* ws = (char*)workspace;
     float4* q[2] = {(float4*)(ws + L.q0), (float4*)(ws + L.q1)};
     float4* state = (float4*)(ws + L.state);
+    f.live = (uint32_t*)(ws + L.live);
     uint32_t* partial = (uint32_t*)(ws + L.partial);
     uint32_t* work = (uint32_t*)(ws + L.work);
     int32_t* ovf = (int32_t*)(ws + L.ovf);

@@ -40,6 +40,8 @@ struct Frame {
     int frame_groups;         // one tile shuffle per sample (drawn at bounce 0), not one per bounce
     uint32_t region;          // compacted queues: ray slots per region (8 regions, workgroup blk
                               // writes region blk mod 8): ceil(workgroups / 8) x TS
+    uint32_t* live;           // optional, one word per shade workgroup: nonzero while a path of
+                              // the workgroup goes on (set by ray generation, kept by shading)
 };
 
 // Ray queue record: {ox, oy, oz, excluded prim} {dx, dy, dz, pixel}; pixel = kNoRay: no ray.

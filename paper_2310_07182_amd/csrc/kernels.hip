@@ -1199,6 +1199,7 @@ __device__ __forceinline__ void raygen_body(const Frame& f, int s, uint32_t blk,
     q[2 * (size_t)p + 1] = r1;
     state[2 * (size_t)p] = s0;
     state[2 * (size_t)p + 1] = s1;
+    if (f.live && l == 0) f.live[blk] = 1u;
 }
 
 __global__ __launch_bounds__(1024) void k_raygen(Frame f, int s, float4* q, float4* state, float4* rays_out) {
@@ -1312,6 +1313,24 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
     const uint32_t qpos = __float_as_uint(s1.w);
     const size_t plane = (size_t)f.w * (size_t)f.h;
     const size_t hb = ((size_t)b * f.spp + s) * plane;
+    if (f.live && f.live[blk] == 0u) {
+        // every path of the workgroup is over (its flag, from the last bounce, is uniform):
+        // only the outputs that every slot gets are written (the empty shadow rays, the
+        // debug record, and the dead entries of a plain queue, at the slots themselves: the
+        // group shuffle permutes the workgroup's slots)
+        if (shadow_rays) {
+            shadow_rays[2 * (size_t)p] = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+            shadow_rays[2 * (size_t)p + 1] = make_float4(0.f, 0.f, 0.f, __uint_as_float(kNoRay));
+            shadow_light[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        if (debug && b < f.B && spx.inside)
+            debug[((size_t)b * f.spp + s) * plane + pix] = make_float4(0.f, 0.f, 0.f, __uint_as_float(0u));
+        if (!fill && b < f.B) {
+            q_out[2 * (size_t)p] = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+            q_out[2 * (size_t)p + 1] = make_float4(0.f, 0.f, 0.f, __uint_as_float(kNoRay));
+        }
+        return;
+    }
     // The shading below is straight-line code: every lane evaluates every candidate
     // exit and the results are selected by material kind.  (A divergent three-way
     // branch here was miscompiled: registers live into the last branch were reused
@@ -1569,6 +1588,10 @@ __device__ __forceinline__ void shade_body(const DevScene& sc, const Frame& f, i
     if (alive_in) {
         state[2 * (size_t)p] = make_float4(T[0], T[1], T[2], __uint_as_float((alive ? 1u : 0u) | (nee_next ? 2u : 0u)));
         state[2 * (size_t)p + 1] = make_float4(L[0], L[1], L[2], __uint_as_float(newpos));
+    }
+    if (f.live) {   // every thread has read the flag before this barrier
+        const int any = __syncthreads_or(alive ? 1 : 0);
+        if (l == 0) f.live[blk] = any ? 1u : 0u;
     }
 }
 
