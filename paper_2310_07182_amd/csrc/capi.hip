@@ -868,14 +868,16 @@ pt_status pt_timer_free(pt_timer t) {
 
 // ---------------------------------------------------------------------------- batches
 
-static size_t job_slot_count(const pt_job* j, pt_group g) {
-    return make_frame(j->w, j->h, j->spp, j->bounces, (pt_mode)j->mode, g, 0).nslots;
+// a job's arena: two ray queues and the path state (32 B per slot each), then one flag
+// word per shade workgroup
+static size_t job_bytes_of(const Frame& f) {
+    return 3 * align256((size_t)f.nslots * 32) + align256((size_t)(f.nslots / (uint32_t)f.TS) * 4);
 }
 
 size_t pt_batch_job_bytes(const pt_job* job, pt_group group) {
     if (!job || job->w <= 0 || job->h <= 0 || job->spp <= 0 || job->bounces < 0 || job->bounces > 64) return 0;
     if (check_group(group, job->bounces) != PT_OK) return 0;
-    return 3 * align256(job_slot_count(job, group) * 32);
+    return job_bytes_of(make_frame(job->w, job->h, job->spp, job->bounces, (pt_mode)job->mode, group, 0));
 }
 
 static size_t batch_table_stride(int max_jobs) { return align256((size_t)max_jobs * sizeof(pt::StepJob)); }
@@ -1048,6 +1050,7 @@ static int batch_fill_table(pt_batch bt, const std::vector<int>& ids, std::vecto
         t.q_in = q[b & 1];
         t.q_out = q[(b + 1) & 1];
         t.state = (float4*)(base + 2 * qb);
+        t.f.live = (uint32_t*)(base + 3 * qb);
         t.hit_prim = J.job.hit_prim;
         t.hit_t = J.job.hit_t;
         const size_t plane = (size_t)J.f.w * J.f.h;
