@@ -431,6 +431,59 @@ def test_render_parity_traversal_kinds(api, orc, torch_dev, traversal, mode, nee
         assert np.array_equal(g["shadow_rays_per_bounce"].cpu().numpy(), o["shadow_rays"].astype(np.int64))
 
 
+_open_lit = {}
+
+
+def open_lit_scene(api, orc):
+    """The open-front room of `tiny`, seen from further out, with an emissive ceiling panel
+    and two of its spheres made glossy and mirror-like: the frame's border sees the
+    environment, so whole 8x8 super tiles end at their first hit, while the rest keeps going
+    with every material kind and with next-event estimation towards the panel."""
+    if not _open_lit:
+        s = scenes.tiny()
+        panel = np.asarray(scenes.quad((3, 9.9, 3), (3, 9.9, 7), (7, 9.9, 7), (7, 9.9, 3)), np.float32)
+        mats = np.concatenate([s["mats"], np.array([scenes._mat(scenes.LAMBERT, (0, 0, 0), 0.0, (12, 12, 12)),
+                                                    scenes._mat(scenes.GGX, (0.8, 0.7, 0.6), 0.15),
+                                                    scenes._mat(scenes.MIRROR, (0.9, 0.9, 0.9))],
+                                                   dtype=scenes.MATERIAL_DTYPE)])
+        nm = len(s["mats"])
+        tri_mat = s["tri_mat"].copy()
+        tri_mat[tri_mat == 5] = nm + 1          # one sphere glossy
+        tri_mat[tri_mat == 6] = nm + 2          # one mirror-like
+        lit = scenes.Scene(name="open_lit", tris=np.ascontiguousarray(np.concatenate([s["tris"], panel])),
+                           tri_mat=np.ascontiguousarray(np.concatenate([tri_mat, np.full(2, nm, np.uint32)])),
+                           mats=mats, env=s["env"],
+                           camera=dict(pos=(5.0, 6.0, 34.0), look_at=(5.0, 5.0, 0.0), up=(0.0, 1.0, 0.0), vfov=50.0))
+        _open_lit["s"] = (lit, api.Scene(lit), orc.OracleScene(lit))
+    return _open_lit["s"]
+
+
+@pytest.mark.parametrize("traversal", ["pair", "wide", "queue", "quant"])
+@pytest.mark.parametrize("mode,nee", [("reuse", True), ("incoherent", True), ("sorted", False), ("reuse", False)])
+def test_ended_super_tiles_parity(api, orc, torch_dev, traversal, mode, nee):
+    """Super tiles whose paths have all ended skip their shading and write only what every
+    slot gets (no next ray, no shadow ray, an empty rule record): hits, rays, radiance, rule
+    records and shadow-ray counts against the oracle, with every traversal kernel (plain
+    and compacted queues)."""
+    s, sc, osc = open_lit_scene(api, orc)
+    w, h, spp, B = 96, 80, 2, 3
+    _say(f"[gpu] ended super tiles traversal={traversal} mode={mode} nee={nee}")
+    g = api.render(sc, w, h, spp, B, mode, (8, 8), 8, None, 13, nee=nee, traversal=traversal, rays=True,
+                   debug=True)
+    torch_dev.cuda.synchronize()
+    o = osc.render(w, h, spp, B, mode=mode, tile=(8, 8), k=8, seed=13, nee=nee, rays=True, debug=True)
+    compare_render(g, o, (8, 8), mode)
+    gf = np.ascontiguousarray(g["debug"].cpu().numpy()[..., 3]).view(np.uint32)
+    assert np.array_equal(gf, o["dbg_flags"].view(np.uint32))
+    if nee:
+        assert np.array_equal(g["shadow_rays_per_bounce"].cpu().numpy(), o["shadow_rays"].astype(np.int64))
+        assert o["shadow_rays"][:B].sum() > 0
+    # whole tiles ended at the first hit, and others still tracing at the last bounce
+    ended = (o["hit_prim"][1, 0] == -2).reshape(h // 8, 8, w // 8, 8).all(axis=(1, 3))
+    assert ended.any() and not ended.all()
+    assert o["rays_per_bounce"][B] > 0
+
+
 def test_traversal_kind_out_of_range_is_einval(api, orc, torch_dev):
     from paper_2310_07182_amd import capi
     s, sc, osc = both(api, orc, "tiny")
