@@ -213,6 +213,25 @@ def test_group_leaf_gate_checked(L):
     assert L.pt_batch_job_bytes(C.byref(j), g) > 0
 
 
+def test_batch_job_bytes_hold_queues_state_and_tile_flags(L):
+    """A job's arena: two ray queues and the path state, 32 B per slot each (256-byte
+    aligned), then one flag word per shade workgroup (one super tile of >= 64 slots)."""
+    def al(x):
+        return (x + 255) // 256 * 256
+    j = capi.Job()
+    for (w, h, tile, k) in ((1920, 1080, (8, 8), 8), (101, 67, (4, 4), 2), (70, 66, (32, 32), 128)):
+        j.w, j.h, j.spp, j.bounces, j.mode = w, h, 1, 4, capi.MODES["reuse"]
+        tw, th = tile
+        if tw * th >= 64:
+            sw, sh = tw, th
+        else:
+            cols = max(1, min(8 // tw, 64 // (tw * th)))
+            sw, sh = cols * tw, (64 // (tw * th) // cols) * th
+        nst = -(-w // sw) * -(-h // sh)
+        nslots = nst * sw * sh
+        assert L.pt_batch_job_bytes(C.byref(j), _group(tw, th, k)) == 3 * al(nslots * 32) + al(nst * 4)
+
+
 def test_probe_rejects_before_touching_device(L):
     g, ns = C.c_float(), C.c_float()
     assert L.pt_probe_memory(None, 1 << 20, 1, 1, C.byref(g), C.byref(ns), None) == capi.PT_EINVAL
